@@ -1,0 +1,154 @@
+/*
+ * CPU ORACLE for the Shouji pre-alignment filter -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, character-level implementation used to check the GPU path.
+ * Only tests, the smoke check and the bench's CPU-baseline leg may load it;
+ * the product path never calls it.  It shares no code with the GPU library:
+ * it reads base codes (one uint8 per base), never the packed device layout.
+ *
+ * Source: Alser et al., "Shouji: a fast and efficient pre-alignment filter
+ * for sequence alignment", Sec. 2.2 (three steps), Eq. 1 (neighbourhood map),
+ * Supplementary Sec. 6.2 Algorithm 1 and Algorithm 2 (CZ, count zeros).
+ *
+ * Readings adopted where the paper is ambiguous (each is listed with its
+ * evidence in the design notes):
+ *  - Pattern P = read, text T = reference; map entry N[i][j] compares P[i]
+ *    with T[j] (Eq. 1).  A diagonal d is viewed along the text column j:
+ *    cell (d, j) compares P[j-d] with T[j]; d > 0 are the upper diagonals
+ *    (pattern shifted right, Sec. 2.3), d < 0 the lower ones, d = 0 main.
+ *  - Cells outside the m x m map (j-d or j outside [0, m)) count as
+ *    mismatches (1), which also makes the last three windows of the m
+ *    windows (Sec. 2.2.2: one window per column, width 4, step 1) see ones
+ *    beyond column m-1.
+ *  - Window search: every one of the 2E+1 diagonal segments is examined
+ *    (Sec. 2.2.2); the winner has the most zeros, ties going to a segment
+ *    that starts with a zero; remaining ties go to the earliest segment in
+ *    Algorithm 1's evaluation order L1, U1, L2, U2, ..., LE, UE, M
+ *    ("reading B").  Reading A (off-diagonals first, then the main diagonal
+ *    replaces the winner only with strictly more zeros, as Algorithm 1's
+ *    final comparison is written) is kept behind a flag for sensitivity
+ *    studies only.
+ *  - Shouji bit-vector update: copy the winner into S[i..i+3] only when it
+ *    has strictly more zeros than S[i..i+3] (Algorithm 1's update test).
+ *  - Decision: accept (1) iff the number of ones in S[0..m) is <= E
+ *    (Sec. 2.2.3; Algorithm 1's test CZ(S) >= m - E).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+/* Neighbourhood map entry (Eq. 1) on diagonal d at text column j. */
+static int map_cell(const uint8_t *P, const uint8_t *T, int m, int d, int j) {
+    int q = j - d;                         /* pattern index on this diagonal */
+    if (j < 0 || j >= m || q < 0 || q >= m) return 1;
+    return P[q] == T[j] ? 0 : 1;
+}
+
+/* One diagonal row of the map (Eq. 1): out[j] = cell (d, j) for j in [0, m). */
+int oracle_shouji_map_row(const uint8_t *P, const uint8_t *T, int32_t m, int32_t d, uint8_t *out) {
+    if (m < 0) return -1;
+    for (int j = 0; j < m; j++) out[j] = (uint8_t)map_cell(P, T, m, d, j);
+    return 0;
+}
+
+/* CZ (Algorithm 2): zeros in a bit-vector of length len. */
+static int count_zeros(const uint8_t *v, int len) {
+    int c = 0;
+    for (int t = 0; t < len; t++) if (v[t] == 0) c++;
+    return c;
+}
+
+/*
+ * Filter one pair.  P, T: base codes, length m (>= 0).  reading: 0 = B (the
+ * adopted reading), 1 = A (sensitivity study only).  If S_out is not NULL it
+ * receives the final Shouji bit-vector S[0..m).  Returns the number of ones.
+ */
+int oracle_shouji_pair(const uint8_t *P, const uint8_t *T, int32_t m, int32_t E,
+                       int32_t reading, uint8_t *S_out) {
+    if (m < 0 || E < 0) return -1;
+    /* Step 1 (Sec. 2.2.1): the 2E+1 diagonals, stored as rows over text
+     * columns 0..m+2 so that every window i in [0, m) reads 4 cells. */
+    int nd = 2 * E + 1, w = m + 3;
+    uint8_t *N = (uint8_t *)malloc((size_t)nd * (size_t)w + 1);
+    uint8_t *S = (uint8_t *)malloc((size_t)w + 1);
+    for (int d = -E; d <= E; d++)
+        for (int j = 0; j < w; j++)
+            N[(size_t)(d + E) * w + j] = (uint8_t)map_cell(P, T, m, d, j);
+    /* Step 2 (Sec. 2.2.2): Shouji bit-vector starts as all ones. */
+    for (int j = 0; j < w; j++) S[j] = 1;
+    for (int i = 0; i < m; i++) {
+        const uint8_t *Z = NULL;
+        int best_key = -1;
+        /* off-diagonal candidates in evaluation order L1, U1, ..., LE, UE */
+        for (int k = 1; k <= E; k++) {
+            for (int s = 0; s < 2; s++) {
+                int d = s == 0 ? -k : k;
+                const uint8_t *seg = N + (size_t)(d + E) * w + i;
+                int key = 2 * count_zeros(seg, 4) + (seg[0] == 0 ? 1 : 0);
+                if (key > best_key) { best_key = key; Z = seg; }
+            }
+        }
+        const uint8_t *M = N + (size_t)E * w + i;     /* main diagonal */
+        if (reading == 0) {
+            int key = 2 * count_zeros(M, 4) + (M[0] == 0 ? 1 : 0);
+            if (key > best_key) { best_key = key; Z = M; }
+        } else {
+            if (Z == NULL || count_zeros(M, 4) > count_zeros(Z, 4)) Z = M;
+        }
+        /* update S[i..i+3] only with strictly more zeros */
+        if (count_zeros(Z, 4) > count_zeros(S + i, 4))
+            for (int t = 0; t < 4; t++) S[i + t] = Z[t];
+    }
+    /* Step 3 (Sec. 2.2.3): count the ones over the m positions. */
+    int ones = 0;
+    for (int j = 0; j < m; j++) ones += S[j];
+    if (S_out) memcpy(S_out, S, (size_t)m);
+    free(N); free(S);
+    return ones;
+}
+
+/*
+ * Filter n pairs.  Row p of P and T starts at p * stride (codes).  lengths[p]
+ * is the pair's length; a length outside [0, stride] marks an invalid pair:
+ * out_accept = 0xFF, out_popcount = -1.  Threshold E, or E_per_pair[p] when
+ * E_per_pair is not NULL (a negative entry also marks the pair invalid).
+ * out_popcount may be NULL.  nthreads <= 0 uses the OpenMP default.
+ */
+int oracle_shouji_batch(const uint8_t *P, const uint8_t *T, int64_t stride,
+                        const int32_t *lengths, int64_t n, int32_t E,
+                        const int32_t *E_per_pair, int32_t reading, int32_t nthreads,
+                        uint8_t *out_accept, int16_t *out_popcount) {
+    if (n < 0 || stride < 0 || (E < 0 && !E_per_pair)) return -1;
+    if (nthreads > 0) {
+        #pragma omp parallel for schedule(static) num_threads(nthreads)
+        for (int64_t p = 0; p < n; p++) {
+            int32_t m = lengths[p], e = E_per_pair ? E_per_pair[p] : E;
+            if (m < 0 || m > stride || e < 0) { out_accept[p] = 0xFF; if (out_popcount) out_popcount[p] = -1; continue; }
+            int ones = oracle_shouji_pair(P + p * stride, T + p * stride, m, e, reading, NULL);
+            out_accept[p] = (uint8_t)(ones <= e ? 1 : 0);
+            if (out_popcount) out_popcount[p] = (int16_t)ones;
+        }
+    } else {
+        #pragma omp parallel for schedule(static)
+        for (int64_t p = 0; p < n; p++) {
+            int32_t m = lengths[p], e = E_per_pair ? E_per_pair[p] : E;
+            if (m < 0 || m > stride || e < 0) { out_accept[p] = 0xFF; if (out_popcount) out_popcount[p] = -1; continue; }
+            int ones = oracle_shouji_pair(P + p * stride, T + p * stride, m, e, reading, NULL);
+            out_accept[p] = (uint8_t)(ones <= e ? 1 : 0);
+            if (out_popcount) out_popcount[p] = (int16_t)ones;
+        }
+    }
+    return 0;
+}
+
+/* Number of threads an OpenMP parallel region uses by default here. */
+int oracle_default_threads(void) {
+    int t = 1;
+    #pragma omp parallel
+    {
+        #pragma omp single
+        t = omp_get_num_threads();
+    }
+    return t;
+}
