@@ -1,0 +1,96 @@
+/*
+ * shouji.h -- C ABI of the MI355X Shouji pre-alignment filter.
+ *
+ * The filter (Alser et al., Shouji, Sec. 2.2; Supplementary Algorithm 1)
+ * decides for each read / reference-segment pair whether it may lie within
+ * E edits: it builds the 2E+1 diagonals of the neighbourhood map (Eq. 1),
+ * slides a 4-column window over them, copies into the Shouji bit-vector the
+ * diagonal segment with the most matches, and accepts the pair when that
+ * vector keeps at most E ones (Sec. 2.2.3).  Accepted pairs go on to full
+ * alignment; rejected pairs need none.
+ *
+ * Conventions shared by every entry point:
+ *  - Every array pointer is a DEVICE pointer on the current HIP device.  The
+ *    caller owns all buffers; the library keeps no pointer after returning.
+ *  - Sequences are 2-bit packed, 16 bases per 32-bit word, base j of a
+ *    sequence in bits [2*(j%16), 2*(j%16)+1] of word j/16.  Any fixed code
+ *    assignment works (only equality of codes is tested); the reference
+ *    generator uses A=0, C=1, G=2, T=3.  Words are stored word-major:
+ *    word w of pair p is at seq[w * ld + p], ld >= n_pairs (so one load
+ *    instruction of a wavefront reads one word of 64 consecutive pairs).
+ *    Words needed per pair: ceil(max_len / 16).  Bits beyond a pair's
+ *    length are ignored.
+ *  - The read is the pattern P and the reference segment the text T of
+ *    Eq. 1; read and reference of a pair have the same length (global
+ *    filtering, Sec. 2.3).
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = default stream)
+ *    and results are valid after the stream is synchronised.  Argument
+ *    errors are detected on the host before anything is enqueued.
+ *  - Functions return SHOUJI_OK or a negative shouji_status and never throw.
+ *    shouji_last_error() returns a thread-local description of the last
+ *    failure.
+ *  - Per-pair problems (a length outside [0, max_len]) do not fail the call:
+ *    that pair gets out_accept = 0xFF and out_popcount = -1.
+ *  - Thread-safe and re-entrant; calls on different streams may overlap.
+ */
+#ifndef SHOUJI_H
+#define SHOUJI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SHOUJI_BASES_PER_WORD 16
+#define SHOUJI_MAX_LEN 1024 /* longest supported sequence (bases)            */
+#define SHOUJI_MAX_E 31     /* largest edit threshold after clamping to m-1  */
+
+typedef enum {
+    SHOUJI_OK = 0,
+    SHOUJI_ERR_NULL = -1,   /* a required pointer is NULL                    */
+    SHOUJI_ERR_ARG = -2,    /* a size or stride is invalid                   */
+    SHOUJI_ERR_RANGE = -3,  /* E or max_len beyond the supported maximum     */
+    SHOUJI_ERR_DEVICE = -4, /* the HIP runtime reported an error             */
+    SHOUJI_ERR_NOMEM = -5   /* a device allocation failed                    */
+} shouji_status;
+
+/*
+ * shouji_filter -- the plain form: one edit threshold for every pair.
+ *
+ * Sec. 2.2 (Steps 1-3), Eq. 1, Supplementary Algorithm 1.  Per pair p:
+ *   Step 1: diagonal d in [-E, E] at text column j is 0 iff
+ *           0 <= j, j-d < m and read[j-d] == ref[j], else 1;
+ *   Step 2: S = all ones; for each window i in [0, m) the segment of
+ *           columns i..i+3 with the most zeros wins (ties: a leading zero,
+ *           then the order lower 1, upper 1, ..., lower E, upper E, main);
+ *           it is copied into S[i..i+3] if it has strictly more zeros;
+ *   Step 3: popcount = ones of S over [0, m); accept = popcount <= E.
+ *
+ *   reads, refs   word-major packed sequences (see above), ld words apart.
+ *   lengths       n_pairs lengths m_p, or NULL: every pair has max_len bases.
+ *   E             edit threshold, >= 0.  Internally clamped to max_len - 1
+ *                 (diagonals beyond the map are all ones); after clamping it
+ *                 must be <= SHOUJI_MAX_E, else SHOUJI_ERR_RANGE.
+ *   out_accept    n_pairs bytes: 1 accept, 0 reject, 0xFF invalid pair.
+ *   out_popcount  n_pairs int16 ones counts (-1 for an invalid pair), or NULL.
+ *   n_pairs       >= 0; 0 is a successful no-op.
+ *   max_len       0..SHOUJI_MAX_LEN, the longest length in the batch.
+ *   ld            leading dimension in words, >= n_pairs.
+ *   stream        hipStream_t or NULL.
+ */
+int shouji_filter(const uint32_t *reads, const uint32_t *refs, const int32_t *lengths,
+                  int32_t E, uint8_t *out_accept, int16_t *out_popcount,
+                  int64_t n_pairs, int32_t max_len, int64_t ld, void *stream);
+
+/* Text of the last non-OK status returned on this thread ("" if none). */
+const char *shouji_last_error(void);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int shouji_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHOUJI_H */

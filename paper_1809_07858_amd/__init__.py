@@ -1,0 +1,116 @@
+"""MI355X Shouji pre-alignment filter: thin Python binding over libshouji.so.
+
+Every step of the filter runs in the HIP kernels behind the C ABI declared in
+include/shouji.h; this module only marshals arguments (device pointers of
+torch tensors, the current HIP stream).  It fails loudly when the library is
+not built -- there is no CPU fallback.
+
+Device layout (see include/shouji.h): sequences 2-bit packed, 16 bases per
+32-bit word, word-major (word w of pair p at [w, p] of an [nwords, ld] array).
+`pack_words` builds that layout on the host from base codes.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libshouji.so")
+BASES_PER_WORD = 16
+MAX_LEN = 1024
+MAX_E = 31
+_lib = None
+
+
+class ShoujiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("shouji error %d: %s" % (code, msg))
+        self.code = code
+
+
+def lib():
+    """Load libshouji.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libshouji.so is not built: run __graft_entry__.build() "
+                              "or python -m paper_1809_07858_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.shouji_filter.restype = ctypes.c_int
+        L.shouji_filter.argtypes = [vp, vp, vp, i32, vp, vp, i64, i32, i64, vp]
+        L.shouji_last_error.restype = ctypes.c_char_p
+        L.shouji_version.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise ShoujiError(rc, lib().shouji_last_error().decode())
+
+
+def nwords(max_len):
+    return (int(max_len) + BASES_PER_WORD - 1) // BASES_PER_WORD
+
+
+def pack_words(codes, max_len=None, ld=None):
+    """Base codes [n, stride] (uint8 0..3) -> packed words [nwords, ld] (int32 bit patterns)."""
+    codes = np.ascontiguousarray(codes, dtype=np.uint8)
+    n, stride = codes.shape
+    max_len = stride if max_len is None else int(max_len)
+    nw = nwords(max_len)
+    ld = n if ld is None else int(ld)
+    buf = np.zeros((n, nw * BASES_PER_WORD), dtype=np.uint32)
+    w = min(stride, nw * BASES_PER_WORD)
+    buf[:, :w] = codes[:, :w] & 3
+    shifts = (2 * np.arange(BASES_PER_WORD, dtype=np.uint32))
+    words = (buf.reshape(n, nw, BASES_PER_WORD) << shifts).sum(axis=2, dtype=np.uint64).astype(np.uint32)
+    out = np.zeros((nw, ld), dtype=np.uint32)
+    out[:, :n] = words.T
+    return out.view(np.int32)
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def shouji_filter(reads, refs, lengths, E, out_accept=None, out_popcount=None, n_pairs=None,
+                  max_len=None, ld=None, stream=None, want_popcount=True):
+    """Run the plain filter on device tensors.
+
+    reads, refs : int32 CUDA tensors [nwords, ld] in the packed word-major layout
+    lengths     : int32 CUDA tensor [n] or None (every pair has max_len bases)
+    Returns (accept uint8 [n], popcount int16 [n] or None).
+    """
+    import torch
+    if reads.dim() != 2 or refs.shape != reads.shape:
+        raise ValueError("reads/refs must be [nwords, ld] tensors of the same shape")
+    for t in (reads, refs):
+        if not t.is_cuda or t.dtype != torch.int32 or not t.is_contiguous():
+            raise ValueError("reads/refs must be contiguous int32 CUDA tensors")
+    ld = reads.shape[1] if ld is None else int(ld)
+    if n_pairs is None:
+        n_pairs = lengths.shape[0] if lengths is not None else ld
+    if max_len is None:
+        max_len = reads.shape[0] * BASES_PER_WORD
+    if reads.shape[0] < nwords(max_len):
+        raise ValueError("reads hold fewer words than max_len needs")
+    if lengths is not None and (not lengths.is_cuda or lengths.dtype != torch.int32
+                                or lengths.numel() < n_pairs):
+        raise ValueError("lengths must be an int32 CUDA tensor with n_pairs entries")
+    dev = reads.device
+    if out_accept is None:
+        out_accept = torch.empty(n_pairs, dtype=torch.uint8, device=dev)
+    if out_popcount is None and want_popcount:
+        out_popcount = torch.empty(n_pairs, dtype=torch.int16, device=dev)
+    rc = lib().shouji_filter(ctypes.c_void_p(reads.data_ptr()), ctypes.c_void_p(refs.data_ptr()),
+                             None if lengths is None else ctypes.c_void_p(lengths.data_ptr()),
+                             int(E), ctypes.c_void_p(out_accept.data_ptr()),
+                             None if out_popcount is None else ctypes.c_void_p(out_popcount.data_ptr()),
+                             int(n_pairs), int(max_len), ld, _stream_handle(stream))
+    _check(rc)
+    return out_accept, out_popcount

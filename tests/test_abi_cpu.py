@@ -1,0 +1,70 @@
+"""Host-side checks of the C ABI library (no GPU needed: no kernel is launched)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1809_07858_amd as sj
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if fn.endswith(".h"):
+            text = open(os.path.join(inc, fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names.update(re.findall(r"\b(shouji_\w+)\s*\(", text))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = sj.lib()
+    names = _declared_symbols()
+    assert "shouji_filter" in names
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_version_and_empty_error():
+    assert sj.lib().shouji_version() >= 10000
+
+
+def _call(**kw):
+    a = dict(reads=ctypes.c_void_p(16), refs=ctypes.c_void_p(16), lengths=None, E=2,
+             out_accept=ctypes.c_void_p(16), out_popcount=None, n_pairs=10, max_len=100,
+             ld=10, stream=None)
+    a.update(kw)
+    return sj.lib().shouji_filter(a["reads"], a["refs"], a["lengths"], a["E"], a["out_accept"],
+                                  a["out_popcount"], a["n_pairs"], a["max_len"], a["ld"], a["stream"])
+
+
+def test_argument_errors_are_reported_before_launch():
+    assert _call(n_pairs=-1) == -2
+    assert _call(E=-1) == -2
+    assert _call(max_len=2000) == -3
+    assert _call(max_len=-1) == -3
+    assert _call(E=40, max_len=100) == -3          # clamped E still above 31
+    assert _call(reads=None) == -1
+    assert _call(out_accept=None) == -1
+    assert _call(ld=5) == -2
+    assert b"ld" in sj.lib().shouji_last_error()
+    # zero pairs is a successful no-op, even with NULL pointers
+    assert _call(n_pairs=0, reads=None, refs=None, out_accept=None) == 0
+    assert sj.lib().shouji_last_error() == b""
+
+
+def test_pack_words_layout():
+    rng = np.random.default_rng(0)
+    codes = rng.integers(0, 4, (37, 50)).astype(np.uint8)
+    w = sj.pack_words(codes, 50, ld=40).view(np.uint32)
+    assert w.shape == (4, 40)
+    for p in range(37):
+        for j in range(50):
+            assert (int(w[j // 16, p]) >> (2 * (j % 16))) & 3 == codes[p, j]
+    assert (w[:, 37:] == 0).all()
+    assert (w[3, :37] >> 4 == 0).all()   # bases 50..63 of the last word are zero

@@ -1,0 +1,130 @@
+"""GPU parity: the HIP filter against the CPU oracle, bit-exact on every
+accept bit and popcount, through the C ABI.
+
+Sizes: small enough for the oracle to finish in seconds, spanning several
+wavefront tiles (2048 pairs each) with a ragged tail; plus the full 2M-pair
+headline workload (m=100, E=5) in the launch configuration the bench uses.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+import syninput
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sj():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1809_07858_amd as m
+    m.lib()
+    return m
+
+
+def _run(sj, p, E, max_len, ld=None, with_lengths=True, pop=True):
+    dev = torch.device("cuda:0")
+    reads = torch.from_numpy(sj.pack_words(p.P, max_len, ld=ld)).to(dev)
+    refs = torch.from_numpy(sj.pack_words(p.T, max_len, ld=ld)).to(dev)
+    lens = torch.from_numpy(np.ascontiguousarray(p.lengths, dtype=np.int32)).to(dev) if with_lengths else None
+    acc, pc = sj.shouji_filter(reads, refs, lens, E, n_pairs=p.n, max_len=max_len, want_popcount=pop)
+    torch.cuda.synchronize()
+    return acc.cpu().numpy(), (pc.cpu().numpy() if pc is not None else None)
+
+
+def _check(sj, p, E, max_len, **kw):
+    print("case n=%d max_len=%d E=%d %s" % (p.n, max_len, E, kw), flush=True)
+    ga, gp = _run(sj, p, E, max_len, **kw)
+    ea, ep = oracle.shouji_batch(p.P, p.T, p.lengths, E=E)
+    bad = np.nonzero((ga != ea) | (gp != ep))[0]
+    assert bad.size == 0, "mismatches at %s (gpu %s/%s oracle %s/%s)" % (
+        bad[:8], ga[bad[:8]], gp[bad[:8]], ea[bad[:8]], ep[bad[:8]])
+    return ga, gp
+
+
+def test_config0_full(sj):
+    p = syninput.config0()
+    _check(sj, p, 2, 100)
+
+
+@pytest.mark.parametrize("E", list(range(0, 11)))
+def test_config1_slices(sj, E):
+    p = syninput.config1(E, n=20_000 + 77)
+    _check(sj, p, E, 100)
+
+
+@pytest.mark.parametrize("E", [0, 5, 10, 15, 20, 25])
+def test_config2_slices(sj, E):
+    p = syninput.config2(E, n=6_000 + 13)
+    _check(sj, p, E, 250)
+
+
+@pytest.mark.parametrize("E", [0, 1, 3, 8, 17, 30, 31])
+def test_mixed_lengths(sj, E):
+    p = syninput.generate(9_000, 64, 300, E=E, seed=77 + E)
+    _check(sj, p, E, 300)
+
+
+def test_mixed_short_lengths_and_low_complexity(sj):
+    # lengths 0..40 (m < 4 included), two-letter alphabet: many ties
+    p = syninput.generate(5_000, 0, 40, E=3, seed=5)
+    p.P[:] &= 1
+    p.T[:] &= 1
+    for E in (0, 1, 2, 3, 6, 31):
+        _check(sj, p, E, 40)
+    with pytest.raises(sj.ShoujiError):
+        _run(sj, p, 32, 40)        # clamped E (min(E, max_len-1)) above the maximum
+
+
+def test_tiny_and_ragged_batches(sj):
+    for n in (1, 2, 63, 64, 65, 2047, 2048, 2049):
+        p = syninput.generate(n, 100, E=3, seed=n)
+        _check(sj, p, 3, 100)
+
+
+def test_no_lengths_and_padded_ld(sj):
+    p = syninput.generate(3_000, 100, E=4, seed=9)
+    ga, gp = _run(sj, p, 4, 100, ld=3_333, with_lengths=False)
+    ea, ep = oracle.shouji_batch(p.P, p.T, p.lengths, E=4)
+    assert np.array_equal(ga, ea) and np.array_equal(gp, ep)
+
+
+def test_E_clamped_and_large(sj):
+    p = syninput.generate(2_100, 20, E=3, seed=4)
+    _check(sj, p, 19, 20)
+    _check(sj, p, 500, 20)     # clamped to m-1 internally, decision uses E=500
+
+
+def test_max_len_1024(sj):
+    p = syninput.generate(2_500, 1000, 1024, E=10, seed=8)
+    _check(sj, p, 10, 1024)
+
+
+def test_invalid_lengths_get_sentinels(sj):
+    p = syninput.generate(3_000, 100, E=2, seed=3)
+    p.lengths[::7] = 101
+    p.lengths[3::11] = -5
+    _check(sj, p, 2, 100)
+
+
+def test_identical_pairs(sj):
+    p = syninput.generate(4_096, 150, E=6, seed=2)
+    p.T[:] = p.P
+    ga, gp = _run(sj, p, 6, 150)
+    assert (gp == 0).all() and (ga == 1).all()
+
+
+def test_deterministic(sj):
+    p = syninput.config1(7, n=10_000)
+    a1, p1 = _run(sj, p, 7, 100)
+    a2, p2 = _run(sj, p, 7, 100)
+    assert np.array_equal(a1, a2) and np.array_equal(p1, p2)
+
+
+def test_headline_full_size(sj):
+    # m=100, E=5, 2M pairs: the bench's workload and launch, every output compared
+    p = syninput.config1(5)
+    _check(sj, p, 5, 100)
