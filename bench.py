@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Throughput bench of the Shouji pre-alignment filter on one MI355X.
+
+Default workload: the plain filter over 2,000,000 synthetic read/reference
+pairs of length m=100 at edit threshold E=5 (reads i.i.d. uniform bases, 20%
+unrelated references, the rest the read with k~U{0..2E} random edits; seed
+1005).  One step = one filter call over the whole batch (every step of the
+method: unpack, neighbourhood diagonals, window search, bit-vector update,
+decision), inputs already resident in HBM in the library's packed layout.
+
+Prints one JSON line.  Extra legs:
+  * cpu_baseline: the CPU oracle (test infrastructure) timed on the host's
+    cores over a bounded sample of the same pairs; its outputs also give the
+    parity mismatch count of the GPU result on that sample;
+  * roofline: algorithmic integer lane-ops of the kernel per launch over the
+    average launch time (HIP events on the launch stream), against the
+    chip's 32-bit VALU lane-op peak; HBM traffic per launch from rocprofv3
+    counters when a summary for the current kernel source is committed.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "filtered pairs/sec at m=100,E=5 (1 GPU) vs plain; serving p50/p99 latency"
+# MI355X: 256 CUs x 64 lanes x 2.4 GHz peak engine clock, one 32-bit VALU op
+# per lane per cycle.
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1809_07858_amd/csrc/shouji_plain.hip",
+                  "paper_1809_07858_amd/csrc/shouji_internal.h"]
+
+
+def algorithmic_lane_ops_per_pair(m, E):
+    """Gate count of the bit-sliced filter circuit per pair (one 32-bit lane
+    op evaluates a gate for 32 pairs).
+
+    Per window and candidate diagonal: 2 ops to build a cell (Eq. 1: XOR of
+    code planes, OR of the two bits), 6 to count the segment's ones (2-bit
+    pair sums shared by two windows + one 2-bit add); per window and each of
+    the 2E candidates after the first: 4 ops to compare keys and 7 to keep the
+    winner; per window: 9 ops for the bit-vector update and 3.25 for the
+    carry-save count of its final bit.  Unpack: two sequences of ceil(m/16)
+    16-base words, each a 32x32 bit transpose of 256 ops per 32 pairs.
+    """
+    per32 = m * (2 * E + 1) * 8 + m * (2 * E) * 11 + m * 12.25
+    unpack = 2 * ((m + 15) // 16) * 256
+    return (per32 + unpack) / 32.0
+
+
+def algorithmic_bytes_per_pair(m):
+    """HBM bytes the method must move per pair: two 2-bit packed sequences,
+    the length, the accept byte and the int16 popcount."""
+    return 2 * m / 4.0 + 4 + 1 + 2
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(workload_tag):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "shouji_plain_%s_hbm_traffic.md" % workload_tag)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=2_000_000)
+    ap.add_argument("--m", type=int, default=100)
+    ap.add_argument("--E", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain 1 GiB device copy (counter calibration) and exit")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs on a single MI355X "
+              "(pairs are independent; see the design notes for how batches would "
+              "shard across GPUs).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1809_07858_amd as sj
+    import syninput
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.int32, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_launch": src.numel() * 4,
+                          "copy_bytes_written_per_launch": dst.numel() * 4, "launches": 3}))
+        return
+
+    n, m, E = args.n, args.m, args.E
+    t0 = time.time()
+    pairs = syninput.generate(n, m, E=E, seed=1000 + E)
+    reads = torch.from_numpy(sj.pack_words(pairs.P, m)).to(dev)
+    refs = torch.from_numpy(sj.pack_words(pairs.T, m)).to(dev)
+    lens = torch.from_numpy(pairs.lengths).to(dev)
+    acc = torch.empty(n, dtype=torch.uint8, device=dev)
+    pc = torch.empty(n, dtype=torch.int16, device=dev)
+    torch.cuda.synchronize()
+    setup_s = time.time() - t0
+
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        sj.shouji_filter(reads, refs, lens, E, acc, pc, n_pairs=n, max_len=m, stream=stream)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t_start = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        sj.shouji_filter(reads, refs, lens, E, acc, pc, n_pairs=n, max_len=m, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    value = n / (ms_per_step / 1e3)
+
+    ops_pair = algorithmic_lane_ops_per_pair(m, E)
+    achieved_tops = ops_pair * n / (ms_per_step / 1e3) / 1e12
+    workload_tag = "m%d_E%d_n%d" % (m, E, n)
+    traffic = committed_traffic(workload_tag)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "plain filter, %d pairs, m=%d, E=%d, reads uniform ACGT, "
+                               "20%% unrelated, k~U{0..2E} edits, seed %d" % (n, m, E, 1000 + E),
+                   "pairs_per_step": n, "m": m, "E": E, "form": "plain",
+                   "layout": "2-bit packed, 16 bases per uint32 word, word-major"},
+        "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": VALU_PEAK_TOPS,
+                     "unit": "Tlane-op/s (32-bit integer VALU)",
+                     "frac": achieved_tops / VALU_PEAK_TOPS,
+                     "traffic": traffic,
+                     "algorithmic_lane_ops_per_pair": ops_pair,
+                     "hbm_algorithmic_GBs": algorithmic_bytes_per_pair(m) * value / 1e9,
+                     "hbm_frac": algorithmic_bytes_per_pair(m) * value / 1e9 / HBM_PEAK_GBS,
+                     "kernel_source_sha256": kernel_source_hash()},
+        "wall_s_timed": wall,
+        "setup_s": setup_s,
+        "accept_rate": float(acc.float().mean().item()),
+    }
+
+    if not args.no_cpu:
+        import oracle
+        threads = oracle.default_threads()
+        # calibrate, then size the sample to about cpu_seconds of oracle work
+        cal = min(n, 20_000)
+        tc = time.perf_counter()
+        oracle.shouji_batch(pairs.P[:cal], pairs.T[:cal], pairs.lengths[:cal], E=E)
+        rate = cal / max(time.perf_counter() - tc, 1e-6)
+        ns = int(min(n, max(cal, rate * args.cpu_seconds)))
+        tc = time.perf_counter()
+        ea, ep = oracle.shouji_batch(pairs.P[:ns], pairs.T[:ns], pairs.lengths[:ns], E=E)
+        cpu_s = time.perf_counter() - tc
+        ga = acc[:ns].cpu().numpy()
+        gp = pc[:ns].cpu().numpy()
+        out["cpu_baseline"] = {"value": ns / cpu_s, "unit": "pairs/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": "first %d pairs of the same batch (%.1f s on %d threads)"
+                                         % (ns, cpu_s, threads)}
+        out["parity_mismatches"] = int(((ga != ea) | (gp != ep)).sum())
+        out["parity_sample"] = ns
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

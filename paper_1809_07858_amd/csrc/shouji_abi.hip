@@ -57,11 +57,26 @@ extern "C" int shouji_filter(const uint32_t *reads, const uint32_t *refs, const 
     prm.out_accept = out_accept;
     prm.out_popcount = out_popcount;
     prm.n = n_pairs;
-    const int64_t grid = (n_pairs + shouji::kPairsPerWave - 1) / shouji::kPairsPerWave;
+    // Workgroups of 4 wavefronts (1024 pairs each); LDS and registers let a CU
+    // hold two of them, i.e. two wavefronts per SIMD.
+    const size_t wave_lds = shouji::plain_lds_wave_bytes(Ee);
+    const size_t lds = wave_lds * shouji::kWavesPerGroup;
+    if (lds > shouji::kLdsPerCU) return fail(SHOUJI_ERR_RANGE, "E %d needs more LDS than one CU holds", E);
+    const int64_t waves = (n_pairs + shouji::kPairsPerWave - 1) / shouji::kPairsPerWave;
+    const int64_t grid = (waves + shouji::kWavesPerGroup - 1) / shouji::kWavesPerGroup;
     if (grid > 0x7fffffff) return fail(SHOUJI_ERR_ARG, "n_pairs too large");
-    const size_t lds = shouji::plain_lds_bytes(Ee);
-    hipLaunchKernelGGL(shouji::shouji_plain_kernel, dim3((unsigned)grid), dim3(shouji::kWave), lds,
-                       (hipStream_t)stream, prm);
+    prm.lds_wave_bytes = (int32_t)wave_lds;
+    static bool attr_set = false;   // raise the dynamic LDS limit once per process
+    if (!attr_set) {
+        if (hipFuncSetAttribute((const void *)shouji::shouji_plain_kernel,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)shouji::kLdsPerCU) != hipSuccess)
+            return fail(SHOUJI_ERR_DEVICE, "cannot raise the LDS limit: %s",
+                        hipGetErrorString(hipGetLastError()));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(shouji::shouji_plain_kernel, dim3((unsigned)grid),
+                       dim3(shouji::kWave * shouji::kWavesPerGroup), lds, (hipStream_t)stream, prm);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(SHOUJI_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return ok();

@@ -41,26 +41,68 @@
 
 namespace shouji {
 
+// Truth table of a 3-input boolean function for v_bitop3_b32: bit
+// (a<<2 | b<<1 | c) of the immediate is f(a, b, c) for src0 = a, src1 = b,
+// src2 = c.
+template <class F>
+constexpr unsigned truth_table(F f) {
+    unsigned t = 0;
+    for (int i = 0; i < 8; i++)
+        if (f((i >> 2) & 1, (i >> 1) & 1, i & 1)) t |= 1u << i;
+    return t;
+}
+constexpr unsigned kTTCell = truth_table([](int a, int b, int c) { return a | (b ^ c); });
+constexpr unsigned kTTXor3 = truth_table([](int a, int b, int c) { return a ^ b ^ c; });
+constexpr unsigned kTTMaj = truth_table([](int a, int b, int c) { return a + b + c >= 2; });
+constexpr unsigned kTTMajNotA = truth_table([](int a, int b, int c) { return (1 - a) + b + c >= 2; });
+constexpr unsigned kTTAndNotA = truth_table([](int a, int b, int) { return !a && b; });
+constexpr unsigned kTTNor = truth_table([](int a, int b, int) { return !(a | b); });
+constexpr unsigned kTTOrNotA = truth_table([](int a, int b, int) { return !a || b; });
+constexpr unsigned kTTMux = truth_table([](int a, int b, int c) { return a ? b : c; });
+constexpr unsigned kTTOr3 = truth_table([](int a, int b, int c) { return a | b | c; });
+
+template <unsigned TT>
+__device__ __forceinline__ uint32_t gate(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, TT);
+}
+// select: m ? a : b, bit by bit
+__device__ __forceinline__ uint32_t mux(uint32_t m, uint32_t a, uint32_t b) {
+    return gate<kTTMux>(m, a, b);
+}
+
 // 32x32 bit transpose in registers: after the call a[b] bit k == old a[k] bit b.
+// Stages 16 and 8 move whole bytes (one v_perm_b32 per word); stages 4, 2, 1
+// are a shift and a bit-field select per word.
 __device__ __forceinline__ void transpose32(uint32_t (&a)[32]) {
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+        const uint32_t lo = __builtin_amdgcn_perm(a[i + 16], a[i], 0x05040100u);
+        const uint32_t hi = __builtin_amdgcn_perm(a[i + 16], a[i], 0x07060302u);
+        a[i] = lo;
+        a[i + 16] = hi;
+    }
+#pragma unroll
+    for (int i = 0; i < 32; i++) {
+        if ((i & 8) == 0) {
+            const uint32_t lo = __builtin_amdgcn_perm(a[i + 8], a[i], 0x06020400u);
+            const uint32_t hi = __builtin_amdgcn_perm(a[i + 8], a[i], 0x07030501u);
+            a[i] = lo;
+            a[i + 8] = hi;
+        }
+    }
 #define SHOUJI_TSTAGE(S, M)                                          \
     _Pragma("unroll") for (int i = 0; i < 32; i++) {                 \
         if ((i & (S)) == 0) {                                        \
-            const uint32_t t = ((a[i] >> (S)) ^ a[i + (S)]) & (M);   \
-            a[i + (S)] ^= t;                                         \
-            a[i] ^= t << (S);                                        \
+            const uint32_t lo = mux((M), a[i], a[i + (S)] << (S));   \
+            const uint32_t hi = mux((M), a[i] >> (S), a[i + (S)]);   \
+            a[i] = lo;                                               \
+            a[i + (S)] = hi;                                         \
         }                                                            \
     }
-    SHOUJI_TSTAGE(16, 0x0000FFFFu)
-    SHOUJI_TSTAGE(8, 0x00FF00FFu)
     SHOUJI_TSTAGE(4, 0x0F0F0F0Fu)
     SHOUJI_TSTAGE(2, 0x33333333u)
     SHOUJI_TSTAGE(1, 0x55555555u)
 #undef SHOUJI_TSTAGE
-}
-
-__device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c) {
-    return (a & b) | (c & (a | b));
 }
 
 __device__ __forceinline__ int wave_max(int v) {
@@ -82,21 +124,21 @@ struct Winner {
     uint32_t Z1[kBlock], Z2[kBlock], Z3[kBlock];
 };
 
-// One candidate diagonal over one block: build 11 cells, count each window's
-// segment, and fold it into the running winner.
+// One candidate diagonal d over one block: build 11 cells, count each
+// window's segment, and fold it into the running winner.  `rp` points at this
+// lane's ring entry for pattern position i0 - d; consecutive positions are
+// kRingStride entries apart.
 template <bool FIRST, bool MASKED>
-__device__ __forceinline__ void candidate(Winner &W, const uint2 *__restrict__ ring,
+__device__ __forceinline__ void candidate(Winner &W, const uint2 *__restrict__ rp,
                                           const uint32_t *__restrict__ nv, int lane, int i0,
-                                          int d, int R, const uint32_t (&tl)[kCols],
+                                          int d, const uint32_t (&tl)[kCols],
                                           const uint32_t (&th)[kCols]) {
-    int slot0 = (i0 - d) % R;
-    if (slot0 < 0) slot0 += R;
-    const uint2 *rp = ring + slot0 * kWave + lane;
     uint32_t cell[kCols];
 #pragma unroll
     for (int t = 0; t < kCols; t++) {
-        const uint2 pv = rp[t * kWave];
-        cell[t] = (pv.x ^ tl[t]) | (pv.y ^ th[t]);
+        const uint2 pv = rp[t * kRingStride];
+        // Eq. 1: mismatch iff either code bit differs
+        cell[t] = gate<kTTCell>(pv.x ^ tl[t], pv.y, th[t]);
     }
     if (MASKED) {
         if (d < 0) {
@@ -125,25 +167,25 @@ __device__ __forceinline__ void candidate(Winner &W, const uint2 *__restrict__ r
         // ones of cells w..w+3 = pair sum (w) + pair sum (w+2): 3-bit r2 r1 r0
         const uint32_t r0 = x[w] ^ x[w + 2];
         const uint32_t u = x[w] & x[w + 2];
-        const uint32_t r1 = a[w] ^ a[w + 2] ^ u;
+        const uint32_t r1 = gate<kTTXor3>(a[w], a[w + 2], u);
         const uint32_t r2 = a[w] & a[w + 2];
         const uint32_t k0 = cell[w];
         if (FIRST) {
             W.K0[w] = k0; W.K1[w] = r0; W.K2[w] = r1; W.K3[w] = r2;
             W.Z1[w] = cell[w + 1]; W.Z2[w] = cell[w + 2]; W.Z3[w] = cell[w + 3];
         } else {
-            // lt = (r2 r1 r0 k0) < (K3 K2 K1 K0), borrow chain from the low bit
-            const uint32_t b0 = ~k0 & W.K0[w];
-            const uint32_t b1 = maj3(~r0, W.K1[w], b0);
-            const uint32_t b2 = maj3(~r1, W.K2[w], b1);
-            const uint32_t lt = maj3(~r2, W.K3[w], b2);
-            W.K0[w] = (lt & k0) | (~lt & W.K0[w]);
-            W.K1[w] = (lt & r0) | (~lt & W.K1[w]);
-            W.K2[w] = (lt & r1) | (~lt & W.K2[w]);
-            W.K3[w] = (lt & r2) | (~lt & W.K3[w]);
-            W.Z1[w] = (lt & cell[w + 1]) | (~lt & W.Z1[w]);
-            W.Z2[w] = (lt & cell[w + 2]) | (~lt & W.Z2[w]);
-            W.Z3[w] = (lt & cell[w + 3]) | (~lt & W.Z3[w]);
+            // lt = (r2 r1 r0 k0) < (K3 K2 K1 K0): borrow chain from the low bit
+            const uint32_t b0 = gate<kTTAndNotA>(k0, W.K0[w], W.K0[w]);
+            const uint32_t b1 = gate<kTTMajNotA>(r0, W.K1[w], b0);
+            const uint32_t b2 = gate<kTTMajNotA>(r1, W.K2[w], b1);
+            const uint32_t lt = gate<kTTMajNotA>(r2, W.K3[w], b2);
+            W.K0[w] = mux(lt, k0, W.K0[w]);
+            W.K1[w] = mux(lt, r0, W.K1[w]);
+            W.K2[w] = mux(lt, r1, W.K2[w]);
+            W.K3[w] = mux(lt, r2, W.K3[w]);
+            W.Z1[w] = mux(lt, cell[w + 1], W.Z1[w]);
+            W.Z2[w] = mux(lt, cell[w + 2], W.Z2[w]);
+            W.Z3[w] = mux(lt, cell[w + 3], W.Z3[w]);
         }
     }
 }
@@ -153,47 +195,58 @@ struct FsmState {
     uint32_t ones, twos, fours, e[8];    // carry-save ones counter of final S bits
 };
 
+// Window search of one block of 8 windows at i0 (sb = ring slot of i0): the
+// winner of every window over all 2E+1 diagonals.
 template <bool MASKED>
-__device__ __forceinline__ void run_block(FsmState &F, const uint2 *__restrict__ ring,
-                                          const uint32_t *__restrict__ nv, int lane, int i0,
-                                          int Ee, int R, const uint32_t (&tl)[kCols],
-                                          const uint32_t (&th)[kCols]) {
-    Winner W;
-    // evaluation order: L1, U1, L2, U2, ..., LE, UE, M
+__device__ __forceinline__ void block_winners(Winner &W, const uint2 *__restrict__ ring,
+                                              const uint32_t *__restrict__ nv, int lane, int pl,
+                                              int i0, int sb, int Ee, int R,
+                                              const uint32_t (&tl)[kCols],
+                                              const uint32_t (&th)[kCols]) {
+    // evaluation order L1, U1, L2, U2, ..., LE, UE, M; diagonal d reads the
+    // pattern from position i0 - d, i.e. ring slot sb - d (mod R)
     if (Ee == 0) {
-        candidate<true, MASKED>(W, ring, nv, lane, i0, 0, R, tl, th);
-    } else {
-        candidate<true, MASKED>(W, ring, nv, lane, i0, -1, R, tl, th);
-        for (int c = 1; c <= 2 * Ee; c++) {
-            // c odd: upper diagonal (c+1)/2; c even: lower diagonal c/2+1; last: main
-            const int d = (c == 2 * Ee) ? 0 : ((c & 1) ? (c + 1) / 2 : -(c / 2 + 1));
-            candidate<false, MASKED>(W, ring, nv, lane, i0, d, R, tl, th);
-        }
+        candidate<true, MASKED>(W, ring + sb * kRingStride + pl, nv, lane, i0, 0, tl, th);
+        return;
     }
-    // Shouji bit-vector update, window by window
+    int sL = sb + 1 == R ? 0 : sb + 1;
+    int sU = sb == 0 ? R - 1 : sb - 1;
+    candidate<true, MASKED>(W, ring + sL * kRingStride + pl, nv, lane, i0, -1, tl, th);
+    candidate<false, MASKED>(W, ring + sU * kRingStride + pl, nv, lane, i0, 1, tl, th);
+    for (int k = 2; k <= Ee; k++) {
+        sL = sL + 1 == R ? 0 : sL + 1;
+        sU = sU == 0 ? R - 1 : sU - 1;
+        candidate<false, MASKED>(W, ring + sL * kRingStride + pl, nv, lane, i0, -k, tl, th);
+        candidate<false, MASKED>(W, ring + sU * kRingStride + pl, nv, lane, i0, k, tl, th);
+    }
+    candidate<false, MASKED>(W, ring + sb * kRingStride + pl, nv, lane, i0, 0, tl, th);
+}
+
+// Shouji bit-vector update over the 8 windows of a block, then carry-save
+// accumulation of the 8 bits that became final.
+__device__ __forceinline__ void block_update(FsmState &F, const Winner &W) {
     uint32_t o[kBlock];
 #pragma unroll
     for (int w = 0; w < kBlock; w++) {
-        const uint32_t q0 = F.s0 ^ F.s1 ^ F.s2;     // ones(S[i..i+2]) = q1 q0
-        const uint32_t q1 = maj3(F.s0, F.s1, F.s2);
-        // (q1 q0) < (K2 K1) ?
-        const uint32_t c0 = ~q0 & W.K1[w];
-        const uint32_t c1 = maj3(~q1, W.K2[w], c0);
-        // write iff ones(Z) <= ones(S[i..i+2]):  K3 == 0 and not (q < K2 K1)
-        const uint32_t wr = ~(W.K3[w] | c1);
-        o[w] = (wr & W.K0[w]) | (~wr & F.s0);
-        const uint32_t n1 = (wr & W.Z1[w]) | (~wr & F.s1);
-        const uint32_t n2 = (wr & W.Z2[w]) | (~wr & F.s2);
-        const uint32_t n3 = ~wr | W.Z3[w];
+        const uint32_t q0 = gate<kTTXor3>(F.s0, F.s1, F.s2);  // ones(S[i..i+2]) = q1 q0
+        const uint32_t q1 = gate<kTTMaj>(F.s0, F.s1, F.s2);
+        // c1 = (q1 q0) < (K2 K1)
+        const uint32_t c0 = gate<kTTAndNotA>(q0, W.K1[w], W.K1[w]);
+        const uint32_t c1 = gate<kTTMajNotA>(q1, W.K2[w], c0);
+        // write iff ones(Z) <= ones(S[i..i+2]):  K3 == 0 and not c1
+        const uint32_t wr = gate<kTTNor>(W.K3[w], c1, c1);
+        o[w] = mux(wr, W.K0[w], F.s0);
+        const uint32_t n1 = mux(wr, W.Z1[w], F.s1);
+        const uint32_t n2 = mux(wr, W.Z2[w], F.s2);
+        const uint32_t n3 = gate<kTTOrNotA>(wr, W.Z3[w], W.Z3[w]);
         F.s0 = n1; F.s1 = n2; F.s2 = n3;
     }
-    // Harley-Seal carry-save accumulation of the 8 final bits
     uint32_t t1, t2, f1, f2, g;
-#define SHOUJI_CSA(h, l, a_, b_, c_)                 \
-    {                                                \
-        const uint32_t u_ = (a_) ^ (b_);             \
-        h = ((a_) & (b_)) | (u_ & (c_));             \
-        l = u_ ^ (c_);                               \
+#define SHOUJI_CSA(h, l, a_, b_, c_)                       \
+    {                                                      \
+        const uint32_t aa_ = (a_), bb_ = (b_), cc_ = (c_); \
+        h = gate<kTTMaj>(aa_, bb_, cc_);                   \
+        l = gate<kTTXor3>(aa_, bb_, cc_);                  \
     }
     SHOUJI_CSA(t1, F.ones, F.ones, o[0], o[1])
     SHOUJI_CSA(t2, F.ones, F.ones, o[2], o[3])
@@ -211,33 +264,55 @@ __device__ __forceinline__ void run_block(FsmState &F, const uint2 *__restrict__
     }
 }
 
+// One 16-base word of 32 pairs (pair = base + 32k + pl for bit k).
 __device__ __forceinline__ void load_half(const uint32_t *__restrict__ seq, int64_t ld,
-                                          int64_t base, int64_t n, int lane, int h,
+                                          int64_t base, int64_t n, int pl, int h,
                                           uint32_t (&raw)[32]) {
     const uint32_t *row = seq + (int64_t)h * ld;
 #pragma unroll
     for (int k = 0; k < 32; k++) {
-        const int64_t p = base + (int64_t)k * kWave + lane;
+        const int64_t p = base + (int64_t)k * kPairLanes + pl;
         raw[k] = p < n ? row[p] : 0u;
     }
 }
 
-__global__ __launch_bounds__(kWave) void shouji_plain_kernel(PlainParams prm) {
-    extern __shared__ uint32_t lds[];
-    const int lane = threadIdx.x;
+// Every value of one lane half (0: lanes 0-31, 1: lanes 32-63) to all lanes.
+__device__ __forceinline__ uint32_t from_half0(uint32_t v) {
+    return __builtin_amdgcn_permlane32_swap(v, v, false, false)[0];
+}
+__device__ __forceinline__ uint32_t from_half1(uint32_t v) {
+    return __builtin_amdgcn_permlane32_swap(v, v, false, false)[1];
+}
+
+// A wavefront filters 1024 pairs.  Lanes l and l+32 hold the same 32 pairs
+// (bit k of a plane = pair base + 32k + (l & 31)); the low lane half searches
+// the even blocks of 8 windows, the high half the odd ones (the searches are
+// independent).  The bit-vector update is serial: it runs on the low half for
+// block 2j, the 3-plane state S[i..i+2] moves to the high half with one lane
+// swap per plane, the high half updates block 2j+1 and hands the state back.
+// Both halves read one pattern ring in LDS.
+__global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_plain_kernel(PlainParams prm) {
+    extern __shared__ uint32_t lds_all[];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int half = lane >> 5;
+    const int pl = lane & (kPairLanes - 1);
     const int R = prm.R;
     const int Ee = prm.Ee;
+    const int nmask = kCols + Ee;                      // mask entries per lane
+    uint32_t *lds = lds_all + (size_t)wave * (prm.lds_wave_bytes / 4);
     uint2 *ring = reinterpret_cast<uint2 *>(lds);
-    uint32_t *nv = lds + (R + kMirror) * kWave * 2;
-    const int64_t base = (int64_t)blockIdx.x * kPairsPerWave;
+    uint32_t *nv = lds + (R + kMirror) * kRingStride * 2;
+    const int64_t base = ((int64_t)blockIdx.x * kWavesPerGroup + wave) * kPairsPerWave;
     const int64_t n = prm.n;
+    if (base >= n) return;
 
     // ---- lengths: effective length per pair (0 for padding and invalid pairs)
     uint32_t lenw[32];
     int lmin = 0x7fffffff, lmax = -1;
 #pragma unroll
     for (int k = 0; k < 32; k++) {
-        const int64_t p = base + (int64_t)k * kWave + lane;
+        const int64_t p = base + (int64_t)k * kPairLanes + pl;
         int m = -1;
         if (p < n) m = prm.lengths ? prm.lengths[p] : prm.max_len;
         const bool ok = (m >= 0 && m <= prm.max_len);
@@ -261,33 +336,28 @@ __global__ __launch_bounds__(kWave) void shouji_plain_kernel(PlainParams prm) {
     for (int b = 0; b < 8; b++) F.e[b] = 0u;
 
     const int nblocks = (m_max + kBlock - 1) / kBlock;
-    uint32_t Tc[32], Tn[32];
-    if (nblocks > 0) {
-        load_half(prm.refs, prm.ld, base, n, lane, 0, Tc);
-        transpose32(Tc);
-    }
-    int p_loaded = 0;  // pattern half-chunks already in the ring
+    const int niter = (nblocks + 1) / 2;
+    const int nhalves = (m_max + kHalf - 1) / kHalf;  // words holding positions < m_max
+    const int H0 = (kBlock + kCols - 1 + Ee) / kHalf; // last pattern word iteration 0 reads
 
-    auto ensure_pattern = [&](int upto) {
-        upto = min(upto, m_max - 1);
-        while (p_loaded * 16 <= upto) {
-            uint32_t raw[32];
-            load_half(prm.reads, prm.ld, base, n, lane, p_loaded, raw);
-            transpose32(raw);
+    // transposed pattern word hp -> ring slots of positions 16hp..16hp+15
+    // (both lane halves write the same values to the same entries)
+    auto store_pattern = [&](int hp) {
+        uint32_t raw[32];
+        load_half(prm.reads, prm.ld, base, n, pl, hp, raw);
+        transpose32(raw);
+        int slot = (hp * kHalf) % R;
 #pragma unroll
-            for (int u = 0; u < 16; u++) {
-                const int q = p_loaded * 16 + u;
-                const int slot = q % R;
-                const uint2 v = make_uint2(raw[2 * u], raw[2 * u + 1]);
-                ring[slot * kWave + lane] = v;
-                if (slot < kMirror) ring[(slot + R) * kWave + lane] = v;
-            }
-            p_loaded++;
+        for (int u = 0; u < kHalf; u++) {
+            const uint2 v = make_uint2(raw[2 * u], raw[2 * u + 1]);
+            ring[slot * kRingStride + pl] = v;
+            if (slot < kMirror) ring[(slot + R) * kRingStride + pl] = v;
+            slot = slot + 1 == R ? 0 : slot + 1;
         }
     };
-    // Per-pair "position is past the end" masks for columns i0 .. i0+10+Ee
+    // per-lane "position is past the pair's end" masks, positions i0 .. i0+10+Ee
     auto fill_masks = [&](int i0) {
-        for (int s = 0; s <= kCols - 1 + Ee; s++) {
+        for (int s = 0; s < nmask; s++) {
             const int xpos = i0 + s;
             uint32_t inv;
             if (uniform) {
@@ -297,67 +367,103 @@ __global__ __launch_bounds__(kWave) void shouji_plain_kernel(PlainParams prm) {
 #pragma unroll
                 for (int b = 0; b < kLenBits; b++) {
                     const uint32_t sx = ((xpos >> b) & 1) ? ~0u : 0u;
-                    g = (sx & (Lb[b] & g)) | (~sx & (Lb[b] | g));
+                    g = mux(sx, Lb[b] & g, Lb[b] | g);
                 }
                 inv = ~g;
             }
             nv[s * kWave + lane] = inv;
         }
     };
-    auto block = [&](int i0, const uint32_t (&tl)[kCols], const uint32_t (&th)[kCols]) {
-        const bool masked = (i0 < Ee) || (i0 + kCols - 1 + Ee >= m_min);
-        if (masked) {
-            fill_masks(i0);
-            run_block<true>(F, ring, nv, lane, i0, Ee, R, tl, th);
+
+    // Text planes: Tw = the 11 positions (low, high plane) of this lane's
+    // block.  The low half's block 2j reads positions 0..10 of word j; the high
+    // half's block 2j+1 reads 8..15 of word j (carried in Tcar) and 0..2 of
+    // word j+1.  Each lane half loads and transposes its own word.
+    uint32_t Tw[2 * kCols], Tcar[2 * kBlock];
+    auto next_text = [&](int j) {
+        uint32_t raw[32];
+        const int h = j + half;
+        if (h < nhalves) {
+            load_half(prm.refs, prm.ld, base, n, pl, h, raw);
+            transpose32(raw);
         } else {
-            run_block<false>(F, ring, nv, lane, i0, Ee, R, tl, th);
+#pragma unroll
+            for (int k = 0; k < 32; k++) raw[k] = 0u;
         }
+#pragma unroll
+        for (int t = 0; t < 2 * kCols; t++) {
+            const uint32_t hi = t < 2 * kBlock ? Tcar[t] : raw[t - 2 * kBlock];
+            Tw[t] = half ? hi : raw[t];
+        }
+#pragma unroll
+        for (int t = 0; t < 2 * kBlock; t++) Tcar[t] = raw[2 * kBlock + t];
     };
 
-    for (int b = 0; b < nblocks; b += 2) {
-        const int i0 = b * kBlock;  // = 16 * half index
-        const int h = b >> 1;
-        ensure_pattern(i0 + kCols - 1 + Ee);
+    if (nblocks > 0) {
+        for (int hp = 0; hp <= H0 && hp < nhalves; hp++) store_pattern(hp);
+        {
+            uint32_t raw[32];
+            load_half(prm.refs, prm.ld, base, n, pl, 0, raw);
+            transpose32(raw);
+#pragma unroll
+            for (int t = 0; t < 2 * kBlock; t++) Tcar[t] = raw[2 * kBlock + t];
+        }
+        next_text(0);
+    }
+
+    for (int j = 0; j < niter; j++) {
+        const int i0 = kHalf * j + kBlock * half;       // this lane's block
+        const bool activeB = 2 * j + 1 < nblocks;      // the high half has a block
+        const bool masked = (kHalf * j < Ee) || (kHalf * j + kBlock + kCols - 1 + Ee >= m_min);
+        Winner W;
         {
             uint32_t tl[kCols], th[kCols];
 #pragma unroll
-            for (int t = 0; t < kCols; t++) { tl[t] = Tc[2 * t]; th[t] = Tc[2 * t + 1]; }
-            block(i0, tl, th);
-        }
-        if (b + 1 < nblocks) {
-            if ((h + 1) * 16 < m_max) {
-                load_half(prm.refs, prm.ld, base, n, lane, h + 1, Tn);
-                transpose32(Tn);
+            for (int t = 0; t < kCols; t++) { tl[t] = Tw[2 * t]; th[t] = Tw[2 * t + 1]; }
+            const int sb = i0 % R;
+            if (masked) {
+                fill_masks(i0);
+                block_winners<true>(W, ring, nv, lane, pl, i0, sb, Ee, R, tl, th);
             } else {
-#pragma unroll
-                for (int k = 0; k < 32; k++) Tn[k] = 0u;
+                block_winners<false>(W, ring, nv, lane, pl, i0, sb, Ee, R, tl, th);
             }
-            ensure_pattern(i0 + kBlock + kCols - 1 + Ee);
-            uint32_t tl[kCols], th[kCols];
-#pragma unroll
-            for (int t = 0; t < kCols; t++) {
-                const int u = kBlock + t;  // position within the half-chunk pair
-                tl[t] = u < 16 ? Tc[2 * u] : Tn[2 * (u - 16)];
-                th[t] = u < 16 ? Tc[2 * u + 1] : Tn[2 * (u - 16) + 1];
-            }
-            block(i0 + kBlock, tl, th);
-#pragma unroll
-            for (int k = 0; k < 32; k++) Tc[k] = Tn[k];
+        }
+        // serial bit-vector update: block 2j on the low half, 2j+1 on the high
+        if (half == 0) block_update(F, W);
+        F.s0 = from_half0(F.s0); F.s1 = from_half0(F.s1); F.s2 = from_half0(F.s2);
+        if (half == 1 && activeB) block_update(F, W);
+        F.s0 = from_half1(F.s0); F.s1 = from_half1(F.s1); F.s2 = from_half1(F.s2);
+        if (j + 1 < niter) {
+            // pattern word first needed by iteration j+1, after all reads of j
+            const int hp = j + 1 + H0;
+            if (hp < nhalves) store_pattern(hp);
+            next_text(j + 1);
         }
     }
 
-    // ---- counts back to one value per pair
+    // ---- add the high half's ones counter to the low half's, then output
     uint32_t cnt[32];
     cnt[0] = F.ones; cnt[1] = F.twos; cnt[2] = F.fours;
 #pragma unroll
     for (int b = 0; b < 8; b++) cnt[3 + b] = F.e[b];
+    {
+        uint32_t cy = 0u;
+#pragma unroll
+        for (int b = 0; b < 11; b++) {
+            const uint32_t o = from_half1(cnt[b]);
+            const uint32_t s_ = gate<kTTXor3>(cnt[b], o, cy);
+            cy = gate<kTTMaj>(cnt[b], o, cy);
+            cnt[b] = s_;
+        }
+    }
+    if (half == 1) return;
 #pragma unroll
     for (int b = 11; b < 32; b++) cnt[b] = 0u;
     transpose32(cnt);  // cnt[k] = ones of S over windows [0, 8*nblocks) for pair k
     const int nwin = nblocks * kBlock;
 #pragma unroll
     for (int k = 0; k < 32; k++) {
-        const int64_t p = base + (int64_t)k * kWave + lane;
+        const int64_t p = base + (int64_t)k * kPairLanes + pl;
         if (p >= n) continue;
         const int m = prm.lengths ? prm.lengths[p] : prm.max_len;
         uint8_t acc;
