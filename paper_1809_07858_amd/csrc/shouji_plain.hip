@@ -196,30 +196,53 @@ struct FsmState {
 };
 
 // Window search of one block of 8 windows at i0 (sb = ring slot of i0): the
-// winner of every window over all 2E+1 diagonals.
-template <bool MASKED>
+// winner of every window over all 2E+1 diagonals.  A candidate whose cells
+// can leave the map in this iteration (lo = first window of the iteration's
+// two blocks, m_min = shortest length in the group) takes the masked path.
+__device__ __forceinline__ bool needs_mask(int d, int lo, int m_min) {
+    const int hi_col = lo + kBlock + kCols - 1;             // last text column read
+    return (d > lo) || (hi_col >= m_min) || (hi_col - d >= m_min);
+}
+
+template <bool FIRST>
+__device__ __forceinline__ void candidate_any(bool masked, Winner &W, const uint2 *__restrict__ rp,
+                                              const uint32_t *__restrict__ nv, int lane, int i0,
+                                              int d, const uint32_t (&tl)[kCols],
+                                              const uint32_t (&th)[kCols]) {
+    if (masked)
+        candidate<FIRST, true>(W, rp, nv, lane, i0, d, tl, th);
+    else
+        candidate<FIRST, false>(W, rp, nv, lane, i0, d, tl, th);
+}
+
 __device__ __forceinline__ void block_winners(Winner &W, const uint2 *__restrict__ ring,
                                               const uint32_t *__restrict__ nv, int lane, int pl,
-                                              int i0, int sb, int Ee, int R,
+                                              int i0, int sb, int Ee, int R, int lo, int m_min,
                                               const uint32_t (&tl)[kCols],
                                               const uint32_t (&th)[kCols]) {
     // evaluation order L1, U1, L2, U2, ..., LE, UE, M; diagonal d reads the
     // pattern from position i0 - d, i.e. ring slot sb - d (mod R)
     if (Ee == 0) {
-        candidate<true, MASKED>(W, ring + sb * kRingStride + pl, nv, lane, i0, 0, tl, th);
+        candidate_any<true>(needs_mask(0, lo, m_min), W, ring + sb * kRingStride + pl, nv, lane,
+                            i0, 0, tl, th);
         return;
     }
     int sL = sb + 1 == R ? 0 : sb + 1;
     int sU = sb == 0 ? R - 1 : sb - 1;
-    candidate<true, MASKED>(W, ring + sL * kRingStride + pl, nv, lane, i0, -1, tl, th);
-    candidate<false, MASKED>(W, ring + sU * kRingStride + pl, nv, lane, i0, 1, tl, th);
+    candidate_any<true>(needs_mask(-1, lo, m_min), W, ring + sL * kRingStride + pl, nv, lane, i0,
+                        -1, tl, th);
+    candidate_any<false>(needs_mask(1, lo, m_min), W, ring + sU * kRingStride + pl, nv, lane, i0,
+                         1, tl, th);
     for (int k = 2; k <= Ee; k++) {
         sL = sL + 1 == R ? 0 : sL + 1;
         sU = sU == 0 ? R - 1 : sU - 1;
-        candidate<false, MASKED>(W, ring + sL * kRingStride + pl, nv, lane, i0, -k, tl, th);
-        candidate<false, MASKED>(W, ring + sU * kRingStride + pl, nv, lane, i0, k, tl, th);
+        candidate_any<false>(needs_mask(-k, lo, m_min), W, ring + sL * kRingStride + pl, nv, lane,
+                             i0, -k, tl, th);
+        candidate_any<false>(needs_mask(k, lo, m_min), W, ring + sU * kRingStride + pl, nv, lane,
+                             i0, k, tl, th);
     }
-    candidate<false, MASKED>(W, ring + sb * kRingStride + pl, nv, lane, i0, 0, tl, th);
+    candidate_any<false>(needs_mask(0, lo, m_min), W, ring + sb * kRingStride + pl, nv, lane, i0,
+                         0, tl, th);
 }
 
 // Shouji bit-vector update over the 8 windows of a block, then carry-save
@@ -264,15 +287,18 @@ __device__ __forceinline__ void block_update(FsmState &F, const Winner &W) {
     }
 }
 
-// One 16-base word of 32 pairs (pair = base + 32k + pl for bit k).
-__device__ __forceinline__ void load_half(const uint32_t *__restrict__ seq, int64_t ld,
-                                          int64_t base, int64_t n, int pl, int h,
-                                          uint32_t (&raw)[32]) {
-    const uint32_t *row = seq + (int64_t)h * ld;
+// One 16-base word of 32 pairs (pair = base + 32k + pl for bit k) from row
+// `row` (= seq + w*ld + base).  `full`: all 1024 pairs of the wavefront exist,
+// so no per-pair range check is needed.
+__device__ __forceinline__ void load_word(const uint32_t *__restrict__ row, bool full,
+                                          int64_t left, int pl, uint32_t (&raw)[32]) {
+    const uint32_t *q = row + pl;
+    if (full) {
 #pragma unroll
-    for (int k = 0; k < 32; k++) {
-        const int64_t p = base + (int64_t)k * kPairLanes + pl;
-        raw[k] = p < n ? row[p] : 0u;
+        for (int k = 0; k < 32; k++) raw[k] = q[k * kPairLanes];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 32; k++) raw[k] = (k * kPairLanes + pl < left) ? q[k * kPairLanes] : 0u;
     }
 }
 
@@ -306,18 +332,36 @@ __global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_plain_kernel
     const int64_t base = ((int64_t)blockIdx.x * kWavesPerGroup + wave) * kPairsPerWave;
     const int64_t n = prm.n;
     if (base >= n) return;
+    const bool full = base + kPairsPerWave <= n;
 
-    // ---- lengths: effective length per pair (0 for padding and invalid pairs)
+    // ---- lengths: effective length per pair (0 for padding and invalid pairs),
+    // bit kLenBits set for a valid pair
     uint32_t lenw[32];
     int lmin = 0x7fffffff, lmax = -1;
+    {
+        const int32_t *lp = prm.lengths ? prm.lengths + base + pl : nullptr;
 #pragma unroll
-    for (int k = 0; k < 32; k++) {
-        const int64_t p = base + (int64_t)k * kPairLanes + pl;
-        int m = -1;
-        if (p < n) m = prm.lengths ? prm.lengths[p] : prm.max_len;
-        const bool ok = (m >= 0 && m <= prm.max_len);
-        lenw[k] = ok ? (uint32_t)m : 0u;
-        if (ok) { lmin = min(lmin, m); lmax = max(lmax, m); }
+        for (int k = 0; k < 32; k++) {
+            int m = prm.max_len;
+            const bool in = full || (base + (int64_t)k * kPairLanes + pl < n);
+            if (lp) m = in ? lp[k * kPairLanes] : -1;
+            const bool ok = in && m >= 0 && m <= prm.max_len;
+            lenw[k] = ok ? ((uint32_t)m | (1u << kLenBits)) : 0u;
+            if (ok) { lmin = min(lmin, m); lmax = max(lmax, m); }
+        }
+    }
+    // the first words do not depend on the lengths: load them before waiting
+    const int nwords = (prm.max_len + kHalf - 1) / kHalf;
+    uint32_t raw0[32];
+    {
+        const int w = 0;
+        if (w < nwords) {
+            const uint32_t *row = (half ? prm.refs : prm.reads) + base;
+            load_word(row, full, n - base, pl, raw0);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 32; k++) raw0[k] = 0u;
+        }
     }
     lmin = wave_min(lmin);
     lmax = wave_max(lmax);
@@ -325,9 +369,9 @@ __global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_plain_kernel
     const int m_min = lmax < 0 ? 0 : lmin;
     const bool uniform = (m_min == m_max);
     transpose32(lenw);                 // lenw[b] = bit b of the 32 lengths
-    uint32_t Lb[kLenBits];
+    uint32_t Lb[kLenBits + 1];         // length bits, then the valid-pair plane
 #pragma unroll
-    for (int b = 0; b < kLenBits; b++) Lb[b] = lenw[b];
+    for (int b = 0; b <= kLenBits; b++) Lb[b] = lenw[b];
 
     FsmState F;
     F.s0 = F.s1 = F.s2 = ~0u;
@@ -340,21 +384,6 @@ __global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_plain_kernel
     const int nhalves = (m_max + kHalf - 1) / kHalf;  // words holding positions < m_max
     const int H0 = (kBlock + kCols - 1 + Ee) / kHalf; // last pattern word iteration 0 reads
 
-    // transposed pattern word hp -> ring slots of positions 16hp..16hp+15
-    // (both lane halves write the same values to the same entries)
-    auto store_pattern = [&](int hp) {
-        uint32_t raw[32];
-        load_half(prm.reads, prm.ld, base, n, pl, hp, raw);
-        transpose32(raw);
-        int slot = (hp * kHalf) % R;
-#pragma unroll
-        for (int u = 0; u < kHalf; u++) {
-            const uint2 v = make_uint2(raw[2 * u], raw[2 * u + 1]);
-            ring[slot * kRingStride + pl] = v;
-            if (slot < kMirror) ring[(slot + R) * kRingStride + pl] = v;
-            slot = slot + 1 == R ? 0 : slot + 1;
-        }
-    };
     // per-lane "position is past the pair's end" masks, positions i0 .. i0+10+Ee
     auto fill_masks = [&](int i0) {
         for (int s = 0; s < nmask; s++) {
@@ -375,58 +404,84 @@ __global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_plain_kernel
         }
     };
 
-    // Text planes: Tw = the 11 positions (low, high plane) of this lane's
-    // block.  The low half's block 2j reads positions 0..10 of word j; the high
-    // half's block 2j+1 reads 8..15 of word j (carried in Tcar) and 0..2 of
-    // word j+1.  Each lane half loads and transposes its own word.
-    uint32_t Tw[2 * kCols], Tcar[2 * kBlock];
-    auto next_text = [&](int j) {
-        uint32_t raw[32];
-        const int h = j + half;
-        if (h < nhalves) {
-            load_half(prm.refs, prm.ld, base, n, pl, h, raw);
-            transpose32(raw);
+    // One transpose pass: the low lane half turns pattern word pw into ring
+    // entries (positions 16pw..16pw+15), the high half turns text word tw into
+    // planes left in raw (plane 2u = low code bit of position 16tw+u).  Words
+    // at or beyond `limit` are not read (zero planes).
+    auto pass_load = [&](int pw, int tw, int limit, uint32_t (&raw)[32]) {
+        const int w = half ? tw : pw;
+        if (w >= 0 && w < limit) {
+            const uint32_t *row = (half ? prm.refs : prm.reads) + (int64_t)w * prm.ld + base;
+            load_word(row, full, n - base, pl, raw);
         } else {
 #pragma unroll
             for (int k = 0; k < 32; k++) raw[k] = 0u;
         }
+    };
+    auto pass_finish = [&](int pw, int limit, uint32_t (&raw)[32]) {
+        transpose32(raw);
+        if (half == 0 && pw < limit) {
+            int slot = (pw * kHalf) % R;
+#pragma unroll
+            for (int u = 0; u < kHalf; u++) {
+                const uint2 v = make_uint2(raw[2 * u], raw[2 * u + 1]);
+                ring[slot * kRingStride + pl] = v;
+                if (slot < kMirror) ring[(slot + R) * kRingStride + pl] = v;
+                slot = slot + 1 == R ? 0 : slot + 1;
+            }
+        }
+    };
+    auto pass = [&](int pw, int tw, uint32_t (&raw)[32]) {
+        pass_load(pw, tw, nhalves, raw);
+        pass_finish(pw, nhalves, raw);
+    };
+
+    // Text planes: Tw = the 11 positions (low, high plane) of this lane's
+    // block.  The low half's block 2j reads positions 0..10 of word j, the high
+    // half's block 2j+1 positions 8..15 of word j and 0..2 of word j+1.  The
+    // high half transposes every text word once; Tn keeps what the next
+    // iteration needs of the newest word: in the low half its positions 0..10
+    // (received by lane swaps), in the high half its positions 8..15.
+    uint32_t Tw[2 * kCols], Tn[2 * kCols];
+    // after a pass that left text word j+1 in the high half's raw, with Tn
+    // holding word j: set Tw for blocks 2j (low) and 2j+1 (high), Tn for word j+1
+    auto take_text = [&](const uint32_t (&raw)[32]) {
+#pragma unroll
+        for (int t = 0; t < 2 * kCols; t++)
+            Tw[t] = (t < 2 * kBlock || !half) ? Tn[t] : raw[t - 2 * kBlock];
 #pragma unroll
         for (int t = 0; t < 2 * kCols; t++) {
-            const uint32_t hi = t < 2 * kBlock ? Tcar[t] : raw[t - 2 * kBlock];
-            Tw[t] = half ? hi : raw[t];
+            const uint32_t lowv = from_half1(raw[t]);
+            Tn[t] = (half && t < 2 * kBlock) ? raw[2 * kBlock + t] : lowv;
         }
-#pragma unroll
-        for (int t = 0; t < 2 * kBlock; t++) Tcar[t] = raw[2 * kBlock + t];
     };
 
     if (nblocks > 0) {
-        for (int hp = 0; hp <= H0 && hp < nhalves; hp++) store_pattern(hp);
-        {
-            uint32_t raw[32];
-            load_half(prm.refs, prm.ld, base, n, pl, 0, raw);
-            transpose32(raw);
+        // pattern words 0..H0 into the ring; text words 0 and 1 into Tn / Tw
+        uint32_t raw1[32];
+        pass_finish(0, nhalves, raw0);
 #pragma unroll
-            for (int t = 0; t < 2 * kBlock; t++) Tcar[t] = raw[2 * kBlock + t];
+        for (int t = 0; t < 2 * kCols; t++) {
+            const uint32_t lowv = from_half1(raw0[t]);
+            Tn[t] = (half && t < 2 * kBlock) ? raw0[2 * kBlock + t] : lowv;
         }
-        next_text(0);
+        pass(1, 1, raw1);
+        take_text(raw1);
+        for (int hp = 2; hp <= H0; hp++) pass(hp, -1, raw1);
     }
 
     for (int j = 0; j < niter; j++) {
-        const int i0 = kHalf * j + kBlock * half;       // this lane's block
-        const bool activeB = 2 * j + 1 < nblocks;      // the high half has a block
-        const bool masked = (kHalf * j < Ee) || (kHalf * j + kBlock + kCols - 1 + Ee >= m_min);
+        const int lo = kHalf * j;                       // first window of the iteration
+        const int i0 = lo + kBlock * half;              // this lane's block
+        const bool activeB = 2 * j + 1 < nblocks;       // the high half has a block
         Winner W;
         {
             uint32_t tl[kCols], th[kCols];
 #pragma unroll
             for (int t = 0; t < kCols; t++) { tl[t] = Tw[2 * t]; th[t] = Tw[2 * t + 1]; }
             const int sb = i0 % R;
-            if (masked) {
-                fill_masks(i0);
-                block_winners<true>(W, ring, nv, lane, pl, i0, sb, Ee, R, tl, th);
-            } else {
-                block_winners<false>(W, ring, nv, lane, pl, i0, sb, Ee, R, tl, th);
-            }
+            if ((Ee > lo) || (lo + kBlock + kCols - 1 + Ee >= m_min)) fill_masks(i0);
+            block_winners(W, ring, nv, lane, pl, i0, sb, Ee, R, lo, m_min, tl, th);
         }
         // serial bit-vector update: block 2j on the low half, 2j+1 on the high
         if (half == 0) block_update(F, W);
@@ -434,10 +489,11 @@ __global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_plain_kernel
         if (half == 1 && activeB) block_update(F, W);
         F.s0 = from_half1(F.s0); F.s1 = from_half1(F.s1); F.s2 = from_half1(F.s2);
         if (j + 1 < niter) {
-            // pattern word first needed by iteration j+1, after all reads of j
-            const int hp = j + 1 + H0;
-            if (hp < nhalves) store_pattern(hp);
-            next_text(j + 1);
+            // after all reads of iteration j: the pattern word iteration j+1
+            // first needs, and text word j+2
+            uint32_t raw[32];
+            pass(j + 1 + H0, j + 2, raw);
+            take_text(raw);
         }
     }
 
@@ -457,28 +513,31 @@ __global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_plain_kernel
         }
     }
     if (half == 1) return;
+    // rows 16.. carry each pair's length and valid bit through the transpose
 #pragma unroll
-    for (int b = 11; b < 32; b++) cnt[b] = 0u;
-    transpose32(cnt);  // cnt[k] = ones of S over windows [0, 8*nblocks) for pair k
+    for (int b = 11; b < 32; b++) cnt[b] = (b >= 16 && b <= 16 + kLenBits) ? Lb[b - 16] : 0u;
+    transpose32(cnt);  // cnt[k]: ones of S over windows [0, 8*nblocks) | length << 16 | valid << 27
     const int nwin = nblocks * kBlock;
+    uint8_t *oa = prm.out_accept + base + pl;
+    int16_t *op = prm.out_popcount ? prm.out_popcount + base + pl : nullptr;
 #pragma unroll
     for (int k = 0; k < 32; k++) {
-        const int64_t p = base + (int64_t)k * kPairLanes + pl;
-        if (p >= n) continue;
-        const int m = prm.lengths ? prm.lengths[p] : prm.max_len;
+        if (!full && base + (int64_t)k * kPairLanes + pl >= n) continue;
+        const uint32_t w = cnt[k];
+        const int m = (int)((w >> 16) & ((1u << kLenBits) - 1));
         uint8_t acc;
         int16_t pc;
-        if (m < 0 || m > prm.max_len) {
+        if (!((w >> (16 + kLenBits)) & 1u)) {
             acc = 0xFF;
             pc = -1;
         } else {
             // S stays 1 on [m, nwin): those ones are not part of the pair
-            const int ones = (int)cnt[k] - (nwin - m);
+            const int ones = (int)(w & 0xFFFFu) - (nwin - m);
             acc = ones <= prm.E ? 1 : 0;
             pc = (int16_t)ones;
         }
-        prm.out_accept[p] = acc;
-        if (prm.out_popcount) prm.out_popcount[p] = pc;
+        oa[k * kPairLanes] = acc;
+        if (op) op[k * kPairLanes] = pc;
     }
 }
 
