@@ -16,7 +16,6 @@ constexpr int kLenBits = 11;                  // lengths 0..1024
 constexpr int kHalf = 16;                     // bases per packed word
 constexpr int kWavesPerGroup = 4;             // wavefronts per workgroup
 constexpr size_t kLdsPerCU = 160 * 1024;      // gfx950
-constexpr int kBufferWord3 = 0x00020000;      // buffer resource word 3 (raw dword access, gfx9 family)
 
 struct PlainParams {
     const uint32_t *reads;
