@@ -83,6 +83,56 @@ int shouji_filter(const uint32_t *reads, const uint32_t *refs, const int32_t *le
                   int32_t E, uint8_t *out_accept, int16_t *out_popcount,
                   int64_t n_pairs, int32_t max_len, int64_t ld, void *stream);
 
+/*
+ * Batched form: mixed lengths and one edit threshold per pair in one pass.
+ *
+ * Same filter as shouji_filter (Sec. 2.2, Eq. 1, Algorithm 1) applied to every
+ * pair with its own threshold E_per_pair[p]: results are identical to filtering
+ * each pair alone.  Internally the pairs are grouped into bins of equal E and
+ * similar length (a copy into the caller's workspace), the bins are cut into
+ * tiles of up to 1024 pairs, and one kernel per E class filters all tiles,
+ * writing results at the pairs' original indices.  Nothing is allocated and
+ * every step is a kernel on `stream`, so a call can be captured in a graph
+ * (the workspace contents are overwritten by every call).
+ *
+ *   reads, refs, lengths, ld, max_len, out_accept, out_popcount, n_pairs:
+ *                 as for shouji_filter (lengths may be NULL).
+ *   E_per_pair    n_pairs int32 thresholds (device).  A pair whose length is
+ *                 outside [0, max_len], whose E is negative, or whose E after
+ *                 clamping to m-1 exceeds SHOUJI_MAX_E gets the sentinels.
+ *   workspace     device buffer of at least shouji_batched_workspace_bytes()
+ *                 bytes, owned by the caller; one call at a time per buffer.
+ *   config        tuning knobs, or NULL: the autotuned choice for this size
+ *                 (shouji_tune_batched), else the defaults.
+ */
+typedef struct {
+    int32_t bin_width;       /* length bucket in bases: 4, 8, 16 or 32 (0: default 8)  */
+    int32_t waves_per_group; /* wavefronts per workgroup: 1, 2 or 4 (0: default 4)      */
+} shouji_batched_config;
+
+/* Workspace bytes shouji_filter_batched needs for n_pairs pairs of at most
+ * max_len bases (any config); negative status on bad arguments. */
+int64_t shouji_batched_workspace_bytes(int64_t n_pairs, int32_t max_len);
+
+int shouji_filter_batched(const uint32_t *reads, const uint32_t *refs, const int32_t *lengths,
+                          const int32_t *E_per_pair, uint8_t *out_accept, int16_t *out_popcount,
+                          int64_t n_pairs, int32_t max_len, int64_t ld, void *workspace,
+                          int64_t workspace_bytes, const shouji_batched_config *config,
+                          void *stream);
+
+/*
+ * Autotuner of the batched form: runs every config (bin width x wavefronts
+ * per workgroup) three times on these inputs, timed with events on `stream`
+ * (the call synchronises the stream), keeps the fastest for this size class
+ * (max_len / 64, log2 n_pairs) for later calls with config == NULL, and
+ * returns it in *best (and its time in *best_ms).  Outputs hold the last run.
+ */
+int shouji_tune_batched(const uint32_t *reads, const uint32_t *refs, const int32_t *lengths,
+                        const int32_t *E_per_pair, uint8_t *out_accept, int16_t *out_popcount,
+                        int64_t n_pairs, int32_t max_len, int64_t ld, void *workspace,
+                        int64_t workspace_bytes, void *stream, shouji_batched_config *best,
+                        float *best_ms);
+
 /* Text of the last non-OK status returned on this thread ("" if none). */
 const char *shouji_last_error(void);
 

@@ -39,6 +39,12 @@ def lib():
         vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
         L.shouji_filter.restype = ctypes.c_int
         L.shouji_filter.argtypes = [vp, vp, vp, i32, vp, vp, i64, i32, i64, vp]
+        L.shouji_batched_workspace_bytes.restype = ctypes.c_int64
+        L.shouji_batched_workspace_bytes.argtypes = [i64, i32]
+        L.shouji_filter_batched.restype = ctypes.c_int
+        L.shouji_filter_batched.argtypes = [vp, vp, vp, vp, vp, vp, i64, i32, i64, vp, i64, vp, vp]
+        L.shouji_tune_batched.restype = ctypes.c_int
+        L.shouji_tune_batched.argtypes = [vp, vp, vp, vp, vp, vp, i64, i32, i64, vp, i64, vp, vp, vp]
         L.shouji_last_error.restype = ctypes.c_char_p
         L.shouji_version.restype = ctypes.c_int
         _lib = L
@@ -114,3 +120,80 @@ def shouji_filter(reads, refs, lengths, E, out_accept=None, out_popcount=None, n
                              int(n_pairs), int(max_len), ld, _stream_handle(stream))
     _check(rc)
     return out_accept, out_popcount
+
+
+class BatchedConfig(ctypes.Structure):
+    """Tuning knobs of the batched form (0 = default / autotuned)."""
+    _fields_ = [("bin_width", ctypes.c_int32), ("waves_per_group", ctypes.c_int32)]
+
+
+def batched_workspace_bytes(n_pairs, max_len):
+    v = lib().shouji_batched_workspace_bytes(int(n_pairs), int(max_len))
+    if v < 0:
+        _check(int(v))
+    return int(v)
+
+
+def _batched_args(reads, refs, lengths, E_per_pair, out_accept, out_popcount, n_pairs, max_len,
+                  workspace, want_popcount):
+    import torch
+    if reads.dim() != 2 or refs.shape != reads.shape:
+        raise ValueError("reads/refs must be [nwords, ld] tensors of the same shape")
+    for t in (reads, refs):
+        if not t.is_cuda or t.dtype != torch.int32 or not t.is_contiguous():
+            raise ValueError("reads/refs must be contiguous int32 CUDA tensors")
+    if E_per_pair is None or not E_per_pair.is_cuda or E_per_pair.dtype != torch.int32:
+        raise ValueError("E_per_pair must be an int32 CUDA tensor")
+    ld = reads.shape[1]
+    if n_pairs is None:
+        n_pairs = E_per_pair.shape[0]
+    if max_len is None:
+        max_len = reads.shape[0] * BASES_PER_WORD
+    if reads.shape[0] < nwords(max_len):
+        raise ValueError("reads hold fewer words than max_len needs")
+    if lengths is not None and (not lengths.is_cuda or lengths.dtype != torch.int32
+                                or lengths.numel() < n_pairs):
+        raise ValueError("lengths must be an int32 CUDA tensor with n_pairs entries")
+    dev = reads.device
+    if out_accept is None:
+        out_accept = torch.empty(n_pairs, dtype=torch.uint8, device=dev)
+    if out_popcount is None and want_popcount:
+        out_popcount = torch.empty(n_pairs, dtype=torch.int16, device=dev)
+    need = batched_workspace_bytes(n_pairs, max_len)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    if workspace.numel() * workspace.element_size() < need:
+        raise ValueError("workspace too small: %d bytes needed" % need)
+    args = [ctypes.c_void_p(reads.data_ptr()), ctypes.c_void_p(refs.data_ptr()),
+            None if lengths is None else ctypes.c_void_p(lengths.data_ptr()),
+            ctypes.c_void_p(E_per_pair.data_ptr()), ctypes.c_void_p(out_accept.data_ptr()),
+            None if out_popcount is None else ctypes.c_void_p(out_popcount.data_ptr()),
+            int(n_pairs), int(max_len), int(ld), ctypes.c_void_p(workspace.data_ptr()),
+            int(workspace.numel() * workspace.element_size())]
+    return args, out_accept, out_popcount, workspace
+
+
+def shouji_filter_batched(reads, refs, lengths, E_per_pair, out_accept=None, out_popcount=None,
+                          n_pairs=None, max_len=None, workspace=None, config=None, stream=None,
+                          want_popcount=True):
+    """Batched form: per-pair thresholds, mixed lengths.  config: (bin_width, waves_per_group) or None."""
+    args, out_accept, out_popcount, workspace = _batched_args(
+        reads, refs, lengths, E_per_pair, out_accept, out_popcount, n_pairs, max_len, workspace,
+        want_popcount)
+    cfg = None
+    if config is not None:
+        cfg = ctypes.byref(BatchedConfig(int(config[0]), int(config[1])))
+    _check(lib().shouji_filter_batched(*args, cfg, _stream_handle(stream)))
+    return out_accept, out_popcount
+
+
+def tune_batched(reads, refs, lengths, E_per_pair, n_pairs=None, max_len=None, workspace=None,
+                 stream=None):
+    """Run the library's autotuner on these inputs; returns ((bin_width, waves_per_group), ms)."""
+    args, _, _, _ = _batched_args(reads, refs, lengths, E_per_pair, None, None, n_pairs, max_len,
+                                  workspace, True)
+    best = BatchedConfig(0, 0)
+    ms = ctypes.c_float(0.0)
+    _check(lib().shouji_tune_batched(*args, _stream_handle(stream), ctypes.byref(best),
+                                     ctypes.byref(ms)))
+    return (best.bin_width, best.waves_per_group), float(ms.value)

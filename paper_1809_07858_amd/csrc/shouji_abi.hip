@@ -3,6 +3,11 @@
 #include <stdarg.h>
 #include <stdio.h>
 #include <stdint.h>
+#include <stdlib.h>
+
+#include <map>
+#include <mutex>
+#include <utility>
 
 #include "../../include/shouji.h"
 #include "shouji_internal.h"
@@ -27,6 +32,21 @@ int ok() {
 }  // namespace
 
 extern "C" const char *shouji_last_error(void) { return g_err; }
+
+namespace {
+
+// Raise the dynamic LDS limit of a kernel once per process.
+int raise_lds_limit(const void *kernel, bool &done) {
+    if (done) return SHOUJI_OK;
+    if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)shouji::kLdsPerCU) != hipSuccess)
+        return fail(SHOUJI_ERR_DEVICE, "cannot raise the LDS limit: %s",
+                    hipGetErrorString(hipGetLastError()));
+    done = true;
+    return SHOUJI_OK;
+}
+
+}  // namespace
 
 extern "C" int shouji_version(void) { return 1 * 10000 + 0 * 100 + 0; }
 
@@ -66,18 +86,206 @@ extern "C" int shouji_filter(const uint32_t *reads, const uint32_t *refs, const 
     const int64_t grid = (waves + shouji::kWavesPerGroup - 1) / shouji::kWavesPerGroup;
     if (grid > 0x7fffffff) return fail(SHOUJI_ERR_ARG, "n_pairs too large");
     prm.lds_wave_bytes = (int32_t)wave_lds;
-    static bool attr_set = false;   // raise the dynamic LDS limit once per process
-    if (!attr_set) {
-        if (hipFuncSetAttribute((const void *)shouji::shouji_plain_kernel,
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)shouji::kLdsPerCU) != hipSuccess)
-            return fail(SHOUJI_ERR_DEVICE, "cannot raise the LDS limit: %s",
-                        hipGetErrorString(hipGetLastError()));
-        attr_set = true;
-    }
+    static bool attr_set = false;
+    if (int rc = raise_lds_limit((const void *)shouji::shouji_plain_kernel, attr_set)) return rc;
     hipLaunchKernelGGL(shouji::shouji_plain_kernel, dim3((unsigned)grid),
                        dim3(shouji::kWave * shouji::kWavesPerGroup), lds, (hipStream_t)stream, prm);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(SHOUJI_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+// ---------------------------------------------------------------- batched form
+
+namespace {
+
+struct TuneKey {
+    int len_bucket, n_log2;
+    bool operator<(const TuneKey &o) const {
+        return len_bucket != o.len_bucket ? len_bucket < o.len_bucket : n_log2 < o.n_log2;
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, shouji_batched_config> g_tune;
+
+TuneKey tune_key(int64_t n, int32_t max_len) {
+    int lg = 0;
+    while ((int64_t(1) << (lg + 1)) <= n) lg++;
+    return TuneKey{max_len / 64, lg};
+}
+
+bool valid_config(const shouji_batched_config &c) {
+    return (c.bin_width == 4 || c.bin_width == 8 || c.bin_width == 16 || c.bin_width == 32) &&
+           (c.waves_per_group == 1 || c.waves_per_group == 2 || c.waves_per_group == 4);
+}
+
+shouji_batched_config resolve_config(const shouji_batched_config *cfg, int64_t n, int32_t max_len) {
+    if (cfg && (cfg->bin_width || cfg->waves_per_group)) {
+        shouji_batched_config c = *cfg;
+        if (!c.bin_width) c.bin_width = 8;
+        if (!c.waves_per_group) c.waves_per_group = shouji::kWavesPerGroup;
+        return c;
+    }
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(tune_key(n, max_len));
+    if (it != g_tune.end()) return it->second;
+    return shouji_batched_config{8, shouji::kWavesPerGroup};
+}
+
+}  // namespace
+
+extern "C" int64_t shouji_batched_workspace_bytes(int64_t n_pairs, int32_t max_len) {
+    if (n_pairs < 0) return fail(SHOUJI_ERR_ARG, "n_pairs < 0");
+    if (max_len < 0 || max_len > SHOUJI_MAX_LEN)
+        return fail(SHOUJI_ERR_RANGE, "max_len %d outside [0, %d]", max_len, SHOUJI_MAX_LEN);
+    ok();
+    return (int64_t)shouji::batched_layout(n_pairs, max_len, shouji::kMinBinWidth).total;
+}
+
+extern "C" int shouji_filter_batched(const uint32_t *reads, const uint32_t *refs,
+                                     const int32_t *lengths, const int32_t *E_per_pair,
+                                     uint8_t *out_accept, int16_t *out_popcount, int64_t n_pairs,
+                                     int32_t max_len, int64_t ld, void *workspace,
+                                     int64_t workspace_bytes, const shouji_batched_config *config,
+                                     void *stream) {
+    if (n_pairs < 0) return fail(SHOUJI_ERR_ARG, "n_pairs < 0 (%lld)", (long long)n_pairs);
+    if (max_len < 0 || max_len > SHOUJI_MAX_LEN)
+        return fail(SHOUJI_ERR_RANGE, "max_len %d outside [0, %d]", max_len, SHOUJI_MAX_LEN);
+    if (n_pairs == 0) return ok();
+    if (!reads || !refs || !E_per_pair || !out_accept || !workspace)
+        return fail(SHOUJI_ERR_NULL, "reads, refs, E_per_pair, out_accept and workspace are required");
+    if (ld < n_pairs) return fail(SHOUJI_ERR_ARG, "ld %lld < n_pairs %lld", (long long)ld, (long long)n_pairs);
+    const shouji_batched_config cfg = resolve_config(config, n_pairs, max_len);
+    if (!valid_config(cfg))
+        return fail(SHOUJI_ERR_ARG, "bad config (bin_width %d, waves_per_group %d)", cfg.bin_width,
+                    cfg.waves_per_group);
+    const shouji::BatchedLayout L = shouji::batched_layout(n_pairs, max_len, cfg.bin_width);
+    const int64_t need = (int64_t)shouji::batched_layout(n_pairs, max_len, shouji::kMinBinWidth).total;
+    if (workspace_bytes < need)
+        return fail(SHOUJI_ERR_ARG, "workspace of %lld bytes, %lld needed", (long long)workspace_bytes,
+                    (long long)need);
+    hipStream_t st = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    int32_t *counts = (int32_t *)(ws + L.counts);
+    int32_t *ntiles = (int32_t *)(ws + L.ntiles);
+
+    // 1. histogram of (length bucket, E)
+    hipLaunchKernelGGL(shouji::fill_i32_kernel, dim3((L.nbins + 255) / 256), dim3(256), 0, st, counts,
+                       (int64_t)L.nbins, 0);
+    {
+        const int64_t blocks = (n_pairs + 255) / 256;
+        hipLaunchKernelGGL(shouji::bin_count_kernel, dim3((unsigned)(blocks < 2048 ? blocks : 2048)),
+                           dim3(256), (size_t)L.nbins * 4, st, lengths, E_per_pair, n_pairs, max_len,
+                           cfg.bin_width, L.nbins, counts);
+    }
+    // 2. bin offsets and tile lists
+    shouji::PlanOut po;
+    po.offsets = (int64_t *)(ws + L.offsets);
+    po.cursors = (int64_t *)(ws + L.cursors);
+    for (int c = 0; c < shouji::kEClasses; c++) po.tiles[c] = (int4 *)(ws + L.tiles[c]);
+    po.ntiles = ntiles;
+    hipLaunchKernelGGL(shouji::bin_plan_kernel, dim3(1), dim3(shouji::kPlanThreads), 0, st, counts,
+                       L.nbins, (max_len + cfg.bin_width - 1) / cfg.bin_width + 1, po);
+    // 3. scatter into the binned workspace
+    shouji::ScatterParams sp;
+    sp.reads = reads;
+    sp.refs = refs;
+    sp.ld = ld;
+    sp.lengths = lengths;
+    sp.Ep = E_per_pair;
+    sp.n = n_pairs;
+    sp.max_len = max_len;
+    sp.bw = cfg.bin_width;
+    sp.cursors = po.cursors;
+    sp.bperm = (int64_t *)(ws + L.bperm);
+    sp.blens = (int32_t *)(ws + L.blens);
+    sp.bE = (int32_t *)(ws + L.bE);
+    sp.breads = (uint32_t *)(ws + L.breads);
+    sp.brefs = (uint32_t *)(ws + L.brefs);
+    sp.bld = n_pairs;
+    sp.out_accept = out_accept;
+    sp.out_popcount = out_popcount;
+    {
+        const int64_t blocks = (n_pairs + 255) / 256;
+        hipLaunchKernelGGL(shouji::bin_scatter_kernel, dim3((unsigned)(blocks < 8192 ? blocks : 8192)),
+                           dim3(256), 0, st, sp);
+    }
+    // 4. the filter over the tiles, largest E class first
+    static bool attr_set = false;
+    if (int rc = raise_lds_limit((const void *)shouji::shouji_tiles_kernel, attr_set)) return rc;
+    const int Emax_len = max_len > 0 ? max_len - 1 : 0;
+    for (int c = shouji::kEClasses - 1; c >= 0; c--) {
+        int Ecls = c == 0 ? shouji::kEClassBound0 : shouji::kMaxE;
+        if (Ecls > Emax_len) Ecls = Emax_len;
+        if (c == 1 && Emax_len <= shouji::kEClassBound0) continue;   // class 1 is empty
+        shouji::TilesParams tp;
+        tp.breads = sp.breads;
+        tp.brefs = sp.brefs;
+        tp.ld = n_pairs;
+        tp.blens = sp.blens;
+        tp.bE = sp.bE;
+        tp.bperm = sp.bperm;
+        tp.tiles = po.tiles[c];
+        tp.ntiles = ntiles + c;
+        tp.max_len = max_len;
+        tp.R = shouji::ring_slots(Ecls);
+        const size_t wave_lds = shouji::plain_lds_wave_bytes(Ecls);
+        int wpg = cfg.waves_per_group;
+        while (wpg > 1 && wave_lds * wpg > shouji::kLdsPerCU) wpg >>= 1;
+        if (wave_lds * wpg > shouji::kLdsPerCU) return fail(SHOUJI_ERR_RANGE, "LDS too small for E %d", Ecls);
+        tp.lds_wave_bytes = (int32_t)wave_lds;
+        tp.waves_per_group = wpg;
+        tp.out_accept = out_accept;
+        tp.out_popcount = out_popcount;
+        const int64_t grid = (L.max_tiles + wpg - 1) / wpg;
+        hipLaunchKernelGGL(shouji::shouji_tiles_kernel, dim3((unsigned)grid), dim3(shouji::kWave * wpg),
+                           wave_lds * wpg, st, tp);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SHOUJI_ERR_DEVICE, "batched launch failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+extern "C" int shouji_tune_batched(const uint32_t *reads, const uint32_t *refs, const int32_t *lengths,
+                                   const int32_t *E_per_pair, uint8_t *out_accept,
+                                   int16_t *out_popcount, int64_t n_pairs, int32_t max_len, int64_t ld,
+                                   void *workspace, int64_t workspace_bytes, void *stream,
+                                   shouji_batched_config *best, float *best_ms) {
+    static const int widths[] = {4, 8, 16, 32};
+    static const int wpgs[] = {2, 4};
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+        return fail(SHOUJI_ERR_DEVICE, "cannot create events");
+    shouji_batched_config top{0, 0};
+    float top_ms = 1e30f;
+    int rc = SHOUJI_OK;
+    for (int wi = 0; wi < 4 && rc == SHOUJI_OK; wi++) {
+        for (int gi = 0; gi < 2 && rc == SHOUJI_OK; gi++) {
+            const shouji_batched_config c{widths[wi], wpgs[gi]};
+            rc = shouji_filter_batched(reads, refs, lengths, E_per_pair, out_accept, out_popcount,
+                                       n_pairs, max_len, ld, workspace, workspace_bytes, &c, stream);
+            if (rc) break;
+            hipEventRecord(a, st);
+            for (int r = 0; r < 3 && rc == SHOUJI_OK; r++)
+                rc = shouji_filter_batched(reads, refs, lengths, E_per_pair, out_accept, out_popcount,
+                                           n_pairs, max_len, ld, workspace, workspace_bytes, &c, stream);
+            hipEventRecord(b, st);
+            if (hipEventSynchronize(b) != hipSuccess) { rc = fail(SHOUJI_ERR_DEVICE, "tuning run failed"); break; }
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, a, b);
+            ms /= 3.f;
+            if (ms < top_ms) { top_ms = ms; top = c; }
+        }
+    }
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune[tune_key(n_pairs, max_len)] = top;
+    }
+    if (best) *best = top;
+    if (best_ms) *best_ms = top_ms;
     return ok();
 }

@@ -1,0 +1,158 @@
+// Batched form of the Shouji filter: pairs of mixed lengths with one edit
+// threshold per pair in one pass.
+//
+// The filter's cost per pair is proportional to (windows) x (2E+1 diagonals),
+// and a wavefront filters 1024 pairs in lock step, so pairs are first grouped
+// into bins of equal E and similar length (a length bucket of `bw` bases):
+//   1. bin_count_kernel    histogram of (length bucket, E) keys
+//   2. bin_plan_kernel     offsets of the bins in a binned workspace, and a
+//                          list of tiles (<= 1024 pairs of one bin) per E class,
+//                          in decreasing cost order
+//   3. bin_scatter_kernel  copies every pair (words, length, E, original index)
+//                          to its slot in the binned workspace; pairs with an
+//                          invalid length or E get their sentinels here
+//   4. shouji_tiles_kernel the plain filter on each tile (shouji_plain.hip),
+//                          writing results back to the original pair index
+// Within a bin every pair is filtered exactly as alone: E is equal, and cells
+// beyond a pair's own length are masked to mismatches (the neighbourhood map
+// of Eq. 1 ends there), which is what the single-pair method computes.
+// Every kernel here is enqueued on the caller's stream and allocates nothing,
+// so the whole pipeline can be captured in a graph (counters are cleared with
+// a fill kernel, not a memset).
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "shouji_internal.h"
+
+namespace shouji {
+
+__device__ __forceinline__ bool pair_key(int m, int e, int max_len, int bw, int &bin, int &Ee) {
+    if (m < 0 || m > max_len || e < 0) return false;
+    Ee = e < m - 1 ? e : (m > 0 ? m - 1 : 0);
+    if (Ee > kMaxE) return false;
+    bin = ((m + bw - 1) / bw) * kBinE + Ee;
+    return true;
+}
+
+__global__ void fill_i32_kernel(int32_t *p, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void bin_count_kernel(const int32_t *__restrict__ lengths,
+                                                        const int32_t *__restrict__ Ep, int64_t n,
+                                                        int max_len, int bw, int nbins,
+                                                        int32_t *__restrict__ counts) {
+    extern __shared__ int32_t hist[];
+    for (int b = threadIdx.x; b < nbins; b += blockDim.x) hist[b] = 0;
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+        const int m = lengths ? lengths[p] : max_len;
+        int bin, Ee;
+        if (pair_key(m, Ep[p], max_len, bw, bin, Ee)) atomicAdd(&hist[bin], 1);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nbins; b += blockDim.x)
+        if (hist[b]) atomicAdd(&counts[b], hist[b]);
+}
+
+// One workgroup of kPlanThreads threads.
+//  offsets[b]  first slot of bin b in the binned workspace (bins in index order)
+//  cursors[b]  = offsets[b], advanced by the scatter
+//  tiles[c]    tile list of E class c (Ee <= class_bound[c]), longest first
+//  ntiles[c]   number of tiles of class c
+__global__ __launch_bounds__(kPlanThreads) void bin_plan_kernel(
+    const int32_t *__restrict__ counts, int nbins, int nbucket_len, PlanOut out) {
+    __shared__ int64_t part[kPlanThreads];
+    __shared__ int32_t npos[kCostBuckets * kEClasses];
+    __shared__ int32_t tpos[kCostBuckets * kEClasses];
+    const int tid = threadIdx.x;
+    const int per = (nbins + kPlanThreads - 1) / kPlanThreads;
+    const int lo = tid * per, hi = min(lo + per, nbins);
+
+    // exclusive scan of the bin counts
+    int64_t s = 0;
+    for (int b = lo; b < hi; b++) s += counts[b];
+    part[tid] = s;
+    __syncthreads();
+    for (int off = 1; off < kPlanThreads; off <<= 1) {
+        const int64_t v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int64_t run = part[tid] - s;
+    for (int b = lo; b < hi; b++) {
+        out.offsets[b] = run;
+        out.cursors[b] = run;
+        run += counts[b];
+    }
+
+    // tiles per (cost bucket, E class): cost = length buckets x (2E+1), bucketed
+    // by its bit length so that dispatch order is roughly longest first
+    for (int i = tid; i < kCostBuckets * kEClasses; i += kPlanThreads) npos[i] = 0;
+    __syncthreads();
+    for (int b = lo; b < hi; b++) {
+        const int c = counts[b];
+        if (!c) continue;
+        const int Ee = b % kBinE, mb = b / kBinE;
+        const int cls = Ee <= kEClassBound0 ? 0 : 1;
+        const uint32_t cost = (uint32_t)(mb + 1) * (uint32_t)(2 * Ee + 1);
+        const int cb = kCostBuckets - 1 - min(kCostBuckets - 1, 31 - __builtin_clz(cost));
+        atomicAdd(&npos[cls * kCostBuckets + cb], (c + kPairsPerWave - 1) / kPairsPerWave);
+    }
+    __syncthreads();
+    if (tid < kEClasses) {
+        int32_t acc = 0;
+        for (int cb = 0; cb < kCostBuckets; cb++) {
+            const int32_t v = npos[tid * kCostBuckets + cb];
+            tpos[tid * kCostBuckets + cb] = acc;
+            acc += v;
+        }
+        out.ntiles[tid] = acc;
+    }
+    __syncthreads();
+    for (int b = lo; b < hi; b++) {
+        const int c = counts[b];
+        if (!c) continue;
+        const int Ee = b % kBinE, mb = b / kBinE;
+        const int cls = Ee <= kEClassBound0 ? 0 : 1;
+        const uint32_t cost = (uint32_t)(mb + 1) * (uint32_t)(2 * Ee + 1);
+        const int cb = kCostBuckets - 1 - min(kCostBuckets - 1, 31 - __builtin_clz(cost));
+        const int nt = (c + kPairsPerWave - 1) / kPairsPerWave;
+        const int t0 = atomicAdd(&tpos[cls * kCostBuckets + cb], nt);
+        int4 *tl = out.tiles[cls];
+        for (int i = 0; i < nt; i++) {
+            const int cnt = min(kPairsPerWave, c - i * kPairsPerWave);
+            tl[t0 + i] = make_int4((int)(out.offsets[b] + (int64_t)i * kPairsPerWave), cnt, Ee, 0);
+        }
+    }
+    (void)nbucket_len;
+}
+
+__global__ __launch_bounds__(256) void bin_scatter_kernel(ScatterParams prm) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < prm.n; p += stride) {
+        const int m = prm.lengths ? prm.lengths[p] : prm.max_len;
+        const int e = prm.Ep[p];
+        int bin, Ee;
+        if (!pair_key(m, e, prm.max_len, prm.bw, bin, Ee)) {
+            prm.out_accept[p] = 0xFF;
+            if (prm.out_popcount) prm.out_popcount[p] = -1;
+            continue;
+        }
+        const int64_t dst = (int64_t)atomicAdd((unsigned long long *)&prm.cursors[bin], 1ull);
+        prm.bperm[dst] = p;
+        prm.blens[dst] = m;
+        prm.bE[dst] = e;
+        const int nw = (m + kHalf - 1) / kHalf;
+        for (int w = 0; w < nw; w++) {
+            prm.breads[(int64_t)w * prm.bld + dst] = prm.reads[(int64_t)w * prm.ld + p];
+            prm.brefs[(int64_t)w * prm.bld + dst] = prm.refs[(int64_t)w * prm.ld + p];
+        }
+    }
+}
+
+}  // namespace shouji

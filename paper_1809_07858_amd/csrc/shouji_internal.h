@@ -32,6 +32,103 @@ struct PlainParams {
     int32_t lds_wave_bytes;  // LDS bytes owned by one wavefront
 };
 
+// ---- batched form
+constexpr int kMaxE = 31;                     // largest E (after clamping to m-1)
+constexpr int kBinE = kMaxE + 1;              // E values per length bucket
+constexpr int kPlanThreads = 1024;
+constexpr int kCostBuckets = 16;
+constexpr int kEClasses = 2;                  // tiles launched per E class
+constexpr int kEClassBound0 = 12;             // class 0: Ee <= 12 (two wavefronts per SIMD fit)
+constexpr int kMinBinWidth = 4;
+
+struct PlanOut {
+    int64_t *offsets;
+    int64_t *cursors;
+    int4 *tiles[kEClasses];
+    int32_t *ntiles;          // kEClasses counts
+};
+
+struct ScatterParams {
+    const uint32_t *reads;
+    const uint32_t *refs;
+    int64_t ld;
+    const int32_t *lengths;
+    const int32_t *Ep;
+    int64_t n;
+    int32_t max_len;
+    int32_t bw;
+    int64_t *cursors;
+    int64_t *bperm;
+    int32_t *blens;
+    int32_t *bE;
+    uint32_t *breads;
+    uint32_t *brefs;
+    int64_t bld;
+    uint8_t *out_accept;
+    int16_t *out_popcount;
+};
+
+// Byte offsets of the batched workspace regions (each 256-byte aligned).
+struct BatchedLayout {
+    size_t breads, brefs, blens, bE, bperm, counts, offsets, cursors, tiles[kEClasses], ntiles, total;
+    int nbins, nw;
+    int64_t max_tiles;
+};
+inline BatchedLayout batched_layout(int64_t n, int max_len, int bw) {
+    BatchedLayout L;
+    L.nw = (max_len + kHalf - 1) / kHalf;
+    L.nbins = ((max_len + bw - 1) / bw + 1) * kBinE;
+    L.max_tiles = L.nbins + (n + kPairsPerWave - 1) / kPairsPerWave;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; };
+    L.breads = take((size_t)L.nw * n * 4);
+    L.brefs = take((size_t)L.nw * n * 4);
+    L.blens = take((size_t)n * 4);
+    L.bE = take((size_t)n * 4);
+    L.bperm = take((size_t)n * 8);
+    L.counts = take((size_t)L.nbins * 4);
+    L.offsets = take((size_t)L.nbins * 8);
+    L.cursors = take((size_t)L.nbins * 8);
+    for (int c = 0; c < kEClasses; c++) L.tiles[c] = take((size_t)L.max_tiles * 16);
+    L.ntiles = take(kEClasses * 4);
+    L.total = off;
+    return L;
+}
+
+// One group of up to 1024 pairs [base, min(base+1024, n)) for filter_group.
+struct GroupJob {
+    const uint32_t *reads;
+    const uint32_t *refs;
+    int64_t ld;
+    const int32_t *lengths;   // or null: every pair has max_len bases
+    int32_t max_len;
+    int32_t Ee;               // diagonals built on each side
+    int32_t E;                // decision threshold when Edec is null
+    const int32_t *Edec;      // per-pair decision thresholds, or null
+    const int64_t *perm;      // output index of each pair, or null (identity)
+    uint8_t *out_accept;
+    int16_t *out_popcount;
+    int64_t base;
+    int64_t n;
+};
+
+struct TilesParams {
+    const uint32_t *breads;   // binned words, word-major with leading dimension ld
+    const uint32_t *brefs;
+    int64_t ld;
+    const int32_t *blens;
+    const int32_t *bE;
+    const int64_t *bperm;
+    const int4 *tiles;        // start, count, Ee, unused
+    const int32_t *ntiles;    // device count of valid tiles
+    int32_t max_len;
+    int32_t R;
+    int32_t lds_wave_bytes;
+    int32_t waves_per_group;
+    uint8_t *out_accept;
+    int16_t *out_popcount;
+};
+
 // Pattern ring slots.  Iteration j reads pattern positions [16j-Ee, 16j+18+Ee]
 // (both lane halves).  After its searches the word that iteration j+1 first
 // needs, word j+1+H0 with H0 = (18+Ee)/16, is written; it must not overwrite
@@ -47,5 +144,11 @@ inline size_t plain_lds_wave_bytes(int Ee) {
 }
 
 __global__ void shouji_plain_kernel(PlainParams prm);
+__global__ void shouji_tiles_kernel(TilesParams prm);
+__global__ void fill_i32_kernel(int32_t *p, int64_t n, int32_t v);
+__global__ void bin_count_kernel(const int32_t *lengths, const int32_t *Ep, int64_t n, int max_len,
+                                 int bw, int nbins, int32_t *counts);
+__global__ void bin_plan_kernel(const int32_t *counts, int nbins, int nbucket_len, PlanOut out);
+__global__ void bin_scatter_kernel(ScatterParams prm);
 
 }  // namespace shouji

@@ -317,21 +317,15 @@ __device__ __forceinline__ uint32_t from_half1(uint32_t v) {
 // block 2j, the 3-plane state S[i..i+2] moves to the high half with one lane
 // swap per plane, the high half updates block 2j+1 and hands the state back.
 // Both halves read one pattern ring in LDS.
-__global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_plain_kernel(PlainParams prm) {
-    extern __shared__ uint32_t lds_all[];
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x / kWave;
+__device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, int R, int lane) {
     const int half = lane >> 5;
     const int pl = lane & (kPairLanes - 1);
-    const int R = prm.R;
-    const int Ee = prm.Ee;
+    const int Ee = J.Ee;
     const int nmask = kCols + Ee;                      // mask entries per lane
-    uint32_t *lds = lds_all + (size_t)wave * (prm.lds_wave_bytes / 4);
     uint2 *ring = reinterpret_cast<uint2 *>(lds);
     uint32_t *nv = lds + (R + kMirror) * kRingStride * 2;
-    const int64_t base = ((int64_t)blockIdx.x * kWavesPerGroup + wave) * kPairsPerWave;
-    const int64_t n = prm.n;
-    if (base >= n) return;
+    const int64_t base = J.base;
+    const int64_t n = J.n;
     const bool full = base + kPairsPerWave <= n;
 
     // ---- lengths: effective length per pair (0 for padding and invalid pairs),
@@ -339,24 +333,24 @@ __global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_plain_kernel
     uint32_t lenw[32];
     int lmin = 0x7fffffff, lmax = -1;
     {
-        const int32_t *lp = prm.lengths ? prm.lengths + base + pl : nullptr;
+        const int32_t *lp = J.lengths ? J.lengths + base + pl : nullptr;
 #pragma unroll
         for (int k = 0; k < 32; k++) {
-            int m = prm.max_len;
+            int m = J.max_len;
             const bool in = full || (base + (int64_t)k * kPairLanes + pl < n);
             if (lp) m = in ? lp[k * kPairLanes] : -1;
-            const bool ok = in && m >= 0 && m <= prm.max_len;
+            const bool ok = in && m >= 0 && m <= J.max_len;
             lenw[k] = ok ? ((uint32_t)m | (1u << kLenBits)) : 0u;
             if (ok) { lmin = min(lmin, m); lmax = max(lmax, m); }
         }
     }
     // the first words do not depend on the lengths: load them before waiting
-    const int nwords = (prm.max_len + kHalf - 1) / kHalf;
+    const int nwords = (J.max_len + kHalf - 1) / kHalf;
     uint32_t raw0[32];
     {
         const int w = 0;
         if (w < nwords) {
-            const uint32_t *row = (half ? prm.refs : prm.reads) + base;
+            const uint32_t *row = (half ? J.refs : J.reads) + base;
             load_word(row, full, n - base, pl, raw0);
         } else {
 #pragma unroll
@@ -411,7 +405,7 @@ __global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_plain_kernel
     auto pass_load = [&](int pw, int tw, int limit, uint32_t (&raw)[32]) {
         const int w = half ? tw : pw;
         if (w >= 0 && w < limit) {
-            const uint32_t *row = (half ? prm.refs : prm.reads) + (int64_t)w * prm.ld + base;
+            const uint32_t *row = (half ? J.refs : J.reads) + (int64_t)w * J.ld + base;
             load_word(row, full, n - base, pl, raw);
         } else {
 #pragma unroll
@@ -518,11 +512,10 @@ __global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_plain_kernel
     for (int b = 11; b < 32; b++) cnt[b] = (b >= 16 && b <= 16 + kLenBits) ? Lb[b - 16] : 0u;
     transpose32(cnt);  // cnt[k]: ones of S over windows [0, 8*nblocks) | length << 16 | valid << 27
     const int nwin = nblocks * kBlock;
-    uint8_t *oa = prm.out_accept + base + pl;
-    int16_t *op = prm.out_popcount ? prm.out_popcount + base + pl : nullptr;
 #pragma unroll
     for (int k = 0; k < 32; k++) {
-        if (!full && base + (int64_t)k * kPairLanes + pl >= n) continue;
+        const int64_t p = base + (int64_t)k * kPairLanes + pl;
+        if (!full && p >= n) continue;
         const uint32_t w = cnt[k];
         const int m = (int)((w >> 16) & ((1u << kLenBits) - 1));
         uint8_t acc;
@@ -533,12 +526,64 @@ __global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_plain_kernel
         } else {
             // S stays 1 on [m, nwin): those ones are not part of the pair
             const int ones = (int)(w & 0xFFFFu) - (nwin - m);
-            acc = ones <= prm.E ? 1 : 0;
+            const int E = J.Edec ? J.Edec[p] : J.E;
+            acc = ones <= E ? 1 : 0;
             pc = (int16_t)ones;
         }
-        oa[k * kPairLanes] = acc;
-        if (op) op[k * kPairLanes] = pc;
+        const int64_t o = J.perm ? J.perm[p] : p;
+        J.out_accept[o] = acc;
+        if (J.out_popcount) J.out_popcount[o] = pc;
     }
+}
+
+__global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_plain_kernel(PlainParams prm) {
+    extern __shared__ uint32_t lds_all[];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    GroupJob J;
+    J.reads = prm.reads;
+    J.refs = prm.refs;
+    J.ld = prm.ld;
+    J.lengths = prm.lengths;
+    J.max_len = prm.max_len;
+    J.Ee = prm.Ee;
+    J.E = prm.E;
+    J.Edec = nullptr;
+    J.perm = nullptr;
+    J.out_accept = prm.out_accept;
+    J.out_popcount = prm.out_popcount;
+    J.base = ((int64_t)blockIdx.x * kWavesPerGroup + wave) * kPairsPerWave;
+    J.n = prm.n;
+    if (J.base >= J.n) return;
+    filter_group(J, lds_all + (size_t)wave * (prm.lds_wave_bytes / 4), prm.R, lane);
+}
+
+// Batched form: one wavefront per tile of at most 1024 pairs of one bin of
+// the binned workspace (equal E, lengths within one bucket).  Tiles are
+// listed in decreasing cost, so the hardware's in-order dispatch hands the
+// longest work out first.
+__global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_tiles_kernel(TilesParams prm) {
+    extern __shared__ uint32_t lds_all[];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int64_t t = (int64_t)blockIdx.x * prm.waves_per_group + wave;
+    if (wave >= prm.waves_per_group || t >= *prm.ntiles) return;
+    const int4 tile = prm.tiles[t];                      // start, count, Ee, -
+    GroupJob J;
+    J.reads = prm.breads;
+    J.refs = prm.brefs;
+    J.ld = prm.ld;
+    J.lengths = prm.blens;
+    J.max_len = prm.max_len;
+    J.Ee = tile.z;
+    J.E = 0;
+    J.Edec = prm.bE;
+    J.perm = prm.bperm;
+    J.out_accept = prm.out_accept;
+    J.out_popcount = prm.out_popcount;
+    J.base = tile.x;
+    J.n = (int64_t)tile.x + tile.y;
+    filter_group(J, lds_all + (size_t)wave * (prm.lds_wave_bytes / 4), prm.R, lane);
 }
 
 }  // namespace shouji
