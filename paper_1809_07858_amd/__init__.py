@@ -60,21 +60,49 @@ def nwords(max_len):
     return (int(max_len) + BASES_PER_WORD - 1) // BASES_PER_WORD
 
 
-def pack_words(codes, max_len=None, ld=None):
-    """Base codes [n, stride] (uint8 0..3) -> packed words [nwords, ld] (int32 bit patterns)."""
-    codes = np.ascontiguousarray(codes, dtype=np.uint8)
+def pack_words(codes, max_len=None, ld=None, chunk=1 << 18):
+    """Base codes [n, stride] (uint8 0..3) -> packed words [nwords, ld] (int32 bit patterns).
+
+    Word w of pair p holds bases 16w..16w+15 of row p, base j in bits 2(j%16)..2(j%16)+1.
+    """
+    codes = np.asarray(codes)
     n, stride = codes.shape
     max_len = stride if max_len is None else int(max_len)
     nw = nwords(max_len)
     ld = n if ld is None else int(ld)
-    buf = np.zeros((n, nw * BASES_PER_WORD), dtype=np.uint32)
-    w = min(stride, nw * BASES_PER_WORD)
-    buf[:, :w] = codes[:, :w] & 3
-    shifts = (2 * np.arange(BASES_PER_WORD, dtype=np.uint32))
-    words = (buf.reshape(n, nw, BASES_PER_WORD) << shifts).sum(axis=2, dtype=np.uint64).astype(np.uint32)
     out = np.zeros((nw, ld), dtype=np.uint32)
-    out[:, :n] = words.T
+    w = min(stride, nw * BASES_PER_WORD)
+    shifts = (2 * np.arange(BASES_PER_WORD, dtype=np.uint32))
+    for lo in range(0, n, chunk):
+        hi = min(n, lo + chunk)
+        buf = np.zeros((hi - lo, nw * BASES_PER_WORD), dtype=np.uint32)
+        buf[:, :w] = codes[lo:hi, :w] & 3
+        words = np.bitwise_or.reduce(buf.reshape(hi - lo, nw, BASES_PER_WORD) << shifts, axis=2)
+        out[:, lo:hi] = words.T
     return out.view(np.int32)
+
+
+def pack_words_device(codes, max_len=None, ld=None, chunk=1 << 20):
+    """Same layout as pack_words, computed on the GPU from a uint8 code tensor [n, stride]
+    (host or device).  Returns an int32 CUDA tensor [nwords, ld]."""
+    import torch
+    n, stride = codes.shape
+    max_len = stride if max_len is None else int(max_len)
+    nw = nwords(max_len)
+    ld = n if ld is None else int(ld)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    out = torch.zeros((nw, ld), dtype=torch.int32, device=dev)
+    w = min(stride, nw * BASES_PER_WORD)
+    shifts = (2 * torch.arange(BASES_PER_WORD, dtype=torch.int64, device=dev))
+    for lo in range(0, n, chunk):
+        hi = min(n, lo + chunk)
+        c = torch.as_tensor(codes[lo:hi, :w]).to(dev, non_blocking=False).to(torch.int64) & 3
+        buf = torch.zeros((hi - lo, nw * BASES_PER_WORD), dtype=torch.int64, device=dev)
+        buf[:, :w] = c
+        words = (buf.view(hi - lo, nw, BASES_PER_WORD) << shifts).sum(dim=2)
+        words = torch.where(words >= 2 ** 31, words - 2 ** 32, words)
+        out[:, lo:hi] = words.to(torch.int32).t()
+    return out
 
 
 def _stream_handle(stream):

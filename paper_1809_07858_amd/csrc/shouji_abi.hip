@@ -35,14 +35,16 @@ extern "C" const char *shouji_last_error(void) { return g_err; }
 
 namespace {
 
-// Raise the dynamic LDS limit of a kernel once per process.
-int raise_lds_limit(const void *kernel, bool &done) {
-    if (done) return SHOUJI_OK;
-    if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)shouji::kLdsPerCU) != hipSuccess)
-        return fail(SHOUJI_ERR_DEVICE, "cannot raise the LDS limit: %s",
+// Raise the dynamic LDS limit of a kernel to at least `bytes` (the largest
+// limit set so far is remembered per kernel in `limit`).
+std::mutex g_attr_mu;
+int raise_lds_limit(const void *kernel, size_t &limit, size_t bytes) {
+    std::lock_guard<std::mutex> g(g_attr_mu);
+    if (bytes <= limit) return SHOUJI_OK;
+    if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
+        return fail(SHOUJI_ERR_DEVICE, "cannot raise the LDS limit to %zu bytes: %s", bytes,
                     hipGetErrorString(hipGetLastError()));
-    done = true;
+    limit = bytes;
     return SHOUJI_OK;
 }
 
@@ -86,8 +88,8 @@ extern "C" int shouji_filter(const uint32_t *reads, const uint32_t *refs, const 
     const int64_t grid = (waves + shouji::kWavesPerGroup - 1) / shouji::kWavesPerGroup;
     if (grid > 0x7fffffff) return fail(SHOUJI_ERR_ARG, "n_pairs too large");
     prm.lds_wave_bytes = (int32_t)wave_lds;
-    static bool attr_set = false;
-    if (int rc = raise_lds_limit((const void *)shouji::shouji_plain_kernel, attr_set)) return rc;
+    static size_t lds_limit = 0;
+    if (int rc = raise_lds_limit((const void *)shouji::shouji_plain_kernel, lds_limit, lds)) return rc;
     hipLaunchKernelGGL(shouji::shouji_plain_kernel, dim3((unsigned)grid),
                        dim3(shouji::kWave * shouji::kWavesPerGroup), lds, (hipStream_t)stream, prm);
     const hipError_t e = hipGetLastError();
@@ -205,14 +207,22 @@ extern "C" int shouji_filter_batched(const uint32_t *reads, const uint32_t *refs
     sp.bld = n_pairs;
     sp.out_accept = out_accept;
     sp.out_popcount = out_popcount;
-    {
+    sp.nbins = L.nbins;
+    if (L.nbins <= shouji::kScatterMaxBins) {
+        static size_t slimit = 0;
+        if (int rc = raise_lds_limit((const void *)shouji::bin_scatter_lds_kernel, slimit,
+                                     shouji::scatter_lds_bytes(L.nbins)))
+            return rc;
+        const int64_t chunks = (n_pairs + shouji::kScatterChunk - 1) / shouji::kScatterChunk;
+        hipLaunchKernelGGL(shouji::bin_scatter_lds_kernel, dim3((unsigned)chunks),
+                           dim3(shouji::kScatterThreads), shouji::scatter_lds_bytes(L.nbins), st, sp);
+    } else {
         const int64_t blocks = (n_pairs + 255) / 256;
         hipLaunchKernelGGL(shouji::bin_scatter_kernel, dim3((unsigned)(blocks < 8192 ? blocks : 8192)),
                            dim3(256), 0, st, sp);
     }
     // 4. the filter over the tiles, largest E class first
-    static bool attr_set = false;
-    if (int rc = raise_lds_limit((const void *)shouji::shouji_tiles_kernel, attr_set)) return rc;
+    static size_t tlimit = 0;
     const int Emax_len = max_len > 0 ? max_len - 1 : 0;
     for (int c = shouji::kEClasses - 1; c >= 0; c--) {
         int Ecls = c == 0 ? shouji::kEClassBound0 : shouji::kMaxE;
@@ -235,6 +245,8 @@ extern "C" int shouji_filter_batched(const uint32_t *reads, const uint32_t *refs
         if (wave_lds * wpg > shouji::kLdsPerCU) return fail(SHOUJI_ERR_RANGE, "LDS too small for E %d", Ecls);
         tp.lds_wave_bytes = (int32_t)wave_lds;
         tp.waves_per_group = wpg;
+        if (int rc = raise_lds_limit((const void *)shouji::shouji_tiles_kernel, tlimit, wave_lds * wpg))
+            return rc;
         tp.out_accept = out_accept;
         tp.out_popcount = out_popcount;
         const int64_t grid = (L.max_tiles + wpg - 1) / wpg;

@@ -155,4 +155,107 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(ScatterParams prm) {
     }
 }
 
+// Scatter staged through LDS.  A workgroup takes a chunk of kScatterChunk
+// consecutive pairs, reserves one run per bin in the binned workspace (one
+// global atomic per bin and chunk), ranks its pairs by bin in LDS, and then
+// writes every word row, the lengths, thresholds and original indices in
+// slot order, so consecutive threads write consecutive slots of a run.
+// Reads of the input rows stay coalesced.  Needs nbins <= kScatterMaxBins.
+__global__ __launch_bounds__(kScatterThreads) void bin_scatter_lds_kernel(ScatterParams prm) {
+    extern __shared__ int32_t sm[];
+    const int nbins = prm.nbins;
+    int32_t *cnt = sm;                                         // counts, then cursors
+    int32_t *loff = cnt + nbins;                               // local run offsets
+    int64_t *gbase = reinterpret_cast<int64_t *>(loff + nbins + (nbins & 1));
+    uint16_t *slotbin = reinterpret_cast<uint16_t *>(gbase + nbins);
+    uint16_t *slotsrc = slotbin + kScatterChunk;
+    uint32_t *buf = reinterpret_cast<uint32_t *>(slotsrc + kScatterChunk);
+    __shared__ int32_t part[kScatterThreads];
+    const int tid = threadIdx.x;
+    const int64_t c0 = (int64_t)blockIdx.x * kScatterChunk;
+    constexpr int PER = kScatterChunk / kScatterThreads;
+
+    for (int b = tid; b < nbins; b += kScatterThreads) cnt[b] = 0;
+    __syncthreads();
+    int bin[PER];
+#pragma unroll
+    for (int i = 0; i < PER; i++) {
+        const int64_t p = c0 + tid + (int64_t)i * kScatterThreads;
+        bin[i] = -1;
+        if (p >= prm.n) continue;
+        const int m = prm.lengths ? prm.lengths[p] : prm.max_len;
+        int b, Ee;
+        if (pair_key(m, prm.Ep[p], prm.max_len, prm.bw, b, Ee)) {
+            bin[i] = b;
+            atomicAdd(&cnt[b], 1);
+        } else {
+            prm.out_accept[p] = 0xFF;
+            if (prm.out_popcount) prm.out_popcount[p] = -1;
+        }
+    }
+    __syncthreads();
+    // reserve runs; exclusive scan of the counts over the bins
+    const int per = (nbins + kScatterThreads - 1) / kScatterThreads;
+    const int lo = tid * per, hi = min(lo + per, nbins);
+    int32_t s = 0;
+    for (int b = lo; b < hi; b++) {
+        const int32_t c = cnt[b];
+        if (c) gbase[b] = (int64_t)atomicAdd((unsigned long long *)&prm.cursors[b], (unsigned long long)c);
+        s += c;
+    }
+    part[tid] = s;
+    __syncthreads();
+    for (int off = 1; off < kScatterThreads; off <<= 1) {
+        const int32_t v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int32_t run = part[tid] - s;
+    for (int b = lo; b < hi; b++) {
+        loff[b] = run;
+        const int32_t c = cnt[b];
+        cnt[b] = run;                                          // becomes the slot cursor
+        run += c;
+    }
+    __syncthreads();
+    const int nvalid = part[kScatterThreads - 1];
+    int slot[PER];
+#pragma unroll
+    for (int i = 0; i < PER; i++) {
+        slot[i] = -1;
+        if (bin[i] < 0) continue;
+        slot[i] = atomicAdd(&cnt[bin[i]], 1);
+        slotbin[slot[i]] = (uint16_t)bin[i];
+        slotsrc[slot[i]] = (uint16_t)(tid + i * kScatterThreads);
+    }
+    __syncthreads();
+    // per-pair metadata, in slot order
+    for (int q = tid; q < nvalid; q += kScatterThreads) {
+        const int b = slotbin[q];
+        const int64_t dst = gbase[b] + (q - loff[b]);
+        const int64_t src = c0 + slotsrc[q];
+        prm.bperm[dst] = src;
+        prm.blens[dst] = prm.lengths ? prm.lengths[src] : prm.max_len;
+        prm.bE[dst] = prm.Ep[src];
+    }
+    // word rows, one at a time through the LDS buffer
+    const int nw = (prm.max_len + kHalf - 1) / kHalf;
+    for (int seq = 0; seq < 2; seq++) {
+        const uint32_t *in = seq ? prm.refs : prm.reads;
+        uint32_t *outp = seq ? prm.brefs : prm.breads;
+        for (int w = 0; w < nw; w++) {
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < PER; i++)
+                if (slot[i] >= 0) buf[slot[i]] = in[(int64_t)w * prm.ld + c0 + tid + (int64_t)i * kScatterThreads];
+            __syncthreads();
+            for (int q = tid; q < nvalid; q += kScatterThreads) {
+                const int b = slotbin[q];
+                outp[(int64_t)w * prm.bld + gbase[b] + (q - loff[b])] = buf[q];
+            }
+        }
+    }
+}
+
 }  // namespace shouji

@@ -40,6 +40,12 @@ constexpr int kCostBuckets = 16;
 constexpr int kEClasses = 2;                  // tiles launched per E class
 constexpr int kEClassBound0 = 12;             // class 0: Ee <= 12 (two wavefronts per SIMD fit)
 constexpr int kMinBinWidth = 4;
+constexpr int kScatterChunk = 8192;           // pairs per workgroup of the staged scatter
+constexpr int kScatterThreads = 1024;
+constexpr int kScatterMaxBins = 4128;         // LDS tables of the staged scatter
+inline size_t scatter_lds_bytes(int nbins) {
+    return (size_t)nbins * 4 * 2 + 8 + (size_t)nbins * 8 + (size_t)kScatterChunk * (2 + 2 + 4);
+}
 
 struct PlanOut {
     int64_t *offsets;
@@ -66,6 +72,7 @@ struct ScatterParams {
     int64_t bld;
     uint8_t *out_accept;
     int16_t *out_popcount;
+    int32_t nbins;
 };
 
 // Byte offsets of the batched workspace regions (each 256-byte aligned).
@@ -150,5 +157,6 @@ __global__ void bin_count_kernel(const int32_t *lengths, const int32_t *Ep, int6
                                  int bw, int nbins, int32_t *counts);
 __global__ void bin_plan_kernel(const int32_t *counts, int nbins, int nbucket_len, PlanOut out);
 __global__ void bin_scatter_kernel(ScatterParams prm);
+__global__ void bin_scatter_lds_kernel(ScatterParams prm);
 
 }  // namespace shouji
