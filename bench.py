@@ -100,6 +100,11 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-form leg (mixed lengths, per-pair E)")
     ap.add_argument("--batched-n", type=int, default=8_000_000)
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving leg (Poisson request stream through the server)")
+    ap.add_argument("--serving-pairs", type=int, default=40_000_000)
+    ap.add_argument("--serving-batch", type=int, default=1 << 19)
+    ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -215,6 +220,9 @@ def main():
         out["parity_sample"] = ns
     if not args.no_batched:
         out["batched"] = bench_batched(args.batched_n, dev)
+    if not args.no_serving:
+        out["serving"] = bench_serving(dev, args.serving_pairs, args.serving_batch,
+                                       args.serving_slots, with_oracle=not args.no_cpu)
     print(json.dumps(out), flush=True)
 
 
@@ -301,6 +309,158 @@ def bench_batched(n, dev, steps=20):
             "plain_per_group_value": n / (plain_ms / 1e3), "plain_groups": len(groups),
             "plain_ms": plain_ms, "vs_plain": plain_ms / ms, "mismatches_vs_plain": same,
             "accept_rate": float(acc.float().mean().item())}
+
+
+def bench_serving(dev, total_pairs, batch_pairs, slots, distinct=1_000_000, load=0.8,
+                  with_oracle=True, seed=4000):
+    """Serving form: a Poisson stream of requests through the request server.
+
+    Requests hold U{1..200000} pairs (about total_pairs in all), lengths uniform
+    in 64..300, E_p = floor(r*m) with r uniform in [0, 0.10], 20% unrelated
+    pairs.  The references sit in a 2 GiB device-resident packed pool (8 Gi
+    bases: random bases around a region holding the generated reference
+    segments); a request's pairs are a contiguous run of `distinct` generated
+    pairs.  First the whole stream is submitted at once (peak pairs/s), then it
+    is replayed with Poisson arrivals at `load` x that peak; latency = submit to
+    results in the caller's host buffers.  Every served result is compared with
+    the batched form run on the same pairs resident on the device."""
+    import threading
+    import numpy as np
+    import torch
+    import paper_1809_07858_amd as sj
+    import syninput
+    max_len = 300
+    t0 = time.time()
+    pairs = syninput.generate(distinct, 64, max_len, E=None, r_max=0.10, seed=seed)
+    codes, off = syninput.reference_pool(pairs, seed=seed + 1)
+    region = sj.pack_pool(codes)
+    del codes
+    pool_words = 1 << 29
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed + 2)
+    pool = torch.empty(pool_words, dtype=torch.int32, device=dev)
+    chunk = 1 << 26
+    for lo in range(0, pool_words, chunk):
+        r = torch.randint(0, 1 << 32, (chunk,), dtype=torch.int64, device=dev, generator=gen)
+        pool[lo:lo + chunk] = (r - (1 << 31)).to(torch.int32)
+    rng = np.random.default_rng(seed + 3)
+    r0 = int(rng.integers(0, pool_words - region.size))
+    pool[r0:r0 + region.size] = torch.from_numpy(region.view(np.int32)).to(dev)
+    offsets = off + 16 * r0
+    reads = sj.pack_pairs(pairs.P, max_len)
+    lens, Ep = pairs.lengths, pairs.E
+
+    # the batched form on the same pairs, device-resident: expected results, and
+    # the autotuned config for full batches
+    rd = sj.pack_words_device(pairs.P, max_len)
+    rf = sj.pack_words_device(pairs.T, max_len)
+    Ld = torch.from_numpy(lens).to(dev)
+    Ed = torch.from_numpy(Ep).to(dev)
+    b = min(batch_pairs, distinct)
+    sj.tune_batched(rd[:, :b].contiguous(), rf[:, :b].contiguous(), Ld[:b].contiguous(),
+                    Ed[:b].contiguous(), max_len=max_len)
+    ref_acc, ref_pc = sj.shouji_filter_batched(rd, rf, Ld, Ed, max_len=max_len)
+    torch.cuda.synchronize()
+    ref_acc, ref_pc = ref_acc.cpu().numpy(), ref_pc.cpu().numpy()
+    del rd, rf
+    oracle_bad = None
+    if with_oracle:
+        import oracle
+        ns = 20_000
+        ea, ep = oracle.shouji_batch(pairs.P[:ns], pairs.T[:ns], lens[:ns], E_per_pair=Ep[:ns])
+        oracle_bad = int(((ea != ref_acc[:ns]) | (ep != ref_pc[:ns])).sum())
+    del pairs
+
+    sizes = []
+    while sum(sizes) < total_pairs:
+        sizes.append(int(rng.integers(1, 200_001)))
+    sizes[-1] -= sum(sizes) - total_pairs
+    if sizes[-1] <= 0:
+        sizes.pop()
+    starts = [int(rng.integers(0, distinct - s + 1)) for s in sizes]
+    setup_s = time.time() - t0
+
+    srv = sj.Server(pool, pool_words * 16, max_len, slots=slots, max_batch_pairs=batch_pairs,
+                    memory_budget=16 << 30)
+    try:
+        def submit(i):
+            a, s = starts[i], sizes[i]
+            return srv.submit(reads[a:a + s], offsets[a:a + s], lens[a:a + s], Ep[a:a + s])
+
+        for i in range(3):                        # warm-up
+            srv.wait(submit(i))
+        bad = 0
+
+        def check(i, acc, pc):
+            a, s = starts[i], sizes[i]
+            return int(((acc != ref_acc[a:a + s]) | (pc != ref_pc[a:a + s])).sum())
+
+        # peak: the whole stream at once
+        st0 = srv.stats()
+        tb = time.perf_counter()
+        tickets = [submit(i) for i in range(len(sizes))]
+        for i, t in enumerate(tickets):
+            acc, pc, _ = srv.wait(t)
+            bad += check(i, acc, pc)
+        peak_s = time.perf_counter() - tb
+        peak = total_pairs / peak_s
+        st1 = srv.stats()
+
+        # Poisson arrivals at load x peak
+        mean_size = total_pairs / len(sizes)
+        rate = load * peak / mean_size             # requests per second
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, len(sizes)))
+        lat = [None] * len(sizes)
+        sub_t = [None] * len(sizes)
+        tq = []
+        ready = threading.Condition()
+
+        def waiter():
+            for i in range(len(sizes)):
+                with ready:
+                    while len(tq) <= i:
+                        ready.wait()
+                    t = tq[i]
+                acc, pc, ms = srv.wait(t)
+                lat[i] = ms
+                nonlocal bad
+                bad += check(i, acc, pc)
+
+        wt = threading.Thread(target=waiter)
+        wt.start()
+        tp = time.perf_counter()
+        for i in range(len(sizes)):
+            d = tp + arrivals[i] - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            sub_t[i] = time.perf_counter()
+            t = submit(i)
+            with ready:
+                tq.append(t)
+                ready.notify()
+        wt.join()
+        end = max(sub_t[i] + lat[i] / 1e3 for i in range(len(sizes)))
+        poisson_s = end - sub_t[0]
+        st2 = srv.stats()
+    finally:
+        srv.close()
+    lat = np.array(lat)
+    return {"workload": "Poisson stream of %d requests, %d pairs in all, request size U{1..200000}, "
+                        "lengths uniform 64..300, E_p=floor(r*m) r~U[0,0.10], 2 GiB device-"
+                        "resident packed reference pool (8 Gi bases), seed %d"
+                        % (len(sizes), total_pairs, seed),
+            "value": total_pairs / poisson_s, "unit": "pairs/s",
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
+            "offered_pairs_per_s": load * peak, "load": load,
+            "peak_pairs_per_s": peak, "peak_s": peak_s,
+            "requests": len(sizes), "pairs": total_pairs, "distinct_pairs": distinct,
+            "batch_pairs": batch_pairs, "slots": st2["slots"],
+            "batches_peak": st1["batches"] - st0["batches"],
+            "batches_poisson": st2["batches"] - st1["batches"],
+            "deferred_poisson": st2["requests_deferred"] - st1["requests_deferred"],
+            "mismatches_vs_batched": bad, "batched_vs_oracle_sample_mismatches": oracle_bad,
+            "pool_bytes": pool_words * 4, "setup_s": setup_s}
 
 
 if __name__ == "__main__":

@@ -133,6 +133,94 @@ int shouji_tune_batched(const uint32_t *reads, const uint32_t *refs, const int32
                         int64_t workspace_bytes, void *stream, shouji_batched_config *best,
                         float *best_ms);
 
+/*
+ * Serving form: a request server with continuous batching.
+ *
+ * Same filter (Sec. 2.2, Eq. 1, Algorithm 1) served to a stream of requests
+ * of any size.  The references live in a packed pool in device memory that the
+ * caller fills once (candidate locations of a read mapper point into it); a
+ * request names, per pair, the offset of its reference segment in the pool.
+ * The server splits its device memory budget into batch slots of
+ * max_batch_pairs pairs.  Whenever a slot is free and requests are queued,
+ * it takes queued pairs in arrival order (a request may span several batches
+ * and a batch several requests), copies them to the device and runs the
+ * batched form on them on the slot's own stream; results are copied back into
+ * the request's buffers.  Each pair's result is the one shouji_filter gives
+ * that pair alone, whatever else is batched with it.
+ *
+ * Unlike the calls above, requests are HOST buffers; the pool is a device
+ * buffer.  All device and pinned host memory is allocated by
+ * shouji_server_create and released by shouji_server_destroy.  Submit, poll,
+ * wait and get_stats may be called from any thread.
+ */
+typedef struct shouji_server shouji_server;
+
+typedef struct {
+    const uint32_t *pool;    /* device: reference pool, 16 bases per word, base b in
+                                bits [2*(b%16), 2*(b%16)+1] of word b/16; owned by the
+                                caller and left unchanged while the server exists */
+    int64_t pool_bases;      /* bases in the pool (> 0)                               */
+    int32_t max_len;         /* longest pair any request holds, 1..SHOUJI_MAX_LEN     */
+    int32_t slots;           /* batches in flight at most (> 0)                       */
+    int64_t max_batch_pairs; /* pairs per batch slot (> 0)                            */
+    int64_t memory_budget;   /* device bytes the slots may take, 0 = no limit; fewer
+                                slots are made when `slots` would not fit, and
+                                SHOUJI_ERR_NOMEM is returned when not even one does   */
+    int32_t host_threads;    /* threads staging a batch into pinned memory (0: 8)     */
+} shouji_server_config;
+
+typedef struct {
+    const uint32_t *reads;      /* host, pair-major: read p in words
+                                   [p*words_per_read, (p+1)*words_per_read), packed
+                                   as the pool (base j in word j/16)                 */
+    int32_t words_per_read;     /* > 0; words beyond ceil(max_len/16) are ignored     */
+    const int64_t *ref_offsets; /* host: pool base where pair p's reference begins     */
+    const int32_t *lengths;     /* host: length m_p of read and reference              */
+    const int32_t *E;           /* host: edit threshold of pair p                      */
+    uint8_t *out_accept;        /* host: 1 accept, 0 reject, 0xFF invalid pair         */
+    int16_t *out_popcount;      /* host or NULL: ones of the Shouji bit-vector, -1 for
+                                   an invalid pair                                     */
+    int64_t n_pairs;            /* >= 0                                                */
+} shouji_request;
+
+typedef struct {
+    int32_t slots;          /* batch slots the memory budget allowed */
+    int64_t batches;        /* batches launched so far               */
+    int64_t pairs_done;     /* pairs whose results were delivered    */
+    int64_t requests_done;  /* requests completed                    */
+    int64_t requests_deferred; /* requests that found every slot busy or
+                                  pairs already queued when submitted */
+    int64_t queued_pairs;   /* pairs waiting for a slot              */
+} shouji_server_stats;
+
+/* Device bytes one batch slot of max_batch_pairs pairs of at most max_len bases
+ * takes (to size memory_budget); negative status on bad arguments. */
+int64_t shouji_server_slot_bytes(int64_t max_batch_pairs, int32_t max_len);
+
+/* Create a server on the current device.  Invalid sizes: SHOUJI_ERR_ARG or
+ * SHOUJI_ERR_RANGE; allocation failure: SHOUJI_ERR_NOMEM (nothing is leaked). */
+int shouji_server_create(const shouji_server_config *config, shouji_server **out);
+
+/* Queue a request and return its ticket.  The request's buffers are read and
+ * written by the server until shouji_server_wait returns for this ticket; the
+ * caller keeps them alive and untouched until then.  A pair whose length lies
+ * outside [0, max_len], whose segment is not inside the pool, whose E is
+ * negative or, after clamping to m-1, above SHOUJI_MAX_E gets the sentinels. */
+int shouji_server_submit(shouji_server *server, const shouji_request *request, uint64_t *ticket);
+
+/* *done = 1 when the request's results are in its buffers, else 0. */
+int shouji_server_poll(shouji_server *server, uint64_t ticket, int32_t *done);
+
+/* Block until the request is complete, return its latency (submit to results
+ * delivered) in *latency_ms (may be NULL) and forget the ticket.  A device
+ * failure in one of its batches is returned as SHOUJI_ERR_DEVICE. */
+int shouji_server_wait(shouji_server *server, uint64_t ticket, double *latency_ms);
+
+int shouji_server_get_stats(shouji_server *server, shouji_server_stats *stats);
+
+/* Finish every queued request, then release all memory.  NULL is a no-op. */
+int shouji_server_destroy(shouji_server *server);
+
 /* Text of the last non-OK status returned on this thread ("" if none). */
 const char *shouji_last_error(void);
 

@@ -28,6 +28,25 @@ class ShoujiError(RuntimeError):
         self.code = code
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("pool", ctypes.c_void_p), ("pool_bases", ctypes.c_int64), ("max_len", ctypes.c_int32),
+                ("slots", ctypes.c_int32), ("max_batch_pairs", ctypes.c_int64),
+                ("memory_budget", ctypes.c_int64), ("host_threads", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("reads", ctypes.c_void_p), ("words_per_read", ctypes.c_int32),
+                ("ref_offsets", ctypes.c_void_p), ("lengths", ctypes.c_void_p), ("E", ctypes.c_void_p),
+                ("out_accept", ctypes.c_void_p), ("out_popcount", ctypes.c_void_p),
+                ("n_pairs", ctypes.c_int64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("batches", ctypes.c_int64), ("pairs_done", ctypes.c_int64),
+                ("requests_done", ctypes.c_int64), ("requests_deferred", ctypes.c_int64),
+                ("queued_pairs", ctypes.c_int64)]
+
+
 def lib():
     """Load libshouji.so (raises if it has not been built)."""
     global _lib
@@ -45,6 +64,20 @@ def lib():
         L.shouji_filter_batched.argtypes = [vp, vp, vp, vp, vp, vp, i64, i32, i64, vp, i64, vp, vp]
         L.shouji_tune_batched.restype = ctypes.c_int
         L.shouji_tune_batched.argtypes = [vp, vp, vp, vp, vp, vp, i64, i32, i64, vp, i64, vp, vp, vp]
+        L.shouji_server_slot_bytes.restype = ctypes.c_int64
+        L.shouji_server_slot_bytes.argtypes = [i64, i32]
+        L.shouji_server_create.restype = ctypes.c_int
+        L.shouji_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
+        L.shouji_server_submit.restype = ctypes.c_int
+        L.shouji_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+        L.shouji_server_poll.restype = ctypes.c_int
+        L.shouji_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(i32)]
+        L.shouji_server_wait.restype = ctypes.c_int
+        L.shouji_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
+        L.shouji_server_get_stats.restype = ctypes.c_int
+        L.shouji_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+        L.shouji_server_destroy.restype = ctypes.c_int
+        L.shouji_server_destroy.argtypes = [vp]
         L.shouji_last_error.restype = ctypes.c_char_p
         L.shouji_version.restype = ctypes.c_int
         _lib = L
@@ -225,3 +258,112 @@ def tune_batched(reads, refs, lengths, E_per_pair, n_pairs=None, max_len=None, w
     _check(lib().shouji_tune_batched(*args, _stream_handle(stream), ctypes.byref(best),
                                      ctypes.byref(ms)))
     return (best.bin_width, best.waves_per_group), float(ms.value)
+
+
+def pack_pairs(codes, max_len=None):
+    """Base codes [n, stride] (uint8 0..3) -> pair-major packed words [n, nwords] (uint32),
+    the read layout of a server request."""
+    return np.ascontiguousarray(pack_words(codes, max_len).view(np.uint32).T)
+
+
+def pack_pool(codes):
+    """Flat base codes (uint8 0..3) -> packed pool words (uint32): base b in bits
+    2(b%16).. of word b/16, the reference-pool layout of the server."""
+    codes = np.asarray(codes, dtype=np.uint8).ravel()
+    nw = nwords(codes.size)
+    buf = np.zeros(nw * BASES_PER_WORD, dtype=np.uint32)
+    buf[:codes.size] = codes & 3
+    shifts = 2 * np.arange(BASES_PER_WORD, dtype=np.uint32)
+    return np.bitwise_or.reduce(buf.reshape(nw, BASES_PER_WORD) << shifts, axis=1)
+
+
+def server_slot_bytes(max_batch_pairs, max_len):
+    """Device bytes of one server batch slot (to size memory_budget)."""
+    v = lib().shouji_server_slot_bytes(int(max_batch_pairs), int(max_len))
+    if v < 0:
+        _check(int(v))
+    return int(v)
+
+
+class Ticket:
+    """A submitted request: keeps its host buffers alive until Server.wait returns."""
+
+    def __init__(self, tid, bufs, out_accept, out_popcount):
+        self.id = tid
+        self._bufs = bufs
+        self.out_accept = out_accept
+        self.out_popcount = out_popcount
+        self.latency_ms = None
+
+
+class Server:
+    """Request server with continuous batching (shouji_server_* in include/shouji.h).
+
+    pool: int32 CUDA tensor of packed reference words (pack_pool), resident for the
+    server's lifetime.  Requests are host numpy arrays.
+    """
+
+    def __init__(self, pool, pool_bases, max_len, slots=3, max_batch_pairs=1 << 20,
+                 memory_budget=0, host_threads=0):
+        import torch
+        if not pool.is_cuda or pool.dtype != torch.int32 or not pool.is_contiguous():
+            raise ValueError("pool must be a contiguous int32 CUDA tensor")
+        if pool.numel() < nwords(pool_bases):
+            raise ValueError("pool holds fewer words than pool_bases needs")
+        self.pool = pool
+        self.max_len = int(max_len)
+        self.nw = nwords(max_len)
+        cfg = ServerConfig(pool.data_ptr(), int(pool_bases), int(max_len), int(slots),
+                           int(max_batch_pairs), int(memory_budget), int(host_threads))
+        h = ctypes.c_void_p()
+        _check(lib().shouji_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, reads, ref_offsets, lengths, E, want_popcount=True):
+        """Queue a request.  reads: uint32 [n, words_per_read] (pack_pairs); ref_offsets int64,
+        lengths int32, E int32 (scalar or per pair).  Returns a Ticket."""
+        reads = np.ascontiguousarray(reads, dtype=np.uint32)
+        if reads.ndim != 2:
+            raise ValueError("reads must be [n_pairs, words_per_read]")
+        n = reads.shape[0]
+        offs = np.ascontiguousarray(ref_offsets, dtype=np.int64)
+        lens = np.ascontiguousarray(lengths, dtype=np.int32)
+        Ep = np.ascontiguousarray(np.broadcast_to(np.asarray(E, dtype=np.int32), (n,)))
+        if offs.shape != (n,) or lens.shape != (n,):
+            raise ValueError("ref_offsets and lengths need one entry per pair")
+        acc = np.empty(n, dtype=np.uint8)
+        pc = np.empty(n, dtype=np.int16) if want_popcount else None
+        req = Request(reads.ctypes.data, max(1, reads.shape[1]), offs.ctypes.data, lens.ctypes.data,
+                      Ep.ctypes.data, acc.ctypes.data, None if pc is None else pc.ctypes.data, n)
+        t = ctypes.c_uint64()
+        _check(lib().shouji_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
+        return Ticket(t.value, (reads, offs, lens, Ep), acc, pc)
+
+    def poll(self, ticket):
+        d = ctypes.c_int32()
+        _check(lib().shouji_server_poll(self._h, ticket.id, ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket):
+        """Block until done; returns (out_accept, out_popcount, latency_ms)."""
+        ms = ctypes.c_double()
+        _check(lib().shouji_server_wait(self._h, ticket.id, ctypes.byref(ms)))
+        ticket.latency_ms = ms.value
+        ticket._bufs = None
+        return ticket.out_accept, ticket.out_popcount, ms.value
+
+    def stats(self):
+        st = ServerStats()
+        _check(lib().shouji_server_get_stats(self._h, ctypes.byref(st)))
+        return {k: int(getattr(st, k)) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _check(lib().shouji_server_destroy(self._h))
+        self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -13,10 +13,12 @@
 #include "shouji_internal.h"
 
 namespace {
-
 thread_local char g_err[512] = "";
+}  // namespace
 
-int fail(int code, const char *fmt, ...) {
+namespace shouji {
+
+int set_error(int code, const char *fmt, ...) {
     va_list ap;
     va_start(ap, fmt);
     vsnprintf(g_err, sizeof(g_err), fmt, ap);
@@ -24,11 +26,17 @@ int fail(int code, const char *fmt, ...) {
     return code;
 }
 
-int ok() {
+int clear_error() {
     g_err[0] = '\0';
     return SHOUJI_OK;
 }
 
+}  // namespace shouji
+
+namespace {
+template <typename... A>
+inline int fail(int code, const char *fmt, A... a) { return shouji::set_error(code, fmt, a...); }
+inline int ok() { return shouji::clear_error(); }
 }  // namespace
 
 extern "C" const char *shouji_last_error(void) { return g_err; }

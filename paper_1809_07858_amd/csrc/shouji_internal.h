@@ -159,4 +159,8 @@ __global__ void bin_plan_kernel(const int32_t *counts, int nbins, int nbucket_le
 __global__ void bin_scatter_kernel(ScatterParams prm);
 __global__ void bin_scatter_lds_kernel(ScatterParams prm);
 
+// Thread-local error text behind shouji_last_error (printf-style format).
+int set_error(int code, const char *fmt, ...);
+int clear_error();
+
 }  // namespace shouji

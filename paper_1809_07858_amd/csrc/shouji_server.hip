@@ -1,0 +1,488 @@
+// Serving form of the Shouji filter: a request server with continuous batching.
+//
+// A request is a set of pairs held in host memory: reads (2-bit packed,
+// pair-major), for each pair the offset of its reference segment in a packed
+// reference pool that stays resident in device memory, its length and its
+// edit threshold.  The device memory budget is cut into batch slots of a fixed
+// pair capacity.  A scheduler thread fills a free slot with the parts of the
+// queued requests, in arrival order, as soon as one is free (a large request
+// spreads over several batches, small ones share a batch) and enqueues the
+// batch on the slot's own stream: host-to-device copies, relayout of the
+// reads, extraction of the reference segments from the pool, the batched
+// filter, copies back.  A completion thread waits for the batches in launch
+// order and hands the results to the requests.  Copies and filtering of
+// different batches overlap, and requests that arrive meanwhile go into the
+// next free slot.  Each pair is filtered exactly as alone (the batched form
+// guarantees it), so a request's results never depend on its batch mates.
+//
+// All device and pinned host memory is allocated in shouji_server_create.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "../../include/shouji.h"
+#include "shouji_internal.h"
+
+namespace shouji {
+
+// pair-major packed reads in[n][wpr] -> word-major out[nw][ld]; words at or
+// beyond wpr are written as 0.
+__global__ void reads_to_word_major_kernel(const uint32_t *__restrict__ in, int wpr, int64_t n,
+                                           uint32_t *__restrict__ out, int nw, int64_t ld) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * nw) return;
+    const int w = (int)(i / n);
+    const int64_t p = i - (int64_t)w * n;
+    out[(int64_t)w * ld + p] = w < wpr ? in[p * wpr + w] : 0u;
+}
+
+// Reference segment of pair p = pool bases [off[p], off[p] + len[p]), written
+// word-major to out[nw][ld]; pool base b sits in bits 2(b%16).. of word b/16.
+// A segment that does not lie inside the pool makes the pair invalid
+// (len[p] = -1, so the filter gives it the sentinels).
+__global__ void pool_gather_kernel(const uint32_t *__restrict__ pool, int64_t pool_bases,
+                                   const int64_t *__restrict__ off, int32_t *__restrict__ len,
+                                   int64_t n, uint32_t *__restrict__ out, int nw, int64_t ld) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * nw) return;
+    const int w = (int)(i / n);
+    const int64_t p = i - (int64_t)w * n;
+    int64_t o = off[p];
+    const bool inside = o >= 0 && o <= pool_bases;
+    if (w == 0) {
+        const int32_t m = len[p];
+        if (!inside || m < 0 || (int64_t)m > pool_bases - o) len[p] = -1;
+    }
+    if (!inside) o = 0;
+    const int64_t pool_words = (pool_bases + kHalf - 1) / kHalf;
+    const int64_t b = o + (int64_t)w * kHalf;   // first base of this word
+    const int64_t q = b >> 4;
+    const int sh = (int)(b & 15) * 2;
+    const uint32_t lo = q < pool_words ? pool[q] : 0u;
+    const uint32_t hi = (sh != 0 && q + 1 < pool_words) ? pool[q + 1] : 0u;
+    out[(int64_t)w * ld + p] = sh ? (uint32_t)((((uint64_t)hi << 32) | lo) >> sh) : lo;
+}
+
+}  // namespace shouji
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+constexpr int kDefaultHostThreads = 8;
+
+struct Request {
+    shouji_request req;
+    clk::time_point submitted, finished;
+    int64_t pairs_left = 0;   // pairs whose results are not delivered yet
+    bool done = false;
+    int status = SHOUJI_OK;
+};
+
+struct Part {
+    Request *r;
+    int64_t first;   // first pair of the request in this part
+    int64_t count;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    uint32_t *h_reads = nullptr;  // pinned staging
+    int64_t *h_off = nullptr;
+    int32_t *h_len = nullptr, *h_E = nullptr;
+    uint8_t *h_acc = nullptr;
+    int16_t *h_pc = nullptr;
+    uint32_t *d_reads_pm = nullptr, *d_reads = nullptr, *d_refs = nullptr;
+    int64_t *d_off = nullptr;
+    int32_t *d_len = nullptr, *d_E = nullptr;
+    uint8_t *d_acc = nullptr;
+    int16_t *d_pc = nullptr;
+    void *d_ws = nullptr;
+    int64_t ws_bytes = 0;
+    std::vector<Part> parts;
+    int64_t pairs = 0;
+    int status = SHOUJI_OK;
+    bool busy = false;
+};
+
+int64_t slot_device_bytes(int64_t B, int nw, int max_len) {
+    return 3 * B * nw * 4 + B * (8 + 4 + 4 + 1 + 2) + shouji_batched_workspace_bytes(B, max_len);
+}
+
+void free_slot(Slot &s) {
+    if (s.stream) hipStreamDestroy(s.stream);
+    if (s.done) hipEventDestroy(s.done);
+    hipHostFree(s.h_reads);
+    hipHostFree(s.h_off);
+    hipHostFree(s.h_len);
+    hipHostFree(s.h_E);
+    hipHostFree(s.h_acc);
+    hipHostFree(s.h_pc);
+    hipFree(s.d_reads_pm);
+    hipFree(s.d_reads);
+    hipFree(s.d_refs);
+    hipFree(s.d_off);
+    hipFree(s.d_len);
+    hipFree(s.d_E);
+    hipFree(s.d_acc);
+    hipFree(s.d_pc);
+    hipFree(s.d_ws);
+}
+
+bool alloc_slot(Slot &s, int64_t B, int nw, int max_len) {
+    s.ws_bytes = shouji_batched_workspace_bytes(B, max_len);
+    return s.ws_bytes > 0 &&
+           hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&s.done, hipEventDisableTiming) == hipSuccess &&
+           hipHostMalloc((void **)&s.h_reads, (size_t)B * nw * 4, 0) == hipSuccess &&
+           hipHostMalloc((void **)&s.h_off, (size_t)B * 8, 0) == hipSuccess &&
+           hipHostMalloc((void **)&s.h_len, (size_t)B * 4, 0) == hipSuccess &&
+           hipHostMalloc((void **)&s.h_E, (size_t)B * 4, 0) == hipSuccess &&
+           hipHostMalloc((void **)&s.h_acc, (size_t)B, 0) == hipSuccess &&
+           hipHostMalloc((void **)&s.h_pc, (size_t)B * 2, 0) == hipSuccess &&
+           hipMalloc((void **)&s.d_reads_pm, (size_t)B * nw * 4) == hipSuccess &&
+           hipMalloc((void **)&s.d_reads, (size_t)B * nw * 4) == hipSuccess &&
+           hipMalloc((void **)&s.d_refs, (size_t)B * nw * 4) == hipSuccess &&
+           hipMalloc((void **)&s.d_off, (size_t)B * 8) == hipSuccess &&
+           hipMalloc((void **)&s.d_len, (size_t)B * 4) == hipSuccess &&
+           hipMalloc((void **)&s.d_E, (size_t)B * 4) == hipSuccess &&
+           hipMalloc((void **)&s.d_acc, (size_t)B) == hipSuccess &&
+           hipMalloc((void **)&s.d_pc, (size_t)B * 2) == hipSuccess &&
+           hipMalloc(&s.d_ws, (size_t)s.ws_bytes) == hipSuccess;
+}
+
+}  // namespace
+
+struct shouji_server {
+    shouji_server_config cfg{};
+    int nw = 0;
+    int device = 0;
+    std::vector<std::unique_ptr<Slot>> slots;
+    std::mutex mu;
+    std::condition_variable cv;       // new parts, a free slot, a launched batch
+    std::condition_variable cv_done;  // a request finished
+    std::deque<Part> queue;           // parts not yet in a batch, arrival order
+    std::deque<Slot *> inflight;      // launched batches, launch order
+    std::map<uint64_t, std::unique_ptr<Request>> reqs;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::thread sched, reaper;
+    int64_t batches = 0, pairs_done = 0, requests_done = 0, requests_deferred = 0;
+};
+
+namespace {
+
+struct CopyJob {
+    void *dst;
+    const void *src;
+    size_t bytes;
+};
+
+// Run host copies on up to `threads` threads (large copies are cut into
+// chunks; a single thread does small batches, where thread start-up would
+// cost more than it saves).
+void run_copies(const std::vector<CopyJob> &jobs, int threads) {
+    constexpr size_t kChunk = size_t(1) << 20;
+    size_t total = 0;
+    for (const CopyJob &j : jobs) total += j.bytes;
+    if (threads <= 1 || total < 4 * kChunk) {
+        for (const CopyJob &j : jobs) memcpy(j.dst, j.src, j.bytes);
+        return;
+    }
+    std::vector<CopyJob> chunks;
+    for (const CopyJob &j : jobs)
+        for (size_t o = 0; o < j.bytes; o += kChunk)
+            chunks.push_back(CopyJob{(char *)j.dst + o, (const char *)j.src + o, std::min(kChunk, j.bytes - o)});
+    std::atomic<size_t> next{0};
+    auto work = [&] {
+        for (size_t i; (i = next.fetch_add(1)) < chunks.size();) memcpy(chunks[i].dst, chunks[i].src, chunks[i].bytes);
+    };
+    const int nt = (int)std::min<size_t>((size_t)threads, chunks.size());
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; t++) pool.emplace_back(work);
+    work();
+    for (std::thread &t : pool) t.join();
+}
+
+// Copy the slot's parts into its pinned staging buffers and enqueue the batch
+// on the slot's stream.  Runs without the server lock: the slot is marked busy
+// and its requests stay alive until all their parts are done.
+int enqueue_batch(shouji_server *S, Slot &s) {
+    const int nw = S->nw;
+    std::vector<CopyJob> jobs;
+    int64_t at = 0;
+    for (const Part &pt : s.parts) {
+        const shouji_request &r = pt.r->req;
+        const int64_t c = pt.count, f = pt.first;
+        if (r.words_per_read == nw) {
+            jobs.push_back(CopyJob{s.h_reads + at * nw, r.reads + f * nw, (size_t)c * nw * 4});
+        } else {
+            const int cw = std::min(nw, (int)r.words_per_read);
+            for (int64_t k = 0; k < c; k++) {
+                uint32_t *dst = s.h_reads + (at + k) * nw;
+                memcpy(dst, r.reads + (f + k) * r.words_per_read, (size_t)cw * 4);
+                for (int w = cw; w < nw; w++) dst[w] = 0u;
+            }
+        }
+        jobs.push_back(CopyJob{s.h_off + at, r.ref_offsets + f, (size_t)c * 8});
+        jobs.push_back(CopyJob{s.h_len + at, r.lengths + f, (size_t)c * 4});
+        jobs.push_back(CopyJob{s.h_E + at, r.E + f, (size_t)c * 4});
+        at += c;
+    }
+    run_copies(jobs, S->cfg.host_threads > 0 ? S->cfg.host_threads : kDefaultHostThreads);
+    const int64_t n = s.pairs;
+    hipStream_t st = s.stream;
+    bool good = hipMemcpyAsync(s.d_reads_pm, s.h_reads, (size_t)n * nw * 4, hipMemcpyHostToDevice, st) == hipSuccess &&
+                hipMemcpyAsync(s.d_off, s.h_off, (size_t)n * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
+                hipMemcpyAsync(s.d_len, s.h_len, (size_t)n * 4, hipMemcpyHostToDevice, st) == hipSuccess &&
+                hipMemcpyAsync(s.d_E, s.h_E, (size_t)n * 4, hipMemcpyHostToDevice, st) == hipSuccess;
+    int rc = good ? SHOUJI_OK : SHOUJI_ERR_DEVICE;
+    if (good) {
+        const unsigned blocks = (unsigned)((n * nw + 255) / 256);
+        hipLaunchKernelGGL(shouji::reads_to_word_major_kernel, dim3(blocks), dim3(256), 0, st, s.d_reads_pm,
+                           nw, n, s.d_reads, nw, n);
+        hipLaunchKernelGGL(shouji::pool_gather_kernel, dim3(blocks), dim3(256), 0, st, S->cfg.pool,
+                           S->cfg.pool_bases, s.d_off, s.d_len, n, s.d_refs, nw, n);
+        rc = hipGetLastError() == hipSuccess ? SHOUJI_OK : SHOUJI_ERR_DEVICE;
+    }
+    if (rc == SHOUJI_OK)
+        rc = shouji_filter_batched(s.d_reads, s.d_refs, s.d_len, s.d_E, s.d_acc, s.d_pc, n, S->cfg.max_len, n,
+                                   s.d_ws, s.ws_bytes, nullptr, st);
+    if (rc == SHOUJI_OK &&
+        (hipMemcpyAsync(s.h_acc, s.d_acc, (size_t)n, hipMemcpyDeviceToHost, st) != hipSuccess ||
+         hipMemcpyAsync(s.h_pc, s.d_pc, (size_t)n * 2, hipMemcpyDeviceToHost, st) != hipSuccess))
+        rc = SHOUJI_ERR_DEVICE;
+    if (hipEventRecord(s.done, st) != hipSuccess && rc == SHOUJI_OK) rc = SHOUJI_ERR_DEVICE;
+    return rc;
+}
+
+void scheduler_loop(shouji_server *S) {
+    hipSetDevice(S->device);
+    const int64_t B = S->cfg.max_batch_pairs;
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (;;) {
+        if (S->stop) break;
+        Slot *s = nullptr;
+        for (auto &q : S->slots)
+            if (!q->busy) { s = q.get(); break; }
+        if (!s || S->queue.empty()) {
+            S->cv.wait(lk);
+            continue;
+        }
+        // fill the slot with queued parts in arrival order
+        s->parts.clear();
+        s->pairs = 0;
+        while (!S->queue.empty() && s->pairs < B) {
+            Part &q = S->queue.front();
+            const int64_t take = std::min(q.count, B - s->pairs);
+            s->parts.push_back(Part{q.r, q.first, take});
+            s->pairs += take;
+            q.first += take;
+            q.count -= take;
+            if (q.count == 0) S->queue.pop_front();
+        }
+        s->busy = true;
+        S->batches++;
+        lk.unlock();
+        s->status = enqueue_batch(S, *s);
+        lk.lock();
+        S->inflight.push_back(s);
+        S->cv.notify_all();
+    }
+}
+
+void reaper_loop(shouji_server *S) {
+    hipSetDevice(S->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (;;) {
+        if (S->inflight.empty()) {
+            if (S->stop) break;
+            S->cv.wait(lk);
+            continue;
+        }
+        Slot &s = *S->inflight.front();
+        lk.unlock();
+        if (hipEventSynchronize(s.done) != hipSuccess && s.status == SHOUJI_OK) s.status = SHOUJI_ERR_DEVICE;
+        int64_t at = 0;
+        for (const Part &pt : s.parts) {
+            shouji_request &r = pt.r->req;
+            memcpy(r.out_accept + pt.first, s.h_acc + at, (size_t)pt.count);
+            if (r.out_popcount) memcpy(r.out_popcount + pt.first, s.h_pc + at, (size_t)pt.count * 2);
+            at += pt.count;
+        }
+        const auto now = clk::now();
+        lk.lock();
+        for (const Part &pt : s.parts) {
+            Request &R = *pt.r;
+            if (s.status != SHOUJI_OK) R.status = s.status;
+            R.pairs_left -= pt.count;
+            if (R.pairs_left == 0) {
+                R.done = true;
+                R.finished = now;
+                S->requests_done++;
+            }
+        }
+        S->pairs_done += s.pairs;
+        S->inflight.pop_front();
+        s.parts.clear();
+        s.busy = false;
+        S->cv.notify_all();
+        S->cv_done.notify_all();
+    }
+}
+
+}  // namespace
+
+extern "C" int64_t shouji_server_slot_bytes(int64_t max_batch_pairs, int32_t max_len) {
+    using shouji::set_error;
+    if (max_batch_pairs <= 0) return set_error(SHOUJI_ERR_ARG, "shouji_server_slot_bytes: max_batch_pairs must be positive");
+    if (max_len <= 0 || max_len > SHOUJI_MAX_LEN)
+        return set_error(SHOUJI_ERR_RANGE, "shouji_server_slot_bytes: max_len %d outside 1..%d", max_len, SHOUJI_MAX_LEN);
+    shouji::clear_error();
+    return slot_device_bytes(max_batch_pairs, (max_len + shouji::kHalf - 1) / shouji::kHalf, max_len);
+}
+
+extern "C" int shouji_server_create(const shouji_server_config *cfg, shouji_server **out) {
+    using shouji::set_error;
+    if (!cfg || !out) return set_error(SHOUJI_ERR_NULL, "shouji_server_create: config and out are required");
+    *out = nullptr;
+    if (!cfg->pool || cfg->pool_bases <= 0)
+        return set_error(SHOUJI_ERR_ARG, "shouji_server_create: a non-empty reference pool is required");
+    if (cfg->max_len <= 0 || cfg->max_len > SHOUJI_MAX_LEN)
+        return set_error(SHOUJI_ERR_RANGE, "shouji_server_create: max_len %d outside 1..%d", cfg->max_len,
+                         SHOUJI_MAX_LEN);
+    if (cfg->max_batch_pairs <= 0 || cfg->slots <= 0 || cfg->memory_budget < 0)
+        return set_error(SHOUJI_ERR_ARG, "shouji_server_create: max_batch_pairs and slots must be positive");
+    std::unique_ptr<shouji_server> S(new shouji_server());
+    S->cfg = *cfg;
+    S->nw = (cfg->max_len + shouji::kHalf - 1) / shouji::kHalf;
+    if (hipGetDevice(&S->device) != hipSuccess)
+        return set_error(SHOUJI_ERR_DEVICE, "shouji_server_create: no current HIP device");
+    const int64_t per = slot_device_bytes(cfg->max_batch_pairs, S->nw, cfg->max_len);
+    int64_t nslots = cfg->slots;
+    if (cfg->memory_budget > 0) nslots = std::min<int64_t>(nslots, cfg->memory_budget / per);
+    if (nslots < 1)
+        return set_error(SHOUJI_ERR_NOMEM, "shouji_server_create: memory budget %lld below one batch slot (%lld bytes)",
+                         (long long)cfg->memory_budget, (long long)per);
+    for (int64_t i = 0; i < nslots; i++) {
+        std::unique_ptr<Slot> s(new Slot());
+        if (!alloc_slot(*s, cfg->max_batch_pairs, S->nw, cfg->max_len)) {
+            free_slot(*s);
+            for (auto &q : S->slots) free_slot(*q);
+            return set_error(SHOUJI_ERR_NOMEM, "shouji_server_create: cannot allocate batch slot %lld", (long long)i);
+        }
+        S->slots.push_back(std::move(s));
+    }
+    S->sched = std::thread(scheduler_loop, S.get());
+    S->reaper = std::thread(reaper_loop, S.get());
+    *out = S.release();
+    return shouji::clear_error();
+}
+
+extern "C" int shouji_server_submit(shouji_server *S, const shouji_request *r, uint64_t *ticket) {
+    using shouji::set_error;
+    if (!S || !r || !ticket)
+        return set_error(SHOUJI_ERR_NULL, "shouji_server_submit: server, request and ticket are required");
+    if (r->n_pairs < 0) return set_error(SHOUJI_ERR_ARG, "shouji_server_submit: n_pairs < 0");
+    if (r->n_pairs > 0) {
+        if (!r->reads || !r->ref_offsets || !r->lengths || !r->E || !r->out_accept)
+            return set_error(SHOUJI_ERR_NULL, "shouji_server_submit: request buffer missing");
+        if (r->words_per_read <= 0)
+            return set_error(SHOUJI_ERR_ARG, "shouji_server_submit: words_per_read must be positive");
+    }
+    std::unique_ptr<Request> R(new Request());
+    R->req = *r;
+    const int64_t B = S->cfg.max_batch_pairs;
+    std::lock_guard<std::mutex> g(S->mu);
+    R->submitted = clk::now();
+    const uint64_t t = S->next_ticket++;
+    R->pairs_left = r->n_pairs;
+    if (r->n_pairs == 0) {
+        R->done = true;
+        R->finished = R->submitted;
+        S->requests_done++;
+    }
+    if (r->n_pairs > 0 && (!S->queue.empty() || std::all_of(S->slots.begin(), S->slots.end(),
+                                                            [](const std::unique_ptr<Slot> &q) { return q->busy; })))
+        S->requests_deferred++;
+    for (int64_t f = 0; f < r->n_pairs; f += B) S->queue.push_back(Part{R.get(), f, std::min(B, r->n_pairs - f)});
+    S->reqs[t] = std::move(R);
+    *ticket = t;
+    S->cv.notify_all();
+    return shouji::clear_error();
+}
+
+extern "C" int shouji_server_poll(shouji_server *S, uint64_t ticket, int32_t *done) {
+    using shouji::set_error;
+    if (!S || !done) return set_error(SHOUJI_ERR_NULL, "shouji_server_poll: server and done are required");
+    std::lock_guard<std::mutex> g(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end())
+        return set_error(SHOUJI_ERR_ARG, "shouji_server_poll: unknown ticket %llu", (unsigned long long)ticket);
+    *done = it->second->done ? 1 : 0;
+    return shouji::clear_error();
+}
+
+extern "C" int shouji_server_wait(shouji_server *S, uint64_t ticket, double *latency_ms) {
+    using shouji::set_error;
+    if (!S) return set_error(SHOUJI_ERR_NULL, "shouji_server_wait: server is required");
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end())
+        return set_error(SHOUJI_ERR_ARG, "shouji_server_wait: unknown ticket %llu", (unsigned long long)ticket);
+    Request *R = it->second.get();
+    S->cv_done.wait(lk, [R] { return R->done; });
+    if (latency_ms) *latency_ms = std::chrono::duration<double, std::milli>(R->finished - R->submitted).count();
+    const int st = R->status;
+    S->reqs.erase(it);
+    if (st != SHOUJI_OK)
+        return set_error(st, "shouji_server_wait: a batch of request %llu failed", (unsigned long long)ticket);
+    return shouji::clear_error();
+}
+
+extern "C" int shouji_server_get_stats(shouji_server *S, shouji_server_stats *st) {
+    using shouji::set_error;
+    if (!S || !st) return set_error(SHOUJI_ERR_NULL, "shouji_server_get_stats: server and stats are required");
+    std::lock_guard<std::mutex> g(S->mu);
+    st->slots = (int32_t)S->slots.size();
+    st->batches = S->batches;
+    st->pairs_done = S->pairs_done;
+    st->requests_done = S->requests_done;
+    st->requests_deferred = S->requests_deferred;
+    int64_t q = 0;
+    for (const Part &p : S->queue) q += p.count;
+    st->queued_pairs = q;
+    return shouji::clear_error();
+}
+
+extern "C" int shouji_server_destroy(shouji_server *S) {
+    if (!S) return SHOUJI_OK;
+    {
+        std::unique_lock<std::mutex> lk(S->mu);
+        S->cv_done.wait(lk, [S] {
+            return S->queue.empty() && S->inflight.empty() &&
+                   std::none_of(S->slots.begin(), S->slots.end(),
+                                [](const std::unique_ptr<Slot> &s) { return s->busy; });
+        });
+        S->stop = true;
+        S->cv.notify_all();
+    }
+    S->sched.join();
+    S->reaper.join();
+    hipSetDevice(S->device);
+    for (auto &s : S->slots) free_slot(*s);
+    delete S;
+    return SHOUJI_OK;
+}

@@ -103,3 +103,33 @@ def config2(E, n=2_000_000):
 def config3(n=8_000_000):
     """Mixed lengths 64..300, per-pair E_p=floor(r*m) with r~U[0,0.10], seed 3000."""
     return generate(n, 64, 300, E=None, r_max=0.10, seed=3000)
+
+
+def reference_pool(pairs, seed=0, max_gap=7, base_len=0):
+    """Lay the references of `pairs` out in one flat pool of base codes.
+
+    The segments go into the pool in a seeded random order, separated by gaps of
+    0..max_gap uniform random bases, after `base_len` leading random bases.
+    Returns (pool codes uint8 [L], offsets int64 [n]): pair p's reference is
+    pool[offsets[p] : offsets[p] + lengths[p]].
+    """
+    rng = np.random.default_rng(seed)
+    n = pairs.n
+    order = rng.permutation(n)
+    gaps = rng.integers(0, max_gap + 1, n)
+    lens = pairs.lengths.astype(np.int64)
+    step = gaps + lens[order]
+    starts_in_order = base_len + np.cumsum(step) - lens[order]
+    offsets = np.empty(n, dtype=np.int64)
+    offsets[order] = starts_in_order
+    total = int(base_len + step.sum() + max_gap)
+    out = pool(total, seed=seed + 1)
+    stride = pairs.T.shape[1]
+    cols = np.arange(stride)
+    chunk = 1 << 16
+    for lo in range(0, n, chunk):
+        hi = min(n, lo + chunk)
+        mask = cols[None, :] < pairs.lengths[lo:hi, None]
+        pos = offsets[lo:hi, None] + cols[None, :]
+        out[pos[mask]] = pairs.T[lo:hi][mask]
+    return out, offsets

@@ -68,3 +68,39 @@ def test_pack_words_layout():
             assert (int(w[j // 16, p]) >> (2 * (j % 16))) & 3 == codes[p, j]
     assert (w[:, 37:] == 0).all()
     assert (w[3, :37] >> 4 == 0).all()   # bases 50..63 of the last word are zero
+
+
+def test_server_argument_errors_are_reported_without_a_device():
+    L = sj.lib()
+    h = ctypes.c_void_p()
+    assert L.shouji_server_create(None, ctypes.byref(h)) == -1
+    cfg = sj.ServerConfig(None, 1000, 100, 2, 1024, 0, 0)
+    assert L.shouji_server_create(ctypes.byref(cfg), ctypes.byref(h)) == -2      # no pool
+    cfg = sj.ServerConfig(16, 1000, 2000, 2, 1024, 0, 0)
+    assert L.shouji_server_create(ctypes.byref(cfg), ctypes.byref(h)) == -3      # max_len
+    cfg = sj.ServerConfig(16, 1000, 100, 0, 1024, 0, 0)
+    assert L.shouji_server_create(ctypes.byref(cfg), ctypes.byref(h)) == -2      # slots
+    assert b"slots" in L.shouji_last_error()
+    t = ctypes.c_uint64()
+    assert L.shouji_server_submit(None, None, ctypes.byref(t)) == -1
+    assert L.shouji_server_wait(None, 1, None) == -1
+    assert L.shouji_server_destroy(None) == 0
+    assert sj.server_slot_bytes(1 << 20, 300) > (1 << 20) * 19 * 4 * 3
+    with pytest.raises(sj.ShoujiError):
+        sj.server_slot_bytes(0, 300)
+    with pytest.raises(sj.ShoujiError):
+        sj.server_slot_bytes(100, 5000)
+
+
+def test_pool_and_pair_packing_layout():
+    rng = np.random.default_rng(1)
+    c = rng.integers(0, 4, (7, 45), dtype=np.uint8)
+    pp = sj.pack_pairs(c, 45)
+    assert pp.shape == (7, 3) and pp.dtype == np.uint32
+    flat = c.ravel()
+    pool = sj.pack_pool(flat)
+    for b in range(flat.size):
+        assert (int(pool[b // 16]) >> (2 * (b % 16))) & 3 == flat[b]
+    for p in range(7):
+        for j in range(45):
+            assert (int(pp[p, j // 16]) >> (2 * (j % 16))) & 3 == c[p, j]

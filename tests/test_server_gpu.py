@@ -1,0 +1,184 @@
+"""GPU tests of the serving form: requests cut across batches and batches
+shared by requests give the oracle's results bit-exactly; each request's
+results are identical when served alone and inside a concurrent mix; invalid
+pairs get the sentinels; the memory budget decides the number of batch slots."""
+import threading
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+import syninput
+
+pytestmark = pytest.mark.gpu
+
+MAX_LEN = 300
+
+
+@pytest.fixture(scope="module")
+def sj():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1809_07858_amd as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def work(sj):
+    # mixed lengths 64..300, E_p = floor(r m) with r ~ U[0, 0.1]; references laid
+    # out in a shuffled pool with gaps (unaligned offsets)
+    p = syninput.generate(40_000, 64, MAX_LEN, E=None, r_max=0.10, seed=4000)
+    codes, off = syninput.reference_pool(p, seed=4001, base_len=1000)
+    pool = torch.from_numpy(sj.pack_pool(codes).view(np.int32)).to("cuda:0")
+    reads = sj.pack_pairs(p.P, MAX_LEN)
+    ea, ep = oracle.shouji_batch(p.P, p.T, p.lengths, E_per_pair=p.E)
+    return dict(p=p, pool=pool, pool_bases=codes.size, off=off, reads=reads, ea=ea, ep=ep)
+
+
+def _server(sj, w, **kw):
+    return sj.Server(w["pool"], w["pool_bases"], MAX_LEN, **kw)
+
+
+def _submit(srv, w, lo, hi):
+    p = w["p"]
+    return srv.submit(w["reads"][lo:hi], w["off"][lo:hi], p.lengths[lo:hi], p.E[lo:hi])
+
+
+def _expect(w, lo, hi, acc, pc):
+    ea, ep = w["ea"][lo:hi], w["ep"][lo:hi]
+    bad = np.nonzero((acc != ea) | (pc != ep))[0]
+    assert bad.size == 0, "range %d:%d mismatches at %s: server %s/%s oracle %s/%s" % (
+        lo, hi, bad[:6], acc[bad[:6]], pc[bad[:6]], ea[bad[:6]], ep[bad[:6]])
+
+
+def _cuts(n, sizes):
+    out, lo = [], 0
+    for s in sizes:
+        if lo >= n:
+            break
+        out.append((lo, min(n, lo + s)))
+        lo += s
+    if lo < n:
+        out.append((lo, n))
+    return out
+
+
+def test_requests_across_batches_match_oracle(sj, work):
+    # batch capacity 4096: requests smaller than, equal to and larger than a
+    # batch, so batches hold several requests and requests span batches
+    n = work["p"].n
+    cuts = _cuts(n, [1, 2, 17, 1000, 4095, 4096, 4097, 9000, 3, 250, 8192, 64])
+    print("server: %d requests, batch 4096, 3 slots" % len(cuts), flush=True)
+    with _server(sj, work, slots=3, max_batch_pairs=4096) as srv:
+        tickets = [_submit(srv, work, lo, hi) for lo, hi in cuts]
+        for (lo, hi), t in zip(cuts, tickets):
+            acc, pc, ms = srv.wait(t)
+            assert ms >= 0.0
+            _expect(work, lo, hi, acc, pc)
+        st = srv.stats()
+    assert st["pairs_done"] == n and st["requests_done"] == len(cuts)
+    assert st["batches"] >= (n + 4095) // 4096 and st["queued_pairs"] == 0
+
+
+def test_alone_vs_mix_identical(sj, work):
+    # each probe request is served alone on an idle server, then again inside
+    # a mix of other requests submitted concurrently from three threads
+    probes = [(100, 101), (2000, 2600), (10_000, 17_000), (30_000, 30_005), (5, 9000)]
+    with _server(sj, work, slots=2, max_batch_pairs=8192) as srv:
+        alone = []
+        for lo, hi in probes:
+            acc, pc, _ = srv.wait(_submit(srv, work, lo, hi))
+            alone.append((acc.copy(), pc.copy()))
+        results = {}
+        errors = []
+
+        def client(k):
+            try:
+                rng = np.random.default_rng(9 + k)
+                local = []
+                for i in range(12):
+                    if i % 3 == 0:
+                        j = (k + i // 3) % len(probes)
+                        local.append(("probe", j, _submit(srv, work, *probes[j])))
+                    lo = int(rng.integers(0, work["p"].n - 1))
+                    hi = min(work["p"].n, lo + int(rng.integers(1, 6000)))
+                    local.append(("other", (lo, hi), _submit(srv, work, lo, hi)))
+                for kind, key, t in local:
+                    acc, pc, _ = srv.wait(t)
+                    if kind == "probe":
+                        results.setdefault(key, []).append((acc, pc))
+                    else:
+                        _expect(work, key[0], key[1], acc, pc)
+            except Exception as e:  # reported in the main thread
+                errors.append(e)
+
+        threads = [threading.Thread(target=client, args=(k,)) for k in range(3)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        assert not errors, errors
+    assert results, "no probe request ran in the mix"
+    for j, runs in results.items():
+        lo, hi = probes[j]
+        for acc, pc in runs:
+            assert np.array_equal(acc, alone[j][0]) and np.array_equal(pc, alone[j][1])
+        _expect(work, lo, hi, alone[j][0], alone[j][1])
+
+
+def test_invalid_pairs_get_sentinels(sj, work):
+    p = work["p"]
+    lo, hi = 0, 3000
+    offs = work["off"][lo:hi].copy()
+    lens = p.lengths[lo:hi].copy()
+    E = p.E[lo:hi].copy()
+    offs[::37] = -5                                   # before the pool
+    offs[1::41] = work["pool_bases"] + 3              # past the pool
+    offs[2::43] = work["pool_bases"] - 10             # runs off the end
+    lens[3::47] = MAX_LEN + 1                         # longer than max_len
+    E[4::53] = -1                                     # negative threshold
+    E[5::59] = 40                                     # clamped E above 31
+    bad = np.zeros(hi - lo, dtype=bool)
+    bad[::37] = True
+    bad[1::41] = True
+    bad[2::43] |= lens[2::43] > 10
+    bad[3::47] = True
+    bad[4::53] = True
+    bad[5::59] |= np.minimum(40, lens[5::59] - 1) > 31
+    with _server(sj, work, slots=1, max_batch_pairs=1024) as srv:
+        acc, pc, _ = srv.wait(srv.submit(work["reads"][lo:hi], offs, lens, E))
+    assert (acc[bad] == 0xFF).all() and (pc[bad] == -1).all()
+    good = ~bad
+    ea, ep = oracle.shouji_batch(p.P[lo:hi][good], p.T[lo:hi][good], lens[good], E_per_pair=E[good])
+    assert np.array_equal(acc[good], ea) and np.array_equal(pc[good], ep)
+
+
+def test_short_read_rows_and_empty_request(sj, work):
+    # a request whose reads use fewer words than the server's max_len needs
+    p = syninput.generate(5000, 20, 80, E=None, r_max=0.1, seed=77)
+    codes, off = syninput.reference_pool(p, seed=78)
+    pool = torch.from_numpy(sj.pack_pool(codes).view(np.int32)).to("cuda:0")
+    reads = sj.pack_pairs(p.P, 80)                    # 5 words per read
+    with sj.Server(pool, codes.size, MAX_LEN, slots=2, max_batch_pairs=2048) as srv:
+        t0 = srv.submit(np.zeros((0, 5), np.uint32), np.zeros(0, np.int64), np.zeros(0, np.int32), 0)
+        t1 = srv.submit(reads, off, p.lengths, p.E)
+        a0, p0, _ = srv.wait(t0)
+        acc, pc, _ = srv.wait(t1)
+    assert a0.size == 0 and p0.size == 0
+    ea, ep = oracle.shouji_batch(p.P, p.T, p.lengths, E_per_pair=p.E)
+    assert np.array_equal(acc, ea) and np.array_equal(pc, ep)
+
+
+def test_memory_budget_sets_slots(sj, work):
+    per = sj.server_slot_bytes(4096, MAX_LEN)
+    with pytest.raises(sj.ShoujiError) as e:
+        _server(sj, work, slots=4, max_batch_pairs=4096, memory_budget=per - 1)
+    assert e.value.code == -5
+    with _server(sj, work, slots=5, max_batch_pairs=4096, memory_budget=2 * per + 100) as srv:
+        assert srv.stats()["slots"] == 2
+        t = _submit(srv, work, 0, 20_000)
+        acc, pc, _ = srv.wait(t)
+    _expect(work, 0, 20_000, acc, pc)
