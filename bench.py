@@ -322,8 +322,10 @@ def bench_serving(dev, total_pairs, batch_pairs, slots, distinct=1_000_000, load
     segments); a request's pairs are a contiguous run of `distinct` generated
     pairs.  First the whole stream is submitted at once (peak pairs/s), then it
     is replayed with Poisson arrivals at `load` x that peak; latency = submit to
-    results in the caller's host buffers.  Every served result is compared with
-    the batched form run on the same pairs resident on the device."""
+    results in the caller's host buffers.  This runs twice: with request buffers
+    in pinned host memory (moved by DMA in place) and in pageable memory (staged
+    by the server).  Every served result is compared with the batched form run
+    on the same pairs resident on the device."""
     import threading
     import numpy as np
     import torch
@@ -380,88 +382,109 @@ def bench_serving(dev, total_pairs, batch_pairs, slots, distinct=1_000_000, load
     starts = [int(rng.integers(0, distinct - s + 1)) for s in sizes]
     setup_s = time.time() - t0
 
-    srv = sj.Server(pool, pool_words * 16, max_len, slots=slots, max_batch_pairs=batch_pairs,
-                    memory_budget=16 << 30)
-    try:
-        def submit(i):
-            a, s = starts[i], sizes[i]
-            return srv.submit(reads[a:a + s], offsets[a:a + s], lens[a:a + s], Ep[a:a + s])
+    # pinned copies of the request sources and one pinned output area, for the
+    # stream whose requests declare pinned buffers
+    def pinned(a):
+        t = torch.empty(a.shape, dtype={np.dtype(np.uint32): torch.int32}.get(a.dtype, None) or
+                        getattr(torch, a.dtype.name), pin_memory=True)
+        v = t.numpy().view(a.dtype)
+        v[...] = a
+        return t, v
+    pin_src = [pinned(a) for a in (reads, offsets, lens, Ep)]
+    out_base = np.cumsum([0] + sizes)
+    pin_out = [pinned(np.zeros(total_pairs, np.uint8)), pinned(np.zeros(total_pairs, np.int16))]
 
-        for i in range(3):                        # warm-up
-            srv.wait(submit(i))
-        bad = 0
+    def run(mode):
+        srv = sj.Server(pool, pool_words * 16, max_len, slots=slots, max_batch_pairs=batch_pairs,
+                        memory_budget=16 << 30)
+        state = {"bad": 0}
+        try:
+            def submit(i):
+                a, s_ = starts[i], sizes[i]
+                if mode == "pinned":
+                    r, o, L, E = [v for _, v in pin_src]
+                    b0 = out_base[i]
+                    return srv.submit(r[a:a + s_], o[a:a + s_], L[a:a + s_], E[a:a + s_], pinned=True,
+                                      out_accept=pin_out[0][1][b0:b0 + s_],
+                                      out_popcount=pin_out[1][1][b0:b0 + s_])
+                return srv.submit(reads[a:a + s_], offsets[a:a + s_], lens[a:a + s_], Ep[a:a + s_])
 
-        def check(i, acc, pc):
-            a, s = starts[i], sizes[i]
-            return int(((acc != ref_acc[a:a + s]) | (pc != ref_pc[a:a + s])).sum())
+            def check(i, acc, pc):
+                a, s_ = starts[i], sizes[i]
+                state["bad"] += int(((acc != ref_acc[a:a + s_]) | (pc != ref_pc[a:a + s_])).sum())
 
-        # peak: the whole stream at once
-        st0 = srv.stats()
-        tb = time.perf_counter()
-        tickets = [submit(i) for i in range(len(sizes))]
-        for i, t in enumerate(tickets):
-            acc, pc, _ = srv.wait(t)
-            bad += check(i, acc, pc)
-        peak_s = time.perf_counter() - tb
-        peak = total_pairs / peak_s
-        st1 = srv.stats()
+            for i in range(3):                        # warm-up
+                srv.wait(submit(i))
+            # peak: the whole stream at once
+            st0 = srv.stats()
+            tb = time.perf_counter()
+            tickets = [submit(i) for i in range(len(sizes))]
+            for i, t in enumerate(tickets):
+                acc, pc, _ = srv.wait(t)
+                check(i, acc, pc)
+            peak_s = time.perf_counter() - tb
+            peak = total_pairs / peak_s
+            st1 = srv.stats()
 
-        # Poisson arrivals at load x peak
-        mean_size = total_pairs / len(sizes)
-        rate = load * peak / mean_size             # requests per second
-        arrivals = np.cumsum(rng.exponential(1.0 / rate, len(sizes)))
-        lat = [None] * len(sizes)
-        sub_t = [None] * len(sizes)
-        tq = []
-        ready = threading.Condition()
+            # Poisson arrivals at load x peak
+            mean_size = total_pairs / len(sizes)
+            rate = load * peak / mean_size             # requests per second
+            arrivals = np.cumsum(rng.exponential(1.0 / rate, len(sizes)))
+            lat = [None] * len(sizes)
+            sub_t = [None] * len(sizes)
+            tq = []
+            ready = threading.Condition()
 
-        def waiter():
+            def waiter():
+                for i in range(len(sizes)):
+                    with ready:
+                        while len(tq) <= i:
+                            ready.wait()
+                        t = tq[i]
+                    acc, pc, ms = srv.wait(t)
+                    lat[i] = ms
+                    check(i, acc, pc)
+
+            wt = threading.Thread(target=waiter)
+            wt.start()
+            tp = time.perf_counter()
             for i in range(len(sizes)):
+                d = tp + arrivals[i] - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                sub_t[i] = time.perf_counter()
+                t = submit(i)
                 with ready:
-                    while len(tq) <= i:
-                        ready.wait()
-                    t = tq[i]
-                acc, pc, ms = srv.wait(t)
-                lat[i] = ms
-                nonlocal bad
-                bad += check(i, acc, pc)
+                    tq.append(t)
+                    ready.notify()
+            wt.join()
+            end = max(sub_t[i] + lat[i] / 1e3 for i in range(len(sizes)))
+            poisson_s = end - sub_t[0]
+            st2 = srv.stats()
+        finally:
+            srv.close()
+        lat = np.array(lat)
+        return {"value": total_pairs / poisson_s, "unit": "pairs/s",
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
+                "offered_pairs_per_s": load * peak, "load": load,
+                "peak_pairs_per_s": peak, "peak_s": peak_s, "slots": st2["slots"],
+                "batches_peak": st1["batches"] - st0["batches"],
+                "batches_poisson": st2["batches"] - st1["batches"],
+                "deferred_poisson": st2["requests_deferred"] - st1["requests_deferred"],
+                "mismatches_vs_batched": state["bad"]}
 
-        wt = threading.Thread(target=waiter)
-        wt.start()
-        tp = time.perf_counter()
-        for i in range(len(sizes)):
-            d = tp + arrivals[i] - time.perf_counter()
-            if d > 0:
-                time.sleep(d)
-            sub_t[i] = time.perf_counter()
-            t = submit(i)
-            with ready:
-                tq.append(t)
-                ready.notify()
-        wt.join()
-        end = max(sub_t[i] + lat[i] / 1e3 for i in range(len(sizes)))
-        poisson_s = end - sub_t[0]
-        st2 = srv.stats()
-    finally:
-        srv.close()
-    lat = np.array(lat)
-    return {"workload": "Poisson stream of %d requests, %d pairs in all, request size U{1..200000}, "
-                        "lengths uniform 64..300, E_p=floor(r*m) r~U[0,0.10], 2 GiB device-"
-                        "resident packed reference pool (8 Gi bases), seed %d"
-                        % (len(sizes), total_pairs, seed),
-            "value": total_pairs / poisson_s, "unit": "pairs/s",
-            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
-            "offered_pairs_per_s": load * peak, "load": load,
-            "peak_pairs_per_s": peak, "peak_s": peak_s,
-            "requests": len(sizes), "pairs": total_pairs, "distinct_pairs": distinct,
-            "batch_pairs": batch_pairs, "slots": st2["slots"],
-            "batches_peak": st1["batches"] - st0["batches"],
-            "batches_poisson": st2["batches"] - st1["batches"],
-            "deferred_poisson": st2["requests_deferred"] - st1["requests_deferred"],
-            "mismatches_vs_batched": bad, "batched_vs_oracle_sample_mismatches": oracle_bad,
-            "pool_bytes": pool_words * 4, "setup_s": setup_s}
-
+    res = run("pinned")
+    res["pageable"] = run("pageable")
+    res.update({"workload": "Poisson stream of %d requests, %d pairs in all, request size "
+                            "U{1..200000}, lengths uniform 64..300, E_p=floor(r*m) r~U[0,0.10], "
+                            "2 GiB device-resident packed reference pool (8 Gi bases), seed %d; "
+                            "request buffers pinned (the pageable run is nested)"
+                            % (len(sizes), total_pairs, seed),
+                "requests": len(sizes), "pairs": total_pairs, "distinct_pairs": distinct,
+                "batch_pairs": batch_pairs, "batched_vs_oracle_sample_mismatches": oracle_bad,
+                "pool_bytes": pool_words * 4, "setup_s": setup_s})
+    return res
 
 if __name__ == "__main__":
     main()

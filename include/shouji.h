@@ -181,7 +181,13 @@ typedef struct {
     int16_t *out_popcount;      /* host or NULL: ones of the Shouji bit-vector, -1 for
                                    an invalid pair                                     */
     int64_t n_pairs;            /* >= 0                                                */
+    uint32_t flags;             /* SHOUJI_REQUEST_* bits                               */
 } shouji_request;
+
+/* The request's buffers are pinned host memory (hipHostMalloc): when its read
+ * rows are ceil(max_len/16) words wide they move by DMA straight to and from
+ * the device, without a copy through the server's staging buffers. */
+#define SHOUJI_REQUEST_PINNED 1u
 
 typedef struct {
     int32_t slots;          /* batch slots the memory budget allowed */

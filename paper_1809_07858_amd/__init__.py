@@ -38,7 +38,10 @@ class Request(ctypes.Structure):
     _fields_ = [("reads", ctypes.c_void_p), ("words_per_read", ctypes.c_int32),
                 ("ref_offsets", ctypes.c_void_p), ("lengths", ctypes.c_void_p), ("E", ctypes.c_void_p),
                 ("out_accept", ctypes.c_void_p), ("out_popcount", ctypes.c_void_p),
-                ("n_pairs", ctypes.c_int64)]
+                ("n_pairs", ctypes.c_int64), ("flags", ctypes.c_uint32)]
+
+
+REQUEST_PINNED = 1
 
 
 class ServerStats(ctypes.Structure):
@@ -319,9 +322,12 @@ class Server:
         _check(lib().shouji_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
 
-    def submit(self, reads, ref_offsets, lengths, E, want_popcount=True):
+    def submit(self, reads, ref_offsets, lengths, E, want_popcount=True, pinned=False,
+               out_accept=None, out_popcount=None):
         """Queue a request.  reads: uint32 [n, words_per_read] (pack_pairs); ref_offsets int64,
-        lengths int32, E int32 (scalar or per pair).  Returns a Ticket."""
+        lengths int32, E int32 (scalar or per pair).  pinned=True declares that every buffer,
+        outputs included, is pinned host memory (e.g. numpy views of torch pin_memory tensors),
+        so the server moves it by DMA without staging.  Returns a Ticket."""
         reads = np.ascontiguousarray(reads, dtype=np.uint32)
         if reads.ndim != 2:
             raise ValueError("reads must be [n_pairs, words_per_read]")
@@ -331,10 +337,22 @@ class Server:
         Ep = np.ascontiguousarray(np.broadcast_to(np.asarray(E, dtype=np.int32), (n,)))
         if offs.shape != (n,) or lens.shape != (n,):
             raise ValueError("ref_offsets and lengths need one entry per pair")
-        acc = np.empty(n, dtype=np.uint8)
-        pc = np.empty(n, dtype=np.int16) if want_popcount else None
+        if pinned:
+            given = (reads, ref_offsets, lengths, E)
+            if (out_accept is None or (want_popcount and out_popcount is None)
+                    or any(not isinstance(g, np.ndarray) or a.ctypes.data != g.ctypes.data
+                           for g, a in zip(given, (reads, offs, lens, Ep)))):
+                raise ValueError("a pinned request passes contiguous uint32/int64/int32/int32 "
+                                 "arrays (per-pair E) and its own pinned outputs")
+        acc = np.empty(n, dtype=np.uint8) if out_accept is None else out_accept
+        pc = out_popcount if out_popcount is not None else (
+            np.empty(n, dtype=np.int16) if want_popcount else None)
+        if acc.shape != (n,) or acc.dtype != np.uint8 or (pc is not None and (
+                pc.shape != (n,) or pc.dtype != np.int16)):
+            raise ValueError("outputs must be uint8 / int16 arrays with one entry per pair")
         req = Request(reads.ctypes.data, max(1, reads.shape[1]), offs.ctypes.data, lens.ctypes.data,
-                      Ep.ctypes.data, acc.ctypes.data, None if pc is None else pc.ctypes.data, n)
+                      Ep.ctypes.data, acc.ctypes.data, None if pc is None else pc.ctypes.data, n,
+                      REQUEST_PINNED if pinned else 0)
         t = ctypes.c_uint64()
         _check(lib().shouji_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
         return Ticket(t.value, (reads, offs, lens, Ep), acc, pc)

@@ -216,9 +216,17 @@ void run_copies(const std::vector<CopyJob> &jobs, int threads) {
     for (std::thread &t : pool) t.join();
 }
 
-// Copy the slot's parts into its pinned staging buffers and enqueue the batch
-// on the slot's stream.  Runs without the server lock: the slot is marked busy
-// and its requests stay alive until all their parts are done.
+// A part whose request buffers are pinned and whose read rows have the
+// server's width moves by DMA straight between the request and the device.
+bool direct_part(const shouji_request &r, int nw) {
+    return (r.flags & SHOUJI_REQUEST_PINNED) && r.words_per_read == nw;
+}
+
+// Enqueue one batch on the slot's stream: parts in pageable memory are first
+// copied into the slot's pinned staging buffers (consecutive such parts then
+// move in one copy), pinned parts are copied directly.  Runs without the
+// server lock: the slot is marked busy and its requests stay alive until all
+// their pairs are delivered.
 int enqueue_batch(shouji_server *S, Slot &s) {
     const int nw = S->nw;
     std::vector<CopyJob> jobs;
@@ -226,30 +234,60 @@ int enqueue_batch(shouji_server *S, Slot &s) {
     for (const Part &pt : s.parts) {
         const shouji_request &r = pt.r->req;
         const int64_t c = pt.count, f = pt.first;
-        if (r.words_per_read == nw) {
-            jobs.push_back(CopyJob{s.h_reads + at * nw, r.reads + f * nw, (size_t)c * nw * 4});
-        } else {
-            const int cw = std::min(nw, (int)r.words_per_read);
-            for (int64_t k = 0; k < c; k++) {
-                uint32_t *dst = s.h_reads + (at + k) * nw;
-                memcpy(dst, r.reads + (f + k) * r.words_per_read, (size_t)cw * 4);
-                for (int w = cw; w < nw; w++) dst[w] = 0u;
+        if (!direct_part(r, nw)) {
+            if (r.words_per_read == nw) {
+                jobs.push_back(CopyJob{s.h_reads + at * nw, r.reads + f * nw, (size_t)c * nw * 4});
+            } else {
+                const int cw = std::min(nw, (int)r.words_per_read);
+                for (int64_t k = 0; k < c; k++) {
+                    uint32_t *dst = s.h_reads + (at + k) * nw;
+                    memcpy(dst, r.reads + (f + k) * r.words_per_read, (size_t)cw * 4);
+                    for (int w = cw; w < nw; w++) dst[w] = 0u;
+                }
             }
+            jobs.push_back(CopyJob{s.h_off + at, r.ref_offsets + f, (size_t)c * 8});
+            jobs.push_back(CopyJob{s.h_len + at, r.lengths + f, (size_t)c * 4});
+            jobs.push_back(CopyJob{s.h_E + at, r.E + f, (size_t)c * 4});
         }
-        jobs.push_back(CopyJob{s.h_off + at, r.ref_offsets + f, (size_t)c * 8});
-        jobs.push_back(CopyJob{s.h_len + at, r.lengths + f, (size_t)c * 4});
-        jobs.push_back(CopyJob{s.h_E + at, r.E + f, (size_t)c * 4});
         at += c;
     }
     run_copies(jobs, S->cfg.host_threads > 0 ? S->cfg.host_threads : kDefaultHostThreads);
+
     const int64_t n = s.pairs;
     hipStream_t st = s.stream;
-    bool good = hipMemcpyAsync(s.d_reads_pm, s.h_reads, (size_t)n * nw * 4, hipMemcpyHostToDevice, st) == hipSuccess &&
-                hipMemcpyAsync(s.d_off, s.h_off, (size_t)n * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
-                hipMemcpyAsync(s.d_len, s.h_len, (size_t)n * 4, hipMemcpyHostToDevice, st) == hipSuccess &&
-                hipMemcpyAsync(s.d_E, s.h_E, (size_t)n * 4, hipMemcpyHostToDevice, st) == hipSuccess;
+    bool good = true;
+    auto copy = [&](void *dst, const void *src, size_t bytes, hipMemcpyKind kind) {
+        if (good && bytes) good = hipMemcpyAsync(dst, src, bytes, kind, st) == hipSuccess;
+    };
+    // host -> device
+    int64_t run = -1;   // first pair of the current run of staged parts
+    auto flush_in = [&](int64_t e) {
+        if (run < 0) return;
+        const int64_t c = e - run;
+        copy(s.d_reads_pm + run * nw, s.h_reads + run * nw, (size_t)c * nw * 4, hipMemcpyHostToDevice);
+        copy(s.d_off + run, s.h_off + run, (size_t)c * 8, hipMemcpyHostToDevice);
+        copy(s.d_len + run, s.h_len + run, (size_t)c * 4, hipMemcpyHostToDevice);
+        copy(s.d_E + run, s.h_E + run, (size_t)c * 4, hipMemcpyHostToDevice);
+        run = -1;
+    };
+    at = 0;
+    for (const Part &pt : s.parts) {
+        const shouji_request &r = pt.r->req;
+        const int64_t c = pt.count, f = pt.first;
+        if (direct_part(r, nw)) {
+            flush_in(at);
+            copy(s.d_reads_pm + at * nw, r.reads + f * nw, (size_t)c * nw * 4, hipMemcpyHostToDevice);
+            copy(s.d_off + at, r.ref_offsets + f, (size_t)c * 8, hipMemcpyHostToDevice);
+            copy(s.d_len + at, r.lengths + f, (size_t)c * 4, hipMemcpyHostToDevice);
+            copy(s.d_E + at, r.E + f, (size_t)c * 4, hipMemcpyHostToDevice);
+        } else if (run < 0) {
+            run = at;
+        }
+        at += c;
+    }
+    flush_in(at);
     int rc = good ? SHOUJI_OK : SHOUJI_ERR_DEVICE;
-    if (good) {
+    if (rc == SHOUJI_OK) {
         const unsigned blocks = (unsigned)((n * nw + 255) / 256);
         hipLaunchKernelGGL(shouji::reads_to_word_major_kernel, dim3(blocks), dim3(256), 0, st, s.d_reads_pm,
                            nw, n, s.d_reads, nw, n);
@@ -260,10 +298,30 @@ int enqueue_batch(shouji_server *S, Slot &s) {
     if (rc == SHOUJI_OK)
         rc = shouji_filter_batched(s.d_reads, s.d_refs, s.d_len, s.d_E, s.d_acc, s.d_pc, n, S->cfg.max_len, n,
                                    s.d_ws, s.ws_bytes, nullptr, st);
-    if (rc == SHOUJI_OK &&
-        (hipMemcpyAsync(s.h_acc, s.d_acc, (size_t)n, hipMemcpyDeviceToHost, st) != hipSuccess ||
-         hipMemcpyAsync(s.h_pc, s.d_pc, (size_t)n * 2, hipMemcpyDeviceToHost, st) != hipSuccess))
-        rc = SHOUJI_ERR_DEVICE;
+    if (rc == SHOUJI_OK) {
+        // device -> host: staged runs into the slot, pinned parts in place
+        auto flush_out = [&](int64_t e) {
+            if (run < 0) return;
+            copy(s.h_acc + run, s.d_acc + run, (size_t)(e - run), hipMemcpyDeviceToHost);
+            copy(s.h_pc + run, s.d_pc + run, (size_t)(e - run) * 2, hipMemcpyDeviceToHost);
+            run = -1;
+        };
+        at = 0;
+        for (const Part &pt : s.parts) {
+            const shouji_request &r = pt.r->req;
+            const int64_t c = pt.count, f = pt.first;
+            if (direct_part(r, nw)) {
+                flush_out(at);
+                copy(r.out_accept + f, s.d_acc + at, (size_t)c, hipMemcpyDeviceToHost);
+                if (r.out_popcount) copy(r.out_popcount + f, s.d_pc + at, (size_t)c * 2, hipMemcpyDeviceToHost);
+            } else if (run < 0) {
+                run = at;
+            }
+            at += c;
+        }
+        flush_out(at);
+        if (!good) rc = SHOUJI_ERR_DEVICE;
+    }
     if (hipEventRecord(s.done, st) != hipSuccess && rc == SHOUJI_OK) rc = SHOUJI_ERR_DEVICE;
     return rc;
 }
@@ -318,8 +376,10 @@ void reaper_loop(shouji_server *S) {
         int64_t at = 0;
         for (const Part &pt : s.parts) {
             shouji_request &r = pt.r->req;
-            memcpy(r.out_accept + pt.first, s.h_acc + at, (size_t)pt.count);
-            if (r.out_popcount) memcpy(r.out_popcount + pt.first, s.h_pc + at, (size_t)pt.count * 2);
+            if (!direct_part(r, S->nw)) {
+                memcpy(r.out_accept + pt.first, s.h_acc + at, (size_t)pt.count);
+                if (r.out_popcount) memcpy(r.out_popcount + pt.first, s.h_pc + at, (size_t)pt.count * 2);
+            }
             at += pt.count;
         }
         const auto now = clk::now();

@@ -182,3 +182,40 @@ def test_memory_budget_sets_slots(sj, work):
         t = _submit(srv, work, 0, 20_000)
         acc, pc, _ = srv.wait(t)
     _expect(work, 0, 20_000, acc, pc)
+
+
+def _pinned(a):
+    t = torch.empty(a.shape, dtype=getattr(torch, {"uint32": "int32"}.get(a.dtype.name, a.dtype.name)),
+                    pin_memory=True)
+    v = t.numpy().view(a.dtype)
+    v[...] = a
+    return t, v
+
+
+def test_pinned_and_pageable_requests_share_batches(sj, work):
+    # pinned requests move by DMA in place, pageable ones through the staging
+    # buffers; alternating them puts both kinds in the same batches
+    p = work["p"]
+    cuts = _cuts(p.n, [3000, 1, 2500, 777, 5000, 64, 4096, 12_000])
+    keep = []
+    with _server(sj, work, slots=2, max_batch_pairs=6000) as srv:
+        tickets = []
+        for i, (lo, hi) in enumerate(cuts):
+            if i % 2 == 0:
+                bufs = [_pinned(a) for a in (work["reads"][lo:hi], work["off"][lo:hi],
+                                             p.lengths[lo:hi], p.E[lo:hi],
+                                             np.zeros(hi - lo, np.uint8), np.zeros(hi - lo, np.int16))]
+                keep.append(bufs)
+                r, o, L, E, a, c = [v for _, v in bufs]
+                tickets.append(srv.submit(r, o, L, E, pinned=True, out_accept=a, out_popcount=c))
+            else:
+                tickets.append(_submit(srv, work, lo, hi))
+        for (lo, hi), t in zip(cuts, tickets):
+            acc, pc, _ = srv.wait(t)
+            _expect(work, lo, hi, acc, pc)
+    with pytest.raises(ValueError):
+        srv2 = _server(sj, work, slots=1, max_batch_pairs=64)
+        try:
+            srv2.submit(work["reads"][:4], work["off"][:4], p.lengths[:4], p.E[:4], pinned=True)
+        finally:
+            srv2.close()
