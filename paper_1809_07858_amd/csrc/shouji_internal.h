@@ -146,8 +146,14 @@ inline int ring_slots(int Ee) {
     const int b = kHalf * (H0 + 1) + Ee;
     return a > b ? a : b;
 }
+// LDS of one wavefront: the pattern ring (+ mirror); the per-position masks
+// of the iteration's positions lo .. lo+kBlock+kCols+Ee-1; the bit planes of
+// the 32 lengths per lane (+ valid plane).  Lanes l and l+32 hold the same
+// pairs, so masks and length planes are stored once per pair lane.
+__host__ __device__ inline int mask_slots(int Ee) { return kBlock + kCols + Ee; }
 inline size_t plain_lds_wave_bytes(int Ee) {
-    return (size_t)(ring_slots(Ee) + kMirror) * kRingStride * 8 + (size_t)(kCols + Ee) * kWave * 4;
+    return (size_t)(ring_slots(Ee) + kMirror) * kRingStride * 8 + (size_t)mask_slots(Ee) * kPairLanes * 4 +
+           (size_t)(kLenBits + 1) * kPairLanes * 4;
 }
 
 __global__ void shouji_plain_kernel(PlainParams prm);

@@ -127,30 +127,31 @@ struct Winner {
 // One candidate diagonal d over one block: build 11 cells, count each
 // window's segment, and fold it into the running winner.  `rp` points at this
 // lane's ring entry for pattern position i0 - d; consecutive positions are
-// kRingStride entries apart.
+// kRingStride entries apart (all 11 entries are loaded before the first use).
 template <bool FIRST, bool MASKED>
 __device__ __forceinline__ void candidate(Winner &W, const uint2 *__restrict__ rp,
-                                          const uint32_t *__restrict__ nv, int lane, int i0,
-                                          int d, const uint32_t (&tl)[kCols],
-                                          const uint32_t (&th)[kCols]) {
+                                          const uint32_t *__restrict__ nv, int i0, int d,
+                                          const uint32_t (&tl)[kCols], const uint32_t (&th)[kCols]) {
+    uint2 pv[kCols];
+#pragma unroll
+    for (int t = 0; t < kCols; t++) pv[t] = rp[t * kRingStride];
     uint32_t cell[kCols];
 #pragma unroll
     for (int t = 0; t < kCols; t++) {
-        const uint2 pv = rp[t * kRingStride];
         // Eq. 1: mismatch iff either code bit differs
-        cell[t] = gate<kTTCell>(pv.x ^ tl[t], pv.y, th[t]);
+        cell[t] = gate<kTTCell>(pv[t].x ^ tl[t], pv[t].y, th[t]);
     }
     if (MASKED) {
         if (d < 0) {
             // pattern index j - d > j: the pattern side runs out first
-            const uint32_t *np = nv + (-d) * kWave + lane;
+            const uint32_t *np = nv + (-d) * kPairLanes;
 #pragma unroll
-            for (int t = 0; t < kCols; t++) cell[t] |= np[t * kWave];
+            for (int t = 0; t < kCols; t++) cell[t] |= np[t * kPairLanes];
         } else {
-            const uint32_t *np = nv + lane;
+            const uint32_t *np = nv;
 #pragma unroll
             for (int t = 0; t < kCols; t++) {
-                cell[t] |= np[t * kWave];
+                cell[t] |= np[t * kPairLanes];
                 if (i0 + t - d < 0) cell[t] = ~0u;  // before the pattern's start
             }
         }
@@ -206,43 +207,38 @@ __device__ __forceinline__ bool needs_mask(int d, int lo, int m_min) {
 
 template <bool FIRST>
 __device__ __forceinline__ void candidate_any(bool masked, Winner &W, const uint2 *__restrict__ rp,
-                                              const uint32_t *__restrict__ nv, int lane, int i0,
-                                              int d, const uint32_t (&tl)[kCols],
+                                              const uint32_t *__restrict__ nv, int i0, int d,
+                                              const uint32_t (&tl)[kCols],
                                               const uint32_t (&th)[kCols]) {
     if (masked)
-        candidate<FIRST, true>(W, rp, nv, lane, i0, d, tl, th);
+        candidate<FIRST, true>(W, rp, nv, i0, d, tl, th);
     else
-        candidate<FIRST, false>(W, rp, nv, lane, i0, d, tl, th);
+        candidate<FIRST, false>(W, rp, nv, i0, d, tl, th);
 }
 
 __device__ __forceinline__ void block_winners(Winner &W, const uint2 *__restrict__ ring,
-                                              const uint32_t *__restrict__ nv, int lane, int pl,
-                                              int i0, int sb, int Ee, int R, int lo, int m_min,
+                                              const uint32_t *__restrict__ nv, int pl, int i0,
+                                              int sb, int Ee, int R, int lo, int m_min,
                                               const uint32_t (&tl)[kCols],
                                               const uint32_t (&th)[kCols]) {
     // evaluation order L1, U1, L2, U2, ..., LE, UE, M; diagonal d reads the
     // pattern from position i0 - d, i.e. ring slot sb - d (mod R)
     if (Ee == 0) {
-        candidate_any<true>(needs_mask(0, lo, m_min), W, ring + sb * kRingStride + pl, nv, lane,
-                            i0, 0, tl, th);
+        candidate_any<true>(needs_mask(0, lo, m_min), W, ring + sb * kRingStride + pl, nv, i0, 0, tl, th);
         return;
     }
     int sL = sb + 1 == R ? 0 : sb + 1;
     int sU = sb == 0 ? R - 1 : sb - 1;
-    candidate_any<true>(needs_mask(-1, lo, m_min), W, ring + sL * kRingStride + pl, nv, lane, i0,
-                        -1, tl, th);
-    candidate_any<false>(needs_mask(1, lo, m_min), W, ring + sU * kRingStride + pl, nv, lane, i0,
-                         1, tl, th);
+    candidate_any<true>(needs_mask(-1, lo, m_min), W, ring + sL * kRingStride + pl, nv, i0, -1, tl, th);
+    candidate_any<false>(needs_mask(1, lo, m_min), W, ring + sU * kRingStride + pl, nv, i0, 1, tl, th);
     for (int k = 2; k <= Ee; k++) {
         sL = sL + 1 == R ? 0 : sL + 1;
         sU = sU == 0 ? R - 1 : sU - 1;
-        candidate_any<false>(needs_mask(-k, lo, m_min), W, ring + sL * kRingStride + pl, nv, lane,
-                             i0, -k, tl, th);
-        candidate_any<false>(needs_mask(k, lo, m_min), W, ring + sU * kRingStride + pl, nv, lane,
-                             i0, k, tl, th);
+        candidate_any<false>(needs_mask(-k, lo, m_min), W, ring + sL * kRingStride + pl, nv, i0, -k, tl,
+                             th);
+        candidate_any<false>(needs_mask(k, lo, m_min), W, ring + sU * kRingStride + pl, nv, i0, k, tl, th);
     }
-    candidate_any<false>(needs_mask(0, lo, m_min), W, ring + sb * kRingStride + pl, nv, lane, i0,
-                         0, tl, th);
+    candidate_any<false>(needs_mask(0, lo, m_min), W, ring + sb * kRingStride + pl, nv, i0, 0, tl, th);
 }
 
 // Shouji bit-vector update over the 8 windows of a block, then carry-save
@@ -323,10 +319,17 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     const int Ee = J.Ee;
     const int nmask = kCols + Ee;                      // mask entries per lane
     uint2 *ring = reinterpret_cast<uint2 *>(lds);
+    // masks of positions lo + s at nv[s * 32 + pl]; this half's block starts at s = 8 * half
     uint32_t *nv = lds + (R + kMirror) * kRingStride * 2;
+    uint32_t *nvh = nv + kBlock * half * kPairLanes + pl;
+    uint32_t *lbv = nv + mask_slots(Ee) * kPairLanes + pl;   // length bit planes
     const int64_t base = J.base;
     const int64_t n = J.n;
     const bool full = base + kPairsPerWave <= n;
+    // the low half reads pattern words, the high half text words (a select of
+    // the two addresses, not an indexed pair, so that it stays in registers)
+    const uint32_t *seq = reinterpret_cast<const uint32_t *>(
+        half ? reinterpret_cast<uintptr_t>(J.refs) : reinterpret_cast<uintptr_t>(J.reads));
 
     // ---- lengths: effective length per pair (0 for padding and invalid pairs),
     // bit kLenBits set for a valid pair
@@ -350,7 +353,7 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     {
         const int w = 0;
         if (w < nwords) {
-            const uint32_t *row = (half ? J.refs : J.reads) + base;
+            const uint32_t *row = seq + base;
             load_word(row, full, n - base, pl, raw0);
         } else {
 #pragma unroll
@@ -363,9 +366,10 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     const int m_min = lmax < 0 ? 0 : lmin;
     const bool uniform = (m_min == m_max);
     transpose32(lenw);                 // lenw[b] = bit b of the 32 lengths
-    uint32_t Lb[kLenBits + 1];         // length bits, then the valid-pair plane
+    // length bits, then the valid-pair plane, kept in LDS (read by the
+    // boundary masks and the output only)
 #pragma unroll
-    for (int b = 0; b <= kLenBits; b++) Lb[b] = lenw[b];
+    for (int b = 0; b <= kLenBits; b++) lbv[b * kPairLanes] = lenw[b];
 
     FsmState F;
     F.s0 = F.s1 = F.s2 = ~0u;
@@ -390,27 +394,25 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
 #pragma unroll
                 for (int b = 0; b < kLenBits; b++) {
                     const uint32_t sx = ((xpos >> b) & 1) ? ~0u : 0u;
-                    g = mux(sx, Lb[b] & g, Lb[b] | g);
+                    const uint32_t lb = lbv[b * kPairLanes];
+                    g = mux(sx, lb & g, lb | g);
                 }
                 inv = ~g;
             }
-            nv[s * kWave + lane] = inv;
+            nvh[s * kPairLanes] = inv;
         }
     };
 
     // One transpose pass: the low lane half turns pattern word pw into ring
     // entries (positions 16pw..16pw+15), the high half turns text word tw into
-    // planes left in raw (plane 2u = low code bit of position 16tw+u).  Words
-    // at or beyond `limit` are not read (zero planes).
+    // planes left in raw (plane 2u = low code bit of position 16tw+u).  A word
+    // outside [0, limit) is replaced by a valid one: its positions lie beyond
+    // every pair's length, where the masks override every cell, and a pattern
+    // word outside the range is not written to the ring.
     auto pass_load = [&](int pw, int tw, int limit, uint32_t (&raw)[32]) {
-        const int w = half ? tw : pw;
-        if (w >= 0 && w < limit) {
-            const uint32_t *row = (half ? J.refs : J.reads) + (int64_t)w * J.ld + base;
-            load_word(row, full, n - base, pl, raw);
-        } else {
-#pragma unroll
-            for (int k = 0; k < 32; k++) raw[k] = 0u;
-        }
+        const int w = min(max(half ? tw : pw, 0), limit - 1);
+        const uint32_t *row = seq + (int64_t)w * J.ld + base;
+        load_word(row, full, n - base, pl, raw);
     };
     auto pass_finish = [&](int pw, int limit, uint32_t (&raw)[32]) {
         transpose32(raw);
@@ -430,41 +432,46 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
         pass_finish(pw, nhalves, raw);
     };
 
-    // Text planes: Tw = the 11 positions (low, high plane) of this lane's
-    // block.  The low half's block 2j reads positions 0..10 of word j, the high
-    // half's block 2j+1 positions 8..15 of word j and 0..2 of word j+1.  The
-    // high half transposes every text word once; Tn keeps what the next
-    // iteration needs of the newest word: in the low half its positions 0..10
-    // (received by lane swaps), in the high half its positions 8..15.
-    uint32_t Tw[2 * kCols], Tn[2 * kCols];
-    // after a pass that left text word j+1 in the high half's raw, with Tn
-    // holding word j: set Tw for blocks 2j (low) and 2j+1 (high), Tn for word j+1
-    auto take_text = [&](const uint32_t (&raw)[32]) {
+    // Text planes of a block: the 11 positions (low, high plane) of this lane's
+    // block.  The low half's block 2j reads positions 0..10 of text word j, the
+    // high half's block 2j+1 positions 8..15 of word j and 0..2 of word j+1.
+    // The high half transposes every text word once and the low half receives
+    // what it needs by lane swaps.  Two arrays alternate between iterations:
+    // one holds the current block's planes; the other is started from the
+    // newest word (start_text) and completed one pass later (finish_text).
+    //
+    // start_text, from text word w in the high half's raw: low half <- its
+    // positions 0..10 (from the high half), high half <- its positions 8..15.
+    auto start_text = [&](uint32_t (&T)[2 * kCols], const uint32_t (&raw)[32]) {
 #pragma unroll
-        for (int t = 0; t < 2 * kCols; t++)
-            Tw[t] = (t < 2 * kBlock || !half) ? Tn[t] : raw[t - 2 * kBlock];
+        for (int t = 0; t < 2 * kBlock; t++)  // low lanes: raw[t] of the high half; high lanes: own raw[16+t]
+            T[t] = __builtin_amdgcn_permlane32_swap(raw[t], raw[2 * kBlock + t], false, false)[1];
 #pragma unroll
-        for (int t = 0; t < 2 * kCols; t++) {
-            const uint32_t lowv = from_half1(raw[t]);
-            Tn[t] = (half && t < 2 * kBlock) ? raw[2 * kBlock + t] : lowv;
-        }
+        for (int t = 2 * kBlock; t < 2 * kCols; t++) T[t] = from_half1(raw[t]);
+    };
+    // finish_text, from text word w+1 in the high half's raw: high half <- its
+    // positions 0..2 (the low half's planes are complete already).
+    auto finish_text = [&](uint32_t (&T)[2 * kCols], const uint32_t (&raw)[32]) {
+#pragma unroll
+        for (int t = 2 * kBlock; t < 2 * kCols; t++) T[t] = half ? raw[t - 2 * kBlock] : T[t];
     };
 
+    uint32_t TA[2 * kCols], TB[2 * kCols];
     if (nblocks > 0) {
-        // pattern words 0..H0 into the ring; text words 0 and 1 into Tn / Tw
+        // pattern words 0..H0 into the ring; text words 0 and 1
         uint32_t raw1[32];
         pass_finish(0, nhalves, raw0);
-#pragma unroll
-        for (int t = 0; t < 2 * kCols; t++) {
-            const uint32_t lowv = from_half1(raw0[t]);
-            Tn[t] = (half && t < 2 * kBlock) ? raw0[2 * kBlock + t] : lowv;
-        }
+        start_text(TA, raw0);
         pass(1, 1, raw1);
-        take_text(raw1);
+        finish_text(TA, raw1);
+        start_text(TB, raw1);
         for (int hp = 2; hp <= H0; hp++) pass(hp, -1, raw1);
     }
 
-    for (int j = 0; j < niter; j++) {
+    // Iteration j: blocks 2j (low half) and 2j+1 (high half) with text planes
+    // Tc; afterwards Tn (started from word j+1) is completed for iteration j+1
+    // and Tc is restarted from word j+2 for iteration j+2.
+    auto iteration = [&](int j, uint32_t (&Tc)[2 * kCols], uint32_t (&Tn)[2 * kCols]) {
         const int lo = kHalf * j;                       // first window of the iteration
         const int i0 = lo + kBlock * half;              // this lane's block
         const bool activeB = 2 * j + 1 < nblocks;       // the high half has a block
@@ -472,10 +479,10 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
         {
             uint32_t tl[kCols], th[kCols];
 #pragma unroll
-            for (int t = 0; t < kCols; t++) { tl[t] = Tw[2 * t]; th[t] = Tw[2 * t + 1]; }
+            for (int t = 0; t < kCols; t++) { tl[t] = Tc[2 * t]; th[t] = Tc[2 * t + 1]; }
             const int sb = i0 % R;
             if ((Ee > lo) || (lo + kBlock + kCols - 1 + Ee >= m_min)) fill_masks(i0);
-            block_winners(W, ring, nv, lane, pl, i0, sb, Ee, R, lo, m_min, tl, th);
+            block_winners(W, ring, nvh, pl, i0, sb, Ee, R, lo, m_min, tl, th);
         }
         // serial bit-vector update: block 2j on the low half, 2j+1 on the high
         if (half == 0) block_update(F, W);
@@ -487,9 +494,16 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
             // first needs, and text word j+2
             uint32_t raw[32];
             pass(j + 1 + H0, j + 2, raw);
-            take_text(raw);
+            finish_text(Tn, raw);
+            start_text(Tc, raw);
         }
+    };
+    int j = 0;
+    for (; j + 1 < niter; j += 2) {
+        iteration(j, TA, TB);
+        iteration(j + 1, TB, TA);
     }
+    if (j < niter) iteration(j, TA, TB);
 
     // ---- add the high half's ones counter to the low half's, then output
     uint32_t cnt[32];
@@ -509,7 +523,7 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     if (half == 1) return;
     // rows 16.. carry each pair's length and valid bit through the transpose
 #pragma unroll
-    for (int b = 11; b < 32; b++) cnt[b] = (b >= 16 && b <= 16 + kLenBits) ? Lb[b - 16] : 0u;
+    for (int b = 11; b < 32; b++) cnt[b] = (b >= 16 && b <= 16 + kLenBits) ? lbv[(b - 16) * kPairLanes] : 0u;
     transpose32(cnt);  // cnt[k]: ones of S over windows [0, 8*nblocks) | length << 16 | valid << 27
     const int nwin = nblocks * kBlock;
 #pragma unroll
