@@ -116,28 +116,32 @@ __device__ __forceinline__ int wave_min(int v) {
     return v;
 }
 
-// Running winner of the window search for the 8 windows of a block, one
-// register per plane and window: key planes (ones = K3 K2 K1, first bit K0)
-// and the segment's remaining bits Z1..Z3 (Z0 == K0).
+// Running winner of the window search for the NB windows of a block (8, or
+// 4 in a short last iteration), one register per plane and window: key
+// planes (ones = K3 K2 K1, first bit K0) and the segment's remaining bits
+// Z1..Z3 (Z0 == K0).
+template <int NB>
 struct Winner {
-    uint32_t K0[kBlock], K1[kBlock], K2[kBlock], K3[kBlock];
-    uint32_t Z1[kBlock], Z2[kBlock], Z3[kBlock];
+    uint32_t K0[NB], K1[NB], K2[NB], K3[NB];
+    uint32_t Z1[NB], Z2[NB], Z3[NB];
 };
 
-// One candidate diagonal d over one block: build 11 cells, count each
-// window's segment, and fold it into the running winner.  `rp` points at this
-// lane's ring entry for pattern position i0 - d; consecutive positions are
-// kRingStride entries apart (all 11 entries are loaded before the first use).
-template <bool FIRST, bool MASKED>
-__device__ __forceinline__ void candidate(Winner &W, const uint2 *__restrict__ rp,
+// One candidate diagonal d over one block of NB windows: build NB+3 cells,
+// count each window's segment, and fold it into the running winner.  `rp`
+// points at this lane's ring entry for pattern position i0 - d; consecutive
+// positions are kRingStride entries apart (all entries are loaded before the
+// first use).
+template <bool FIRST, bool MASKED, int NB>
+__device__ __forceinline__ void candidate(Winner<NB> &W, const uint2 *__restrict__ rp,
                                           const uint32_t *__restrict__ nv, int i0, int d,
-                                          const uint32_t (&tl)[kCols], const uint32_t (&th)[kCols]) {
-    uint2 pv[kCols];
+                                          const uint32_t (&tl)[NB + 3], const uint32_t (&th)[NB + 3]) {
+    constexpr int C = NB + 3;
+    uint2 pv[C];
 #pragma unroll
-    for (int t = 0; t < kCols; t++) pv[t] = rp[t * kRingStride];
-    uint32_t cell[kCols];
+    for (int t = 0; t < C; t++) pv[t] = rp[t * kRingStride];
+    uint32_t cell[C];
 #pragma unroll
-    for (int t = 0; t < kCols; t++) {
+    for (int t = 0; t < C; t++) {
         // Eq. 1: mismatch iff either code bit differs
         cell[t] = gate<kTTCell>(pv[t].x ^ tl[t], pv[t].y, th[t]);
     }
@@ -146,25 +150,25 @@ __device__ __forceinline__ void candidate(Winner &W, const uint2 *__restrict__ r
             // pattern index j - d > j: the pattern side runs out first
             const uint32_t *np = nv + (-d) * kPairLanes;
 #pragma unroll
-            for (int t = 0; t < kCols; t++) cell[t] |= np[t * kPairLanes];
+            for (int t = 0; t < C; t++) cell[t] |= np[t * kPairLanes];
         } else {
             const uint32_t *np = nv;
 #pragma unroll
-            for (int t = 0; t < kCols; t++) {
+            for (int t = 0; t < C; t++) {
                 cell[t] |= np[t * kPairLanes];
                 if (i0 + t - d < 0) cell[t] = ~0u;  // before the pattern's start
             }
         }
     }
     // 2-bit sums of neighbouring cells: x = exactly one is 1, a = both are 1
-    uint32_t x[kCols - 1], a[kCols - 1];
+    uint32_t x[C - 1], a[C - 1];
 #pragma unroll
-    for (int t = 0; t < kCols - 1; t++) {
+    for (int t = 0; t < C - 1; t++) {
         x[t] = cell[t] ^ cell[t + 1];
         a[t] = cell[t] & cell[t + 1];
     }
 #pragma unroll
-    for (int w = 0; w < kBlock; w++) {
+    for (int w = 0; w < NB; w++) {
         // ones of cells w..w+3 = pair sum (w) + pair sum (w+2): 3-bit r2 r1 r0
         const uint32_t r0 = x[w] ^ x[w + 2];
         const uint32_t u = x[w] & x[w + 2];
@@ -196,57 +200,64 @@ struct FsmState {
     uint32_t ones, twos, fours, e[8];    // carry-save ones counter of final S bits
 };
 
-// Window search of one block of 8 windows at i0 (sb = ring slot of i0): the
-// winner of every window over all 2E+1 diagonals.  A candidate whose cells
-// can leave the map in this iteration (lo = first window of the iteration's
-// two blocks, m_min = shortest length in the group) takes the masked path.
-__device__ __forceinline__ bool needs_mask(int d, int lo, int m_min) {
-    const int hi_col = lo + kBlock + kCols - 1;             // last text column read
+// A candidate whose cells can leave the map in this iteration takes the
+// masked path: lo = first window of the iteration, hi_col = last text column
+// the iteration reads, m_min = shortest length in the group.
+__device__ __forceinline__ bool needs_mask(int d, int lo, int hi_col, int m_min) {
     return (d > lo) || (hi_col >= m_min) || (hi_col - d >= m_min);
 }
 
-template <bool FIRST>
-__device__ __forceinline__ void candidate_any(bool masked, Winner &W, const uint2 *__restrict__ rp,
+template <bool FIRST, int NB>
+__device__ __forceinline__ void candidate_any(bool masked, Winner<NB> &W, const uint2 *__restrict__ rp,
                                               const uint32_t *__restrict__ nv, int i0, int d,
-                                              const uint32_t (&tl)[kCols],
-                                              const uint32_t (&th)[kCols]) {
+                                              const uint32_t (&tl)[NB + 3],
+                                              const uint32_t (&th)[NB + 3]) {
     if (masked)
-        candidate<FIRST, true>(W, rp, nv, i0, d, tl, th);
+        candidate<FIRST, true, NB>(W, rp, nv, i0, d, tl, th);
     else
-        candidate<FIRST, false>(W, rp, nv, i0, d, tl, th);
+        candidate<FIRST, false, NB>(W, rp, nv, i0, d, tl, th);
 }
 
-__device__ __forceinline__ void block_winners(Winner &W, const uint2 *__restrict__ ring,
+// Window search of one block of NB windows at i0 (sb = ring slot of i0): the
+// winner of every window over all 2E+1 diagonals.
+template <int NB>
+__device__ __forceinline__ void block_winners(Winner<NB> &W, const uint2 *__restrict__ ring,
                                               const uint32_t *__restrict__ nv, int pl, int i0,
-                                              int sb, int Ee, int R, int lo, int m_min,
-                                              const uint32_t (&tl)[kCols],
-                                              const uint32_t (&th)[kCols]) {
+                                              int sb, int Ee, int R, int lo, int hi_col, int m_min,
+                                              const uint32_t (&tl)[NB + 3],
+                                              const uint32_t (&th)[NB + 3]) {
     // evaluation order L1, U1, L2, U2, ..., LE, UE, M; diagonal d reads the
     // pattern from position i0 - d, i.e. ring slot sb - d (mod R)
     if (Ee == 0) {
-        candidate_any<true>(needs_mask(0, lo, m_min), W, ring + sb * kRingStride + pl, nv, i0, 0, tl, th);
+        candidate_any<true, NB>(needs_mask(0, lo, hi_col, m_min), W, ring + sb * kRingStride + pl, nv, i0,
+                                0, tl, th);
         return;
     }
     int sL = sb + 1 == R ? 0 : sb + 1;
     int sU = sb == 0 ? R - 1 : sb - 1;
-    candidate_any<true>(needs_mask(-1, lo, m_min), W, ring + sL * kRingStride + pl, nv, i0, -1, tl, th);
-    candidate_any<false>(needs_mask(1, lo, m_min), W, ring + sU * kRingStride + pl, nv, i0, 1, tl, th);
+    candidate_any<true, NB>(needs_mask(-1, lo, hi_col, m_min), W, ring + sL * kRingStride + pl, nv, i0,
+                            -1, tl, th);
+    candidate_any<false, NB>(needs_mask(1, lo, hi_col, m_min), W, ring + sU * kRingStride + pl, nv, i0,
+                             1, tl, th);
     for (int k = 2; k <= Ee; k++) {
         sL = sL + 1 == R ? 0 : sL + 1;
         sU = sU == 0 ? R - 1 : sU - 1;
-        candidate_any<false>(needs_mask(-k, lo, m_min), W, ring + sL * kRingStride + pl, nv, i0, -k, tl,
-                             th);
-        candidate_any<false>(needs_mask(k, lo, m_min), W, ring + sU * kRingStride + pl, nv, i0, k, tl, th);
+        candidate_any<false, NB>(needs_mask(-k, lo, hi_col, m_min), W, ring + sL * kRingStride + pl, nv,
+                                 i0, -k, tl, th);
+        candidate_any<false, NB>(needs_mask(k, lo, hi_col, m_min), W, ring + sU * kRingStride + pl, nv,
+                                 i0, k, tl, th);
     }
-    candidate_any<false>(needs_mask(0, lo, m_min), W, ring + sb * kRingStride + pl, nv, i0, 0, tl, th);
+    candidate_any<false, NB>(needs_mask(0, lo, hi_col, m_min), W, ring + sb * kRingStride + pl, nv, i0,
+                             0, tl, th);
 }
 
-// Shouji bit-vector update over the 8 windows of a block, then carry-save
-// accumulation of the 8 bits that became final.
-__device__ __forceinline__ void block_update(FsmState &F, const Winner &W) {
-    uint32_t o[kBlock];
+// Shouji bit-vector update over the NB windows of a block, then carry-save
+// accumulation of the NB bits that became final.
+template <int NB>
+__device__ __forceinline__ void block_update(FsmState &F, const Winner<NB> &W) {
+    uint32_t o[NB];
 #pragma unroll
-    for (int w = 0; w < kBlock; w++) {
+    for (int w = 0; w < NB; w++) {
         const uint32_t q0 = gate<kTTXor3>(F.s0, F.s1, F.s2);  // ones(S[i..i+2]) = q1 q0
         const uint32_t q1 = gate<kTTMaj>(F.s0, F.s1, F.s2);
         // c1 = (q1 q0) < (K2 K1)
@@ -270,10 +281,16 @@ __device__ __forceinline__ void block_update(FsmState &F, const Winner &W) {
     SHOUJI_CSA(t1, F.ones, F.ones, o[0], o[1])
     SHOUJI_CSA(t2, F.ones, F.ones, o[2], o[3])
     SHOUJI_CSA(f1, F.twos, F.twos, t1, t2)
-    SHOUJI_CSA(t1, F.ones, F.ones, o[4], o[5])
-    SHOUJI_CSA(t2, F.ones, F.ones, o[6], o[7])
-    SHOUJI_CSA(f2, F.twos, F.twos, t1, t2)
-    SHOUJI_CSA(g, F.fours, F.fours, f1, f2)
+    if constexpr (NB == 8) {
+        SHOUJI_CSA(t1, F.ones, F.ones, o[4], o[5])
+        SHOUJI_CSA(t2, F.ones, F.ones, o[6], o[7])
+        SHOUJI_CSA(f2, F.twos, F.twos, t1, t2)
+        SHOUJI_CSA(g, F.fours, F.fours, f1, f2)
+    } else {
+        static_assert(NB == 4, "blocks of 8 or 4 windows");
+        g = F.fours & f1;
+        F.fours ^= f1;
+    }
 #undef SHOUJI_CSA
 #pragma unroll
     for (int b = 0; b < 8; b++) {
@@ -317,7 +334,6 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     const int half = lane >> 5;
     const int pl = lane & (kPairLanes - 1);
     const int Ee = J.Ee;
-    const int nmask = kCols + Ee;                      // mask entries per lane
     uint2 *ring = reinterpret_cast<uint2 *>(lds);
     // masks of positions lo + s at nv[s * 32 + pl]; this half's block starts at s = 8 * half
     uint32_t *nv = lds + (R + kMirror) * kRingStride * 2;
@@ -382,9 +398,10 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     const int nhalves = (m_max + kHalf - 1) / kHalf;  // words holding positions < m_max
     const int H0 = (kBlock + kCols - 1 + Ee) / kHalf; // last pattern word iteration 0 reads
 
-    // per-lane "position is past the pair's end" masks, positions i0 .. i0+10+Ee
-    auto fill_masks = [&](int i0) {
-        for (int s = 0; s < nmask; s++) {
+    // per-lane "position is past the pair's end" masks of positions
+    // i0 .. i0+count-1, stored at dst[s * 32]
+    auto fill_masks = [&](int i0, uint32_t *dst, int count) {
+        for (int s = 0; s < count; s++) {
             const int xpos = i0 + s;
             uint32_t inv;
             if (uniform) {
@@ -399,7 +416,7 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
                 }
                 inv = ~g;
             }
-            nvh[s * kPairLanes] = inv;
+            dst[s * kPairLanes] = inv;
         }
     };
 
@@ -471,23 +488,25 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     // Iteration j: blocks 2j (low half) and 2j+1 (high half) with text planes
     // Tc; afterwards Tn (started from word j+1) is completed for iteration j+1
     // and Tc is restarted from word j+2 for iteration j+2.
+    // Every iteration but a short last one has two full blocks (its 16
+    // windows start below m_max - 8).
     auto iteration = [&](int j, uint32_t (&Tc)[2 * kCols], uint32_t (&Tn)[2 * kCols]) {
         const int lo = kHalf * j;                       // first window of the iteration
         const int i0 = lo + kBlock * half;              // this lane's block
-        const bool activeB = 2 * j + 1 < nblocks;       // the high half has a block
-        Winner W;
+        const int hi_col = lo + kBlock + kCols - 1;     // last text column read
+        Winner<kBlock> W;
         {
             uint32_t tl[kCols], th[kCols];
 #pragma unroll
             for (int t = 0; t < kCols; t++) { tl[t] = Tc[2 * t]; th[t] = Tc[2 * t + 1]; }
             const int sb = i0 % R;
-            if ((Ee > lo) || (lo + kBlock + kCols - 1 + Ee >= m_min)) fill_masks(i0);
-            block_winners(W, ring, nvh, pl, i0, sb, Ee, R, lo, m_min, tl, th);
+            if ((Ee > lo) || (hi_col + Ee >= m_min)) fill_masks(i0, nvh, kCols + Ee);
+            block_winners<kBlock>(W, ring, nvh, pl, i0, sb, Ee, R, lo, hi_col, m_min, tl, th);
         }
         // serial bit-vector update: block 2j on the low half, 2j+1 on the high
-        if (half == 0) block_update(F, W);
+        if (half == 0) block_update<kBlock>(F, W);
         F.s0 = from_half0(F.s0); F.s1 = from_half0(F.s1); F.s2 = from_half0(F.s2);
-        if (half == 1 && activeB) block_update(F, W);
+        if (half == 1) block_update<kBlock>(F, W);
         F.s0 = from_half1(F.s0); F.s1 = from_half1(F.s1); F.s2 = from_half1(F.s2);
         if (j + 1 < niter) {
             // after all reads of iteration j: the pattern word iteration j+1
@@ -498,12 +517,45 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
             start_text(Tc, raw);
         }
     };
+    // A last iteration with at most 8 windows left runs blocks of 4 windows:
+    // the low half's at lo, the high half's at lo+4 (if any window is left
+    // there).  Its text planes: the low half's positions 0..6 of word j are
+    // its own, the high half's positions 4..10 are the low half's.
+    auto short_iteration = [&](int j, const uint32_t (&Tc)[2 * kCols], bool activeB) {
+        constexpr int NB = 4, C = NB + 3;
+        const int lo = kHalf * j;
+        const int i0 = lo + NB * half;
+        uint32_t tl[C], th[C];
+#pragma unroll
+        for (int t = 0; t < C; t++) {
+            tl[t] = __builtin_amdgcn_permlane32_swap(Tc[2 * t], Tc[2 * t + 2 * NB], false, false)[0];
+            th[t] = __builtin_amdgcn_permlane32_swap(Tc[2 * t + 1], Tc[2 * t + 1 + 2 * NB], false, false)[0];
+        }
+        uint32_t *nvs = nv + NB * half * kPairLanes + pl;
+        fill_masks(i0, nvs, C + Ee);
+        Winner<NB> W;
+        block_winners<NB>(W, ring, nvs, pl, i0, i0 % R, Ee, R, lo, lo + NB + C - 1, m_min, tl, th);
+        if (half == 0) block_update<NB>(F, W);
+        F.s0 = from_half0(F.s0); F.s1 = from_half0(F.s1); F.s2 = from_half0(F.s2);
+        if (half == 1 && activeB) block_update<NB>(F, W);
+    };
+    const int rem = m_max - kHalf * (niter - 1);        // windows of the last iteration
+    const bool short_last = niter > 0 && rem <= kBlock;
+    const int nlong = niter - (short_last ? 1 : 0);
     int j = 0;
-    for (; j + 1 < niter; j += 2) {
+    for (; j + 1 < nlong; j += 2) {
         iteration(j, TA, TB);
         iteration(j + 1, TB, TA);
     }
-    if (j < niter) iteration(j, TA, TB);
+    if (j < nlong) iteration(j, TA, TB);
+    if (short_last) {
+        uint32_t Tl[2 * kCols];
+#pragma unroll
+        for (int t = 0; t < 2 * kCols; t++) Tl[t] = (nlong & 1) ? TB[t] : TA[t];
+        short_iteration(nlong, Tl, rem > 4);
+    }
+    // windows whose final S bit went into the counter
+    const int nwin = short_last ? kHalf * nlong + (rem > 4 ? kBlock : kBlock / 2) : kHalf * niter;
 
     // ---- add the high half's ones counter to the low half's, then output
     uint32_t cnt[32];
@@ -524,8 +576,7 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     // rows 16.. carry each pair's length and valid bit through the transpose
 #pragma unroll
     for (int b = 11; b < 32; b++) cnt[b] = (b >= 16 && b <= 16 + kLenBits) ? lbv[(b - 16) * kPairLanes] : 0u;
-    transpose32(cnt);  // cnt[k]: ones of S over windows [0, 8*nblocks) | length << 16 | valid << 27
-    const int nwin = nblocks * kBlock;
+    transpose32(cnt);  // cnt[k]: ones of S over windows [0, nwin) | length << 16 | valid << 27
 #pragma unroll
     for (int k = 0; k < 32; k++) {
         const int64_t p = base + (int64_t)k * kPairLanes + pl;
