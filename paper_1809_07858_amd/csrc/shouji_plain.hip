@@ -130,10 +130,10 @@ struct Winner {
 // count each window's segment, and fold it into the running winner.  `rp`
 // points at this lane's ring entry for pattern position i0 - d; consecutive
 // positions are kRingStride entries apart (all entries are loaded before the
-// first use).
-template <bool FIRST, bool MASKED, int NB>
+// first use).  `masked` (uniform): some cell may lie outside the map.
+template <bool FIRST, int NB>
 __device__ __forceinline__ void candidate(Winner<NB> &W, const uint2 *__restrict__ rp,
-                                          const uint32_t *__restrict__ nv, int i0, int d,
+                                          const uint32_t *__restrict__ nv, int i0, int d, bool masked,
                                           const uint32_t (&tl)[NB + 3], const uint32_t (&th)[NB + 3]) {
     constexpr int C = NB + 3;
     uint2 pv[C];
@@ -145,7 +145,7 @@ __device__ __forceinline__ void candidate(Winner<NB> &W, const uint2 *__restrict
         // Eq. 1: mismatch iff either code bit differs
         cell[t] = gate<kTTCell>(pv[t].x ^ tl[t], pv[t].y, th[t]);
     }
-    if (MASKED) {
+    if (masked) {
         if (d < 0) {
             // pattern index j - d > j: the pattern side runs out first
             const uint32_t *np = nv + (-d) * kPairLanes;
@@ -212,10 +212,7 @@ __device__ __forceinline__ void candidate_any(bool masked, Winner<NB> &W, const 
                                               const uint32_t *__restrict__ nv, int i0, int d,
                                               const uint32_t (&tl)[NB + 3],
                                               const uint32_t (&th)[NB + 3]) {
-    if (masked)
-        candidate<FIRST, true, NB>(W, rp, nv, i0, d, tl, th);
-    else
-        candidate<FIRST, false, NB>(W, rp, nv, i0, d, tl, th);
+    candidate<FIRST, NB>(W, rp, nv, i0, d, masked, tl, th);
 }
 
 // Window search of one block of NB windows at i0 (sb = ring slot of i0): the
@@ -376,8 +373,10 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
             for (int k = 0; k < 32; k++) raw0[k] = 0u;
         }
     }
-    lmin = wave_min(lmin);
-    lmax = wave_max(lmax);
+    // wave-uniform after the reductions: keep them in scalar registers so
+    // that every decision taken from them is a scalar branch
+    lmin = __builtin_amdgcn_readfirstlane(wave_min(lmin));
+    lmax = __builtin_amdgcn_readfirstlane(wave_max(lmax));
     const int m_max = lmax < 0 ? 0 : lmax;
     const int m_min = lmax < 0 ? 0 : lmin;
     const bool uniform = (m_min == m_max);
