@@ -344,9 +344,10 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     const uint32_t *seq = reinterpret_cast<const uint32_t *>(
         half ? reinterpret_cast<uintptr_t>(J.refs) : reinterpret_cast<uintptr_t>(J.reads));
 
-    // ---- lengths: effective length per pair (0 for padding and invalid pairs),
-    // bit kLenBits set for a valid pair
+    // ---- lengths: effective length per pair (0 for padding and invalid
+    // pairs) and the valid-pair plane (bit k: pair k has a length in range)
     uint32_t lenw[32];
+    uint32_t valid = 0u;
     int lmin = 0x7fffffff, lmax = -1;
     {
         const int32_t *lp = J.lengths ? J.lengths + base + pl : nullptr;
@@ -356,7 +357,8 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
             const bool in = full || (base + (int64_t)k * kPairLanes + pl < n);
             if (lp) m = in ? lp[k * kPairLanes] : -1;
             const bool ok = in && m >= 0 && m <= J.max_len;
-            lenw[k] = ok ? ((uint32_t)m | (1u << kLenBits)) : 0u;
+            lenw[k] = ok ? (uint32_t)m : 0u;
+            valid |= ok ? (1u << k) : 0u;
             if (ok) { lmin = min(lmin, m); lmax = max(lmax, m); }
         }
     }
@@ -380,11 +382,14 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     const int m_max = lmax < 0 ? 0 : lmax;
     const int m_min = lmax < 0 ? 0 : lmin;
     const bool uniform = (m_min == m_max);
-    transpose32(lenw);                 // lenw[b] = bit b of the 32 lengths
-    // length bits, then the valid-pair plane, kept in LDS (read by the
-    // boundary masks and the output only)
+    if (!uniform) {
+        // bit planes of the lengths, kept in LDS (read by the boundary masks
+        // and the output only); with one length for all valid pairs none are
+        // needed
+        transpose32(lenw);             // lenw[b] = bit b of the 32 lengths
 #pragma unroll
-    for (int b = 0; b <= kLenBits; b++) lbv[b * kPairLanes] = lenw[b];
+        for (int b = 0; b < kLenBits; b++) lbv[b * kPairLanes] = lenw[b];
+    }
 
     FsmState F;
     F.s0 = F.s1 = F.s2 = ~0u;
@@ -462,8 +467,11 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
 #pragma unroll
         for (int t = 0; t < 2 * kBlock; t++)  // low lanes: raw[t] of the high half; high lanes: own raw[16+t]
             T[t] = __builtin_amdgcn_permlane32_swap(raw[t], raw[2 * kBlock + t], false, false)[1];
+        // low lanes: raw[t] of the high half (the partner raw[t+6] is a
+        // position the block does not read, free to be overwritten)
 #pragma unroll
-        for (int t = 2 * kBlock; t < 2 * kCols; t++) T[t] = from_half1(raw[t]);
+        for (int t = 2 * kBlock; t < 2 * kCols; t++)
+            T[t] = __builtin_amdgcn_permlane32_swap(raw[t], raw[t + 6], false, false)[1];
     };
     // finish_text, from text word w+1 in the high half's raw: high half <- its
     // positions 0..2 (the low half's planes are complete already).
@@ -572,16 +580,19 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
         }
     }
     if (half == 1) return;
-    // rows 16.. carry each pair's length and valid bit through the transpose
+    // rows 16.. carry each pair's length (unless all valid pairs have
+    // length m_max) and valid bit through the transpose
 #pragma unroll
-    for (int b = 11; b < 32; b++) cnt[b] = (b >= 16 && b <= 16 + kLenBits) ? lbv[(b - 16) * kPairLanes] : 0u;
+    for (int b = 11; b < 32; b++)
+        cnt[b] = (b >= 16 && b < 16 + kLenBits && !uniform) ? lbv[(b - 16) * kPairLanes] : 0u;
+    cnt[16 + kLenBits] = valid;
     transpose32(cnt);  // cnt[k]: ones of S over windows [0, nwin) | length << 16 | valid << 27
 #pragma unroll
     for (int k = 0; k < 32; k++) {
         const int64_t p = base + (int64_t)k * kPairLanes + pl;
         if (!full && p >= n) continue;
         const uint32_t w = cnt[k];
-        const int m = (int)((w >> 16) & ((1u << kLenBits) - 1));
+        const int m = uniform ? m_max : (int)((w >> 16) & ((1u << kLenBits) - 1));
         uint8_t acc;
         int16_t pc;
         if (!((w >> (16 + kLenBits)) & 1u)) {
