@@ -63,7 +63,9 @@ typedef enum {
  *           0 <= j, j-d < m and read[j-d] == ref[j], else 1;
  *   Step 2: S = all ones; for each window i in [0, m) the segment of
  *           columns i..i+3 with the most zeros wins (ties: a leading zero,
- *           then the order lower 1, upper 1, ..., lower E, upper E, main);
+ *           then the order d = +1, -1, +2, -2, ..., +E, -E, 0: Algorithm 1
+ *           examines first the diagonal whose text index exceeds the
+ *           pattern index by j, i.e. d = +j);
  *           it is copied into S[i..i+3] if it has strictly more zeros;
  *   Step 3: popcount = ones of S over [0, m); accept = popcount <= E.
  *

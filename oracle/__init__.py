@@ -23,6 +23,12 @@ _lib = None
 READING_B = 0   # adopted reading (global key: zeros, then leading zero, then scan order)
 READING_A = 1   # sensitivity study only: main diagonal replaces on strictly more zeros
 
+# counting modes of the last step (Sec. 2.2.3; Suppl. Sec. 8, Fig. 6(c))
+GLOBAL = 0          # every one of S[0..m_T)
+LOCAL = 1           # without the runs of ones before the first and after the last zero
+GLOCAL_START = 2    # without the run of ones before the first zero
+GLOCAL_END = 3      # without the run of ones after the last zero
+
 
 def build():
     """Compile the oracle's C sources into _build/liboracle.so (gcc -O2, OpenMP)."""
@@ -45,6 +51,10 @@ def _load():
         lib.oracle_shouji_pair.argtypes = [vp, vp, i32, i32, i32, vp]
         lib.oracle_shouji_batch.restype = ctypes.c_int
         lib.oracle_shouji_batch.argtypes = [vp, vp, i64, vp, i64, i32, vp, i32, i32, vp, vp]
+        lib.oracle_shouji_pair2.restype = ctypes.c_int
+        lib.oracle_shouji_pair2.argtypes = [vp, i32, vp, i32, i32, i32, i32, vp]
+        lib.oracle_shouji_batch2.restype = ctypes.c_int
+        lib.oracle_shouji_batch2.argtypes = [vp, vp, i64, vp, vp, i64, i32, vp, i32, i32, vp, vp]
         lib.oracle_shouji_map_row.restype = ctypes.c_int
         lib.oracle_shouji_map_row.argtypes = [vp, vp, i32, i32, vp]
         lib.oracle_default_threads.restype = ctypes.c_int
@@ -82,6 +92,41 @@ def shouji_pair(P, T, E, reading=READING_B):
     if ones < 0:
         raise ValueError("bad arguments")
     return ones, "".join(str(int(b)) for b in S[:m])
+
+
+def shouji_pair2(P, T, E, mode=GLOBAL, reading=READING_B):
+    """Filter one pair of possibly different lengths (read P, reference T) with a
+    counting mode.  Returns (count, S over the reference's positions as a string)."""
+    P = codes(P) if isinstance(P, str) else _c(P, np.uint8)
+    T = codes(T) if isinstance(T, str) else _c(T, np.uint8)
+    mT = len(T)
+    S = np.zeros(max(mT, 1), dtype=np.uint8)
+    ones = _load().oracle_shouji_pair2(P.ctypes.data, len(P), T.ctypes.data, mT, int(E), int(mode),
+                                       reading, S.ctypes.data)
+    if ones < 0:
+        raise ValueError("bad arguments")
+    return ones, "".join(str(int(b)) for b in S[:mT])
+
+
+def shouji_batch2(P, T, read_lengths, ref_lengths, E=None, E_per_pair=None, mode=GLOBAL, nthreads=0):
+    """Batch of pairs with two lengths and a counting mode.  Returns (accept, count)."""
+    P = _c(P, np.uint8)
+    T = _c(T, np.uint8)
+    if P.shape != T.shape:
+        raise ValueError("P and T must share one [n, stride] shape")
+    LP = _c(read_lengths, np.int32)
+    LT = _c(ref_lengths, np.int32)
+    n, stride = P.shape
+    acc = np.empty(n, dtype=np.uint8)
+    pc = np.empty(n, dtype=np.int16)
+    Ep = None if E_per_pair is None else _c(E_per_pair, np.int32)
+    rc = _load().oracle_shouji_batch2(P.ctypes.data, T.ctypes.data, stride, LP.ctypes.data, LT.ctypes.data,
+                                      n, -1 if E is None else int(E),
+                                      None if Ep is None else Ep.ctypes.data, int(mode), nthreads,
+                                      acc.ctypes.data, pc.ctypes.data)
+    if rc != 0:
+        raise ValueError("bad arguments")
+    return acc, pc
 
 
 def map_row(P, T, d):

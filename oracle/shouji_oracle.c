@@ -23,11 +23,15 @@
  *  - Window search: every one of the 2E+1 diagonal segments is examined
  *    (Sec. 2.2.2); the winner has the most zeros, ties going to a segment
  *    that starts with a zero; remaining ties go to the earliest segment in
- *    Algorithm 1's evaluation order L1, U1, L2, U2, ..., LE, UE, M
- *    ("reading B").  Reading A (off-diagonals first, then the main diagonal
- *    replaces the winner only with strictly more zeros, as Algorithm 1's
- *    final comparison is written) is kept behind a flag for sensitivity
- *    studies only.
+ *    Algorithm 1's evaluation order ("reading B"): for j = 1..E the j-th
+ *    diagonal whose text index exceeds the pattern index by j (Algorithm 1
+ *    indexes the map by text row and pattern column and calls it the lower
+ *    one; it is d = +j here and "Upper Diagonal-j" in Fig. 6), then the one
+ *    with d = -j, and the main diagonal last.  Fig. 6(c)'s local count of 2
+ *    needs this order (the opposite order gives 3).  Reading A (off-diagonals
+ *    first, then the main diagonal replaces the winner only with strictly
+ *    more zeros, as Algorithm 1's final comparison is written) is kept behind
+ *    a flag for sensitivity studies only.
  *  - Shouji bit-vector update: copy the winner into S[i..i+3] only when it
  *    has strictly more zeros than S[i..i+3] (Algorithm 1's update test).
  *  - Decision: accept (1) iff the number of ones in S[0..m) is <= E
@@ -38,11 +42,16 @@
 #include <string.h>
 #include <omp.h>
 
-/* Neighbourhood map entry (Eq. 1) on diagonal d at text column j. */
-static int map_cell(const uint8_t *P, const uint8_t *T, int m, int d, int j) {
+/* Neighbourhood map entry (Eq. 1) on diagonal d at text column j, for a
+ * pattern of length mP and a text of length mT. */
+static int map_cell2(const uint8_t *P, int mP, const uint8_t *T, int mT, int d, int j) {
     int q = j - d;                         /* pattern index on this diagonal */
-    if (j < 0 || j >= m || q < 0 || q >= m) return 1;
+    if (j < 0 || j >= mT || q < 0 || q >= mP) return 1;
     return P[q] == T[j] ? 0 : 1;
+}
+
+static int map_cell(const uint8_t *P, const uint8_t *T, int m, int d, int j) {
+    return map_cell2(P, m, T, m, d, j);
 }
 
 /* One diagonal row of the map (Eq. 1): out[j] = cell (d, j) for j in [0, m). */
@@ -80,10 +89,10 @@ int oracle_shouji_pair(const uint8_t *P, const uint8_t *T, int32_t m, int32_t E,
     for (int i = 0; i < m; i++) {
         const uint8_t *Z = NULL;
         int best_key = -1;
-        /* off-diagonal candidates in evaluation order L1, U1, ..., LE, UE */
+        /* off-diagonal candidates in evaluation order d = +1, -1, ..., +E, -E */
         for (int k = 1; k <= E; k++) {
             for (int s = 0; s < 2; s++) {
-                int d = s == 0 ? -k : k;
+                int d = s == 0 ? k : -k;
                 const uint8_t *seg = N + (size_t)(d + E) * w + i;
                 int key = 2 * count_zeros(seg, 4) + (seg[0] == 0 ? 1 : 0);
                 if (key > best_key) { best_key = key; Z = seg; }
@@ -106,6 +115,95 @@ int oracle_shouji_pair(const uint8_t *P, const uint8_t *T, int32_t m, int32_t E,
     if (S_out) memcpy(S_out, S, (size_t)m);
     free(N); free(S);
     return ones;
+}
+
+/*
+ * Counting modes of the final step (Sec. 2.2.3: local filtering ignores the
+ * ones at both ends of the bit-vector, glocal filtering those at one end;
+ * Suppl. Sec. 8, Fig. 6(c)).  The ones "at an end" are the run of ones
+ * before the first zero (start) or after the last zero (end).  A vector
+ * without any zero keeps all its ones in every mode.
+ */
+enum { ORACLE_GLOBAL = 0, ORACLE_LOCAL = 1, ORACLE_GLOCAL_START = 2, ORACLE_GLOCAL_END = 3 };
+
+/*
+ * Filter one pair of possibly different lengths: pattern (read) P of length
+ * mP, text (reference) T of length mT.  The map has the text's mT columns,
+ * so there are mT windows and the bit-vector spans text positions [0, mT);
+ * cells whose pattern index leaves [0, mP) are mismatches, as above.  The
+ * steps are those of oracle_shouji_pair; only the final count depends on
+ * `mode`.  S_out (may be NULL) receives S[0..mT).  Returns the count.
+ */
+int oracle_shouji_pair2(const uint8_t *P, int32_t mP, const uint8_t *T, int32_t mT, int32_t E,
+                        int32_t mode, int32_t reading, uint8_t *S_out) {
+    if (mP < 0 || mT < 0 || E < 0 || mode < 0 || mode > 3) return -1;
+    int nd = 2 * E + 1, w = mT + 3;
+    uint8_t *N = (uint8_t *)malloc((size_t)nd * (size_t)w + 1);
+    uint8_t *S = (uint8_t *)malloc((size_t)w + 1);
+    for (int d = -E; d <= E; d++)
+        for (int j = 0; j < w; j++)
+            N[(size_t)(d + E) * w + j] = (uint8_t)map_cell2(P, mP, T, mT, d, j);
+    for (int j = 0; j < w; j++) S[j] = 1;
+    for (int i = 0; i < mT; i++) {
+        const uint8_t *Z = NULL;
+        int best_key = -1;
+        for (int k = 1; k <= E; k++) {
+            for (int s = 0; s < 2; s++) {
+                int d = s == 0 ? k : -k;
+                const uint8_t *seg = N + (size_t)(d + E) * w + i;
+                int key = 2 * count_zeros(seg, 4) + (seg[0] == 0 ? 1 : 0);
+                if (key > best_key) { best_key = key; Z = seg; }
+            }
+        }
+        const uint8_t *M = N + (size_t)E * w + i;
+        if (reading == 0) {
+            int key = 2 * count_zeros(M, 4) + (M[0] == 0 ? 1 : 0);
+            if (key > best_key) { best_key = key; Z = M; }
+        } else {
+            if (Z == NULL || count_zeros(M, 4) > count_zeros(Z, 4)) Z = M;
+        }
+        if (count_zeros(Z, 4) > count_zeros(S + i, 4))
+            for (int t = 0; t < 4; t++) S[i + t] = Z[t];
+    }
+    /* Step 3 with the counting mode: the range of positions whose ones count */
+    int first = -1, last = -1;
+    for (int j = 0; j < mT; j++)
+        if (S[j] == 0) { if (first < 0) first = j; last = j; }
+    int lo = 0, hi = mT;                    /* count over [lo, hi) */
+    if (first >= 0) {
+        if (mode == ORACLE_LOCAL || mode == ORACLE_GLOCAL_START) lo = first;
+        if (mode == ORACLE_LOCAL || mode == ORACLE_GLOCAL_END) hi = last + 1;
+    }
+    int ones = 0;
+    for (int j = lo; j < hi; j++) ones += S[j];
+    if (S_out) memcpy(S_out, S, (size_t)mT);
+    free(N); free(S);
+    return ones;
+}
+
+/*
+ * Batch form of oracle_shouji_pair2: row p of P and T starts at p * stride;
+ * read_lengths[p] = mP, ref_lengths[p] = mT; a length outside [0, stride] or
+ * a negative threshold marks the pair invalid (0xFF / -1).
+ */
+int oracle_shouji_batch2(const uint8_t *P, const uint8_t *T, int64_t stride,
+                         const int32_t *read_lengths, const int32_t *ref_lengths, int64_t n,
+                         int32_t E, const int32_t *E_per_pair, int32_t mode, int32_t nthreads,
+                         uint8_t *out_accept, int16_t *out_popcount) {
+    if (n < 0 || stride < 0 || (E < 0 && !E_per_pair) || mode < 0 || mode > 3) return -1;
+    #pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : omp_get_max_threads())
+    for (int64_t p = 0; p < n; p++) {
+        int32_t mP = read_lengths[p], mT = ref_lengths[p], e = E_per_pair ? E_per_pair[p] : E;
+        if (mP < 0 || mP > stride || mT < 0 || mT > stride || e < 0) {
+            out_accept[p] = 0xFF;
+            if (out_popcount) out_popcount[p] = -1;
+            continue;
+        }
+        int ones = oracle_shouji_pair2(P + p * stride, mP, T + p * stride, mT, e, mode, 0, NULL);
+        out_accept[p] = (uint8_t)(ones <= e ? 1 : 0);
+        if (out_popcount) out_popcount[p] = (int16_t)ones;
+    }
+    return 0;
 }
 
 /*

@@ -19,7 +19,7 @@
 //  * pattern planes go to a per-lane ring in LDS (the diagonals need pattern
 //    positions up to E away from the text column); text planes stay in VGPRs;
 //  * windows are processed in blocks of 8.  For each candidate diagonal (in
-//    the order lower 1, upper 1, ..., lower E, upper E, main) the 11 cells of
+//    Algorithm 1's order d = +1, -1, ..., +E, -E, main) the 11 cells of
 //    the block's columns are built (XOR of code planes, OR of the two bits:
 //    Eq. 1), counted with 2-bit pair sums, and each window's segment is
 //    compared with the running winner by the key (ones, first bit) -- fewer
@@ -223,26 +223,28 @@ __device__ __forceinline__ void block_winners(Winner<NB> &W, const uint2 *__rest
                                               int sb, int Ee, int R, int lo, int hi_col, int m_min,
                                               const uint32_t (&tl)[NB + 3],
                                               const uint32_t (&th)[NB + 3]) {
-    // evaluation order L1, U1, L2, U2, ..., LE, UE, M; diagonal d reads the
-    // pattern from position i0 - d, i.e. ring slot sb - d (mod R)
+    // evaluation order (Algorithm 1): d = +1, -1, +2, -2, ..., +E, -E, then
+    // the main diagonal (d > 0: text index exceeds pattern index by d, the
+    // diagonal Algorithm 1 calls lower j, drawn as upper in Fig. 6); diagonal
+    // d reads the pattern from position i0 - d, i.e. ring slot sb - d (mod R)
     if (Ee == 0) {
         candidate_any<true, NB>(needs_mask(0, lo, hi_col, m_min), W, ring + sb * kRingStride + pl, nv, i0,
                                 0, tl, th);
         return;
     }
-    int sL = sb + 1 == R ? 0 : sb + 1;
-    int sU = sb == 0 ? R - 1 : sb - 1;
-    candidate_any<true, NB>(needs_mask(-1, lo, hi_col, m_min), W, ring + sL * kRingStride + pl, nv, i0,
-                            -1, tl, th);
-    candidate_any<false, NB>(needs_mask(1, lo, hi_col, m_min), W, ring + sU * kRingStride + pl, nv, i0,
-                             1, tl, th);
+    int sP = sb == 0 ? R - 1 : sb - 1;   // slot of d = +k
+    int sN = sb + 1 == R ? 0 : sb + 1;   // slot of d = -k
+    candidate_any<true, NB>(needs_mask(1, lo, hi_col, m_min), W, ring + sP * kRingStride + pl, nv, i0, 1,
+                            tl, th);
+    candidate_any<false, NB>(needs_mask(-1, lo, hi_col, m_min), W, ring + sN * kRingStride + pl, nv, i0,
+                             -1, tl, th);
     for (int k = 2; k <= Ee; k++) {
-        sL = sL + 1 == R ? 0 : sL + 1;
-        sU = sU == 0 ? R - 1 : sU - 1;
-        candidate_any<false, NB>(needs_mask(-k, lo, hi_col, m_min), W, ring + sL * kRingStride + pl, nv,
-                                 i0, -k, tl, th);
-        candidate_any<false, NB>(needs_mask(k, lo, hi_col, m_min), W, ring + sU * kRingStride + pl, nv,
+        sP = sP == 0 ? R - 1 : sP - 1;
+        sN = sN + 1 == R ? 0 : sN + 1;
+        candidate_any<false, NB>(needs_mask(k, lo, hi_col, m_min), W, ring + sP * kRingStride + pl, nv,
                                  i0, k, tl, th);
+        candidate_any<false, NB>(needs_mask(-k, lo, hi_col, m_min), W, ring + sN * kRingStride + pl, nv,
+                                 i0, -k, tl, th);
     }
     candidate_any<false, NB>(needs_mask(0, lo, hi_col, m_min), W, ring + sb * kRingStride + pl, nv, i0,
                              0, tl, th);

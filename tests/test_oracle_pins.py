@@ -190,9 +190,11 @@ def _matrix_shouji(Pseq, Tseq, E):
     Window w covers text columns w..w+3.  A diagonal is the set of cells with
     c - r = k; its 4-bit segment in window w is the cells (c - k, c) for the
     4 columns, cells outside the map being 1.  The winner has the most zeros,
-    then a leading zero, then comes first in the order lower 1, upper 1, ...,
-    lower E, upper E, main.  S[w..w+3] takes the winner if it has strictly
-    more zeros.
+    then a leading zero, then comes first in Algorithm 1's order: for j = 1..E
+    its "lower" diagonal j, whose text index exceeds the pattern index by j
+    (Algorithm 1 indexes the map by text row, pattern column: k = +j here),
+    before its "upper" diagonal j (k = -j), and the main diagonal last.
+    S[w..w+3] takes the winner if it has strictly more zeros.
     """
     m = len(Tseq)
     Nmat = [[1] * m for _ in range(m)]
@@ -209,7 +211,7 @@ def _matrix_shouji(Pseq, Tseq, E):
 
     names = []
     for k in range(1, E + 1):
-        names += [-k, k]
+        names += [k, -k]
     names.append(0)
     S = [1] * (m + 3)
     for w in range(m):
