@@ -86,6 +86,44 @@ int shouji_filter(const uint32_t *reads, const uint32_t *refs, const int32_t *le
                   int64_t n_pairs, int32_t max_len, int64_t ld, void *stream);
 
 /*
+ * Two-length form: reads and reference segments of different lengths, and
+ * local or glocal counting.
+ *
+ * Sec. 2.2.3 (local filtering leaves out the ones at both ends of the Shouji
+ * bit-vector, glocal filtering those at one end), Suppl. Sec. 8 and Fig. 6(c)
+ * (a read shorter than its reference segment).  Per pair p with read length
+ * mP = read_lengths[p] and reference length mT = ref_lengths[p]:
+ *   Step 1: cell (d, j) for text (reference) column j in [0, mT) is 0 iff
+ *           0 <= j-d < mP and read[j-d] == ref[j], else 1;
+ *   Step 2: as for shouji_filter, over the mT windows of the reference;
+ *   Step 3: count the ones of S over [0, mT), leaving out, when S has a
+ *           zero, the ones before its first zero (modes LOCAL and
+ *           GLOCAL_START) and after its last zero (LOCAL and GLOCAL_END);
+ *           a vector without zeros keeps all its ones.  accept = count <= E.
+ * With mP == mT and mode GLOBAL the results equal shouji_filter's.
+ *
+ *   read_lengths, ref_lengths  n_pairs lengths each (device, required); a
+ *                 pair with either length outside [0, max_len] gets the
+ *                 sentinels 0xFF / -1.
+ *   mode          one of shouji_count_mode; else SHOUJI_ERR_ARG.
+ *   max_len       the longest of all read and reference lengths; both
+ *                 sequences of a pair hold ceil(max_len/16) words.
+ *   other arguments and errors as for shouji_filter (out_popcount receives
+ *                 the count of the chosen mode).
+ */
+typedef enum {
+    SHOUJI_COUNT_GLOBAL = 0,       /* every one of S[0..mT)                     */
+    SHOUJI_COUNT_LOCAL = 1,        /* without the ones at both ends             */
+    SHOUJI_COUNT_GLOCAL_START = 2, /* without the ones before the first zero    */
+    SHOUJI_COUNT_GLOCAL_END = 3    /* without the ones after the last zero      */
+} shouji_count_mode;
+
+int shouji_filter_local(const uint32_t *reads, const uint32_t *refs, const int32_t *read_lengths,
+                        const int32_t *ref_lengths, int32_t E, int32_t mode, uint8_t *out_accept,
+                        int16_t *out_popcount, int64_t n_pairs, int32_t max_len, int64_t ld,
+                        void *stream);
+
+/*
  * Batched form: mixed lengths and one edit threshold per pair in one pass.
  *
  * Same filter as shouji_filter (Sec. 2.2, Eq. 1, Algorithm 1) applied to every

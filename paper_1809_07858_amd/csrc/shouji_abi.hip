@@ -105,6 +105,59 @@ extern "C" int shouji_filter(const uint32_t *reads, const uint32_t *refs, const 
     return ok();
 }
 
+extern "C" int shouji_filter_local(const uint32_t *reads, const uint32_t *refs, const int32_t *read_lengths,
+                                   const int32_t *ref_lengths, int32_t E, int32_t mode, uint8_t *out_accept,
+                                   int16_t *out_popcount, int64_t n_pairs, int32_t max_len, int64_t ld,
+                                   void *stream) {
+    if (n_pairs < 0) return fail(SHOUJI_ERR_ARG, "n_pairs < 0 (%lld)", (long long)n_pairs);
+    if (E < 0) return fail(SHOUJI_ERR_ARG, "E < 0 (%d)", E);
+    if (mode < SHOUJI_COUNT_GLOBAL || mode > SHOUJI_COUNT_GLOCAL_END)
+        return fail(SHOUJI_ERR_ARG, "counting mode %d is not one of 0..3", mode);
+    if (max_len < 0 || max_len > SHOUJI_MAX_LEN)
+        return fail(SHOUJI_ERR_RANGE, "max_len %d outside [0, %d]", max_len, SHOUJI_MAX_LEN);
+    const int32_t Ee = max_len > 0 ? (E < max_len - 1 ? E : max_len - 1) : 0;
+    if (Ee > SHOUJI_MAX_E)
+        return fail(SHOUJI_ERR_RANGE, "E %d (clamped %d) above the supported maximum %d", E, Ee,
+                    SHOUJI_MAX_E);
+    if (n_pairs == 0) return ok();
+    if (!reads || !refs || !out_accept || !read_lengths || !ref_lengths)
+        return fail(SHOUJI_ERR_NULL, "reads, refs, both length arrays and out_accept are required");
+    if (ld < n_pairs) return fail(SHOUJI_ERR_ARG, "ld %lld < n_pairs %lld", (long long)ld, (long long)n_pairs);
+
+    shouji::LocalParams prm;
+    prm.reads = reads;
+    prm.refs = refs;
+    prm.ld = ld;
+    prm.read_lengths = read_lengths;
+    prm.ref_lengths = ref_lengths;
+    prm.max_len = max_len;
+    prm.E = E;
+    prm.Ee = Ee;
+    prm.R = shouji::ring_slots(Ee);
+    prm.mode = mode;
+    prm.out_accept = out_accept;
+    prm.out_popcount = out_popcount;
+    prm.n = n_pairs;
+    // As many wavefronts per CU as LDS allows, up to two per SIMD: workgroups
+    // of four wavefronts when two of them fit, else of one.
+    const size_t wave_lds = shouji::local_lds_wave_bytes(Ee);
+    if (wave_lds > shouji::kLdsPerCU) return fail(SHOUJI_ERR_RANGE, "E %d needs more LDS than one CU holds", E);
+    const int wpg = 8 * wave_lds <= shouji::kLdsPerCU ? shouji::kWavesPerGroup : 1;
+    const size_t lds = wave_lds * wpg;
+    const int64_t waves = (n_pairs + shouji::kPairsPerWave - 1) / shouji::kPairsPerWave;
+    const int64_t grid = (waves + wpg - 1) / wpg;
+    if (grid > 0x7fffffff) return fail(SHOUJI_ERR_ARG, "n_pairs too large");
+    prm.waves_per_group = wpg;
+    prm.lds_wave_bytes = (int32_t)wave_lds;
+    static size_t lds_limit = 0;
+    if (int rc = raise_lds_limit((const void *)shouji::shouji_local_kernel, lds_limit, lds)) return rc;
+    hipLaunchKernelGGL(shouji::shouji_local_kernel, dim3((unsigned)grid), dim3(shouji::kWave * wpg), lds,
+                       (hipStream_t)stream, prm);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SHOUJI_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
 // ---------------------------------------------------------------- batched form
 
 namespace {

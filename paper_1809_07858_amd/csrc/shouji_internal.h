@@ -32,6 +32,26 @@ struct PlainParams {
     int32_t lds_wave_bytes;  // LDS bytes owned by one wavefront
 };
 
+// Two-length form: reads and references of different lengths, with a
+// counting mode (global, local, glocal at the start or at the end).
+struct LocalParams {
+    const uint32_t *reads;
+    const uint32_t *refs;
+    int64_t ld;
+    const int32_t *read_lengths;
+    const int32_t *ref_lengths;
+    int32_t max_len;
+    int32_t E;
+    int32_t Ee;
+    int32_t R;
+    int32_t mode;
+    int32_t waves_per_group;
+    uint8_t *out_accept;
+    int16_t *out_popcount;
+    int64_t n;
+    int32_t lds_wave_bytes;
+};
+
 // ---- batched form
 constexpr int kMaxE = 31;                     // largest E (after clamping to m-1)
 constexpr int kBinE = kMaxE + 1;              // E values per length bucket
@@ -107,7 +127,9 @@ struct GroupJob {
     const uint32_t *reads;
     const uint32_t *refs;
     int64_t ld;
-    const int32_t *lengths;   // or null: every pair has max_len bases
+    const int32_t *lengths;   // or null: every pair has max_len bases (read lengths in the two-length form)
+    const int32_t *ref_lengths;  // two-length form only: reference (text) lengths
+    int32_t mode;             // two-length form only: counting mode
     int32_t max_len;
     int32_t Ee;               // diagonals built on each side
     int32_t E;                // decision threshold when Edec is null
@@ -151,12 +173,22 @@ inline int ring_slots(int Ee) {
 // the 32 lengths per lane (+ valid plane).  Lanes l and l+32 hold the same
 // pairs, so masks and length planes are stored once per pair lane.
 __host__ __device__ inline int mask_slots(int Ee) { return kBlock + kCols + Ee; }
+// two-length form: pattern-position masks cover lo - Ee .. lo + 18 + Ee
+__host__ __device__ inline int pattern_mask_slots(int Ee) { return kBlock + kCols + 2 * Ee; }
 inline size_t plain_lds_wave_bytes(int Ee) {
     return (size_t)(ring_slots(Ee) + kMirror) * kRingStride * 8 + (size_t)mask_slots(Ee) * kPairLanes * 4 +
            (size_t)(kLenBits + 1) * kPairLanes * 4;
 }
 
+// LDS of one wavefront in the two-length form: ring, text masks, pattern
+// masks, and the bit planes of both lengths.
+inline size_t local_lds_wave_bytes(int Ee) {
+    return (size_t)(ring_slots(Ee) + kMirror) * kRingStride * 8 + (size_t)mask_slots(Ee) * kPairLanes * 4 +
+           (size_t)pattern_mask_slots(Ee) * kPairLanes * 4 + (size_t)(2 * kLenBits) * kPairLanes * 4;
+}
+
 __global__ void shouji_plain_kernel(PlainParams prm);
+__global__ void shouji_local_kernel(LocalParams prm);
 __global__ void shouji_tiles_kernel(TilesParams prm);
 __global__ void fill_i32_kernel(int32_t *p, int64_t n, int32_t v);
 __global__ void bin_count_kernel(const int32_t *lengths, const int32_t *Ep, int64_t n, int max_len,

@@ -60,6 +60,7 @@ constexpr unsigned kTTNor = truth_table([](int a, int b, int) { return !(a | b);
 constexpr unsigned kTTOrNotA = truth_table([](int a, int b, int) { return !a || b; });
 constexpr unsigned kTTMux = truth_table([](int a, int b, int c) { return a ? b : c; });
 constexpr unsigned kTTOr3 = truth_table([](int a, int b, int c) { return a | b | c; });
+constexpr unsigned kTTAnd3 = truth_table([](int a, int b, int c) { return a & b & c; });
 
 template <unsigned TT>
 __device__ __forceinline__ uint32_t gate(uint32_t a, uint32_t b, uint32_t c) {
@@ -130,10 +131,13 @@ struct Winner {
 // count each window's segment, and fold it into the running winner.  `rp`
 // points at this lane's ring entry for pattern position i0 - d; consecutive
 // positions are kRingStride entries apart (all entries are loaded before the
-// first use).  `masked` (uniform): some cell may lie outside the map.
-template <bool FIRST, int NB>
+// first use).  `masked` (uniform): some cell may lie outside the map.  With
+// one length per pair, nv[s] masks position i0+s; with two (TWO), nv[s]
+// masks text position i0+s and nvp[s] pattern position i0-Ee+s.
+template <bool FIRST, int NB, bool TWO>
 __device__ __forceinline__ void candidate(Winner<NB> &W, const uint2 *__restrict__ rp,
-                                          const uint32_t *__restrict__ nv, int i0, int d, bool masked,
+                                          const uint32_t *__restrict__ nv, const uint32_t *__restrict__ nvp,
+                                          int Ee, int i0, int d, bool masked,
                                           const uint32_t (&tl)[NB + 3], const uint32_t (&th)[NB + 3]) {
     constexpr int C = NB + 3;
     uint2 pv[C];
@@ -145,7 +149,13 @@ __device__ __forceinline__ void candidate(Winner<NB> &W, const uint2 *__restrict
         // Eq. 1: mismatch iff either code bit differs
         cell[t] = gate<kTTCell>(pv[t].x ^ tl[t], pv[t].y, th[t]);
     }
-    if (masked) {
+    if (masked && TWO) {
+        // text column i0+t past the reference, pattern position i0+t-d
+        // outside the read
+        const uint32_t *np = nvp + (Ee - d) * kPairLanes;
+#pragma unroll
+        for (int t = 0; t < C; t++) cell[t] |= nv[t * kPairLanes] | np[t * kPairLanes];
+    } else if (masked) {
         if (d < 0) {
             // pattern index j - d > j: the pattern side runs out first
             const uint32_t *np = nv + (-d) * kPairLanes;
@@ -207,19 +217,21 @@ __device__ __forceinline__ bool needs_mask(int d, int lo, int hi_col, int m_min)
     return (d > lo) || (hi_col >= m_min) || (hi_col - d >= m_min);
 }
 
-template <bool FIRST, int NB>
+template <bool FIRST, int NB, bool TWO>
 __device__ __forceinline__ void candidate_any(bool masked, Winner<NB> &W, const uint2 *__restrict__ rp,
-                                              const uint32_t *__restrict__ nv, int i0, int d,
+                                              const uint32_t *__restrict__ nv,
+                                              const uint32_t *__restrict__ nvp, int Ee, int i0, int d,
                                               const uint32_t (&tl)[NB + 3],
                                               const uint32_t (&th)[NB + 3]) {
-    candidate<FIRST, NB>(W, rp, nv, i0, d, masked, tl, th);
+    candidate<FIRST, NB, TWO>(W, rp, nv, nvp, Ee, i0, d, masked, tl, th);
 }
 
 // Window search of one block of NB windows at i0 (sb = ring slot of i0): the
 // winner of every window over all 2E+1 diagonals.
-template <int NB>
+template <int NB, bool TWO>
 __device__ __forceinline__ void block_winners(Winner<NB> &W, const uint2 *__restrict__ ring,
-                                              const uint32_t *__restrict__ nv, int pl, int i0,
+                                              const uint32_t *__restrict__ nv,
+                                              const uint32_t *__restrict__ nvp, int pl, int i0,
                                               int sb, int Ee, int R, int lo, int hi_col, int m_min,
                                               const uint32_t (&tl)[NB + 3],
                                               const uint32_t (&th)[NB + 3]) {
@@ -227,33 +239,87 @@ __device__ __forceinline__ void block_winners(Winner<NB> &W, const uint2 *__rest
     // the main diagonal (d > 0: text index exceeds pattern index by d, the
     // diagonal Algorithm 1 calls lower j, drawn as upper in Fig. 6); diagonal
     // d reads the pattern from position i0 - d, i.e. ring slot sb - d (mod R)
+    const uint2 *rb = ring + pl;
     if (Ee == 0) {
-        candidate_any<true, NB>(needs_mask(0, lo, hi_col, m_min), W, ring + sb * kRingStride + pl, nv, i0,
-                                0, tl, th);
+        candidate_any<true, NB, TWO>(needs_mask(0, lo, hi_col, m_min), W, rb + sb * kRingStride, nv, nvp, Ee,
+                                     i0, 0, tl, th);
         return;
     }
     int sP = sb == 0 ? R - 1 : sb - 1;   // slot of d = +k
     int sN = sb + 1 == R ? 0 : sb + 1;   // slot of d = -k
-    candidate_any<true, NB>(needs_mask(1, lo, hi_col, m_min), W, ring + sP * kRingStride + pl, nv, i0, 1,
-                            tl, th);
-    candidate_any<false, NB>(needs_mask(-1, lo, hi_col, m_min), W, ring + sN * kRingStride + pl, nv, i0,
-                             -1, tl, th);
+    candidate_any<true, NB, TWO>(needs_mask(1, lo, hi_col, m_min), W, rb + sP * kRingStride, nv, nvp, Ee, i0,
+                                 1, tl, th);
+    candidate_any<false, NB, TWO>(needs_mask(-1, lo, hi_col, m_min), W, rb + sN * kRingStride, nv, nvp, Ee,
+                                  i0, -1, tl, th);
     for (int k = 2; k <= Ee; k++) {
         sP = sP == 0 ? R - 1 : sP - 1;
         sN = sN + 1 == R ? 0 : sN + 1;
-        candidate_any<false, NB>(needs_mask(k, lo, hi_col, m_min), W, ring + sP * kRingStride + pl, nv,
-                                 i0, k, tl, th);
-        candidate_any<false, NB>(needs_mask(-k, lo, hi_col, m_min), W, ring + sN * kRingStride + pl, nv,
-                                 i0, -k, tl, th);
+        candidate_any<false, NB, TWO>(needs_mask(k, lo, hi_col, m_min), W, rb + sP * kRingStride, nv, nvp, Ee,
+                                      i0, k, tl, th);
+        candidate_any<false, NB, TWO>(needs_mask(-k, lo, hi_col, m_min), W, rb + sN * kRingStride, nv, nvp,
+                                      Ee, i0, -k, tl, th);
     }
-    candidate_any<false, NB>(needs_mask(0, lo, hi_col, m_min), W, ring + sb * kRingStride + pl, nv, i0,
-                             0, tl, th);
+    candidate_any<false, NB, TWO>(needs_mask(0, lo, hi_col, m_min), W, rb + sb * kRingStride, nv, nvp, Ee, i0,
+                                  0, tl, th);
+}
+
+// Where the zeros of the final bit-vector lie, for the local and glocal
+// counts (Sec. 2.2.3: the ones before the first and after the last zero are
+// not counted).  Each lane half tracks the blocks it updates.
+struct Ends {
+    uint32_t seen;                 // a final bit of this half's blocks was 0
+    uint32_t first[kLenBits];      // position of the first such zero (bit planes)
+    uint32_t last[kLenBits];       // position of the last such zero
+};
+
+// Fold the NB final bits o[] of positions start..start+NB-1 (start a
+// multiple of NB, uniform) into the tracker.
+template <int NB>
+__device__ __forceinline__ void track_ends(Ends &X, const uint32_t (&o)[NB], int start) {
+    constexpr int LB = NB == 8 ? 3 : 2;   // index bits within the block
+    uint32_t any, f[LB], l[LB];
+    if constexpr (NB == 8) {
+        const uint32_t all_lo = gate<kTTAnd3>(o[0], o[1], o[2]) & o[3];   // no zero in 0..3
+        const uint32_t all_hi = gate<kTTAnd3>(o[4], o[5], o[6]) & o[7];   // no zero in 4..7
+        any = ~(all_lo & all_hi);
+        // first zero: the quad, then the pair, then the bit
+        f[2] = all_lo;
+        uint32_t q[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) q[j] = mux(all_lo, o[4 + j], o[j]);
+        f[1] = q[0] & q[1];
+        f[0] = mux(f[1], q[2], q[0]);
+        // last zero: the quad, then the pair, then the bit
+        l[2] = ~all_hi;
+        uint32_t r[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) r[j] = mux(all_hi, o[j], o[4 + j]);
+        l[1] = ~(r[2] & r[3]);
+        l[0] = ~mux(l[1], r[3], r[1]);
+    } else {
+        static_assert(NB == 4, "blocks of 8 or 4 windows");
+        const uint32_t all = gate<kTTAnd3>(o[0], o[1], o[2]) & o[3];
+        any = ~all;
+        f[1] = o[0] & o[1];
+        f[0] = mux(f[1], o[2], o[0]);
+        l[1] = ~(o[2] & o[3]);
+        l[0] = ~mux(l[1], o[3], o[1]);
+    }
+    const uint32_t nf = any & ~X.seen;    // this block holds the first zero
+#pragma unroll
+    for (int b = 0; b < kLenBits; b++) {
+        const uint32_t sb = ((start >> b) & 1) ? ~0u : 0u;
+        X.first[b] = mux(nf, b < LB ? f[b < LB ? b : 0] : sb, X.first[b]);
+        X.last[b] = mux(any, b < LB ? l[b < LB ? b : 0] : sb, X.last[b]);
+    }
+    X.seen |= any;
 }
 
 // Shouji bit-vector update over the NB windows of a block, then carry-save
-// accumulation of the NB bits that became final.
-template <int NB>
-__device__ __forceinline__ void block_update(FsmState &F, const Winner<NB> &W) {
+// accumulation of the NB bits that became final (and, with TWO, the
+// positions of their zeros; the block starts at position `start`).
+template <int NB, bool TWO>
+__device__ __forceinline__ void block_update(FsmState &F, const Winner<NB> &W, Ends &X, int start) {
     uint32_t o[NB];
 #pragma unroll
     for (int w = 0; w < NB; w++) {
@@ -297,6 +363,7 @@ __device__ __forceinline__ void block_update(FsmState &F, const Winner<NB> &W) {
         F.e[b] ^= g;
         g = cy;
     }
+    if constexpr (TWO) track_ends<NB>(X, o, start);
 }
 
 // One 16-base word of 32 pairs (pair = base + 32k + pl for bit k) from row
@@ -329,15 +396,27 @@ __device__ __forceinline__ uint32_t from_half1(uint32_t v) {
 // block 2j, the 3-plane state S[i..i+2] moves to the high half with one lane
 // swap per plane, the high half updates block 2j+1 and hands the state back.
 // Both halves read one pattern ring in LDS.
+//
+// TWO: reads and references of different lengths (J.lengths = read lengths,
+// J.ref_lengths = reference lengths) and a counting mode (J.mode); the map
+// has the reference's columns, cells outside the read are mismatches, and
+// the ones before the first / after the last zero of the bit-vector can be
+// left out of the count (Sec. 2.2.3).
+template <bool TWO>
 __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, int R, int lane) {
     const int half = lane >> 5;
     const int pl = lane & (kPairLanes - 1);
     const int Ee = J.Ee;
     uint2 *ring = reinterpret_cast<uint2 *>(lds);
-    // masks of positions lo + s at nv[s * 32 + pl]; this half's block starts at s = 8 * half
+    // masks of (text) positions lo + s at nv[s * 32 + pl]; this half's block
+    // starts at s = 8 * half.  TWO: pattern-position masks of lo - Ee + s at
+    // nvp[s * 32 + pl], then the bit planes of the reference and read lengths.
     uint32_t *nv = lds + (R + kMirror) * kRingStride * 2;
     uint32_t *nvh = nv + kBlock * half * kPairLanes + pl;
-    uint32_t *lbv = nv + mask_slots(Ee) * kPairLanes + pl;   // length bit planes
+    uint32_t *nvp = nv + mask_slots(Ee) * kPairLanes;
+    uint32_t *nvph = nvp + kBlock * half * kPairLanes + pl;
+    uint32_t *lbv = (TWO ? nvp + pattern_mask_slots(Ee) * kPairLanes : nvp) + pl;   // length bit planes
+    uint32_t *lbvp = lbv + kLenBits * kPairLanes;                               // TWO: read lengths
     const int64_t base = J.base;
     const int64_t n = J.n;
     const bool full = base + kPairsPerWave <= n;
@@ -348,20 +427,34 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
 
     // ---- lengths: effective length per pair (0 for padding and invalid
     // pairs) and the valid-pair plane (bit k: pair k has a length in range)
-    uint32_t lenw[32];
+    // (TWO: lenw = reference lengths, lenr = read lengths)
+    uint32_t lenw[32], lenr[TWO ? 32 : 1];
     uint32_t valid = 0u;
-    int lmin = 0x7fffffff, lmax = -1;
+    int lmin = 0x7fffffff, lmax = -1, rmin = 0x7fffffff, rmax = -1;
     {
         const int32_t *lp = J.lengths ? J.lengths + base + pl : nullptr;
+        const int32_t *tp = TWO ? J.ref_lengths + base + pl : nullptr;
 #pragma unroll
         for (int k = 0; k < 32; k++) {
             int m = J.max_len;
             const bool in = full || (base + (int64_t)k * kPairLanes + pl < n);
             if (lp) m = in ? lp[k * kPairLanes] : -1;
-            const bool ok = in && m >= 0 && m <= J.max_len;
-            lenw[k] = ok ? (uint32_t)m : 0u;
-            valid |= ok ? (1u << k) : 0u;
-            if (ok) { lmin = min(lmin, m); lmax = max(lmax, m); }
+            if constexpr (TWO) {
+                const int mt = in ? tp[k * kPairLanes] : -1;
+                const bool ok = in && m >= 0 && m <= J.max_len && mt >= 0 && mt <= J.max_len;
+                lenw[k] = ok ? (uint32_t)mt : 0u;
+                lenr[k] = ok ? (uint32_t)m : 0u;
+                valid |= ok ? (1u << k) : 0u;
+                if (ok) {
+                    lmin = min(lmin, mt); lmax = max(lmax, mt);
+                    rmin = min(rmin, m); rmax = max(rmax, m);
+                }
+            } else {
+                const bool ok = in && m >= 0 && m <= J.max_len;
+                lenw[k] = ok ? (uint32_t)m : 0u;
+                valid |= ok ? (1u << k) : 0u;
+                if (ok) { lmin = min(lmin, m); lmax = max(lmax, m); }
+            }
         }
     }
     // the first words do not depend on the lengths: load them before waiting
@@ -381,9 +474,16 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     // that every decision taken from them is a scalar branch
     lmin = __builtin_amdgcn_readfirstlane(wave_min(lmin));
     lmax = __builtin_amdgcn_readfirstlane(wave_max(lmax));
+    if constexpr (TWO) {
+        rmin = __builtin_amdgcn_readfirstlane(wave_min(rmin));
+        rmax = __builtin_amdgcn_readfirstlane(wave_max(rmax));
+    }
+    // m_max: windows (the reference's positions); m_min: shortest of both
+    // sequences (below it no cell needs a mask); m_words: positions to load
     const int m_max = lmax < 0 ? 0 : lmax;
-    const int m_min = lmax < 0 ? 0 : lmin;
-    const bool uniform = (m_min == m_max);
+    const int m_min = lmax < 0 ? 0 : (TWO ? min(lmin, rmin) : lmin);
+    const int m_words = lmax < 0 ? 0 : (TWO ? max(lmax, rmax) : lmax);
+    const bool uniform = !TWO && (m_min == m_max);
     if (!uniform) {
         // bit planes of the lengths, kept in LDS (read by the boundary masks
         // and the output only); with one length for all valid pairs none are
@@ -391,6 +491,17 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
         transpose32(lenw);             // lenw[b] = bit b of the 32 lengths
 #pragma unroll
         for (int b = 0; b < kLenBits; b++) lbv[b * kPairLanes] = lenw[b];
+        if constexpr (TWO) {
+            transpose32(lenr);
+#pragma unroll
+            for (int b = 0; b < kLenBits; b++) lbvp[b * kPairLanes] = lenr[b];
+        }
+    }
+    Ends X;
+    if constexpr (TWO) {
+        X.seen = 0u;
+#pragma unroll
+        for (int b = 0; b < kLenBits; b++) X.first[b] = X.last[b] = 0u;
     }
 
     FsmState F;
@@ -401,28 +512,35 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
 
     const int nblocks = (m_max + kBlock - 1) / kBlock;
     const int niter = (nblocks + 1) / 2;
-    const int nhalves = (m_max + kHalf - 1) / kHalf;  // words holding positions < m_max
+    const int nhalves = (m_words + kHalf - 1) / kHalf;  // words holding positions < m_words
     const int H0 = (kBlock + kCols - 1 + Ee) / kHalf; // last pattern word iteration 0 reads
 
-    // per-lane "position is past the pair's end" masks of positions
-    // i0 .. i0+count-1, stored at dst[s * 32]
+    // "position xpos is past the pair's end" for the lengths whose bit planes
+    // are at planes[b * 32], bit-sliced over the 32 pairs
+    auto past_end = [&](int xpos, const uint32_t *planes) {
+        uint32_t g = 0u;  // g = (length > xpos)
+#pragma unroll
+        for (int b = 0; b < kLenBits; b++) {
+            const uint32_t sx = ((xpos >> b) & 1) ? ~0u : 0u;
+            const uint32_t lb = planes[b * kPairLanes];
+            g = mux(sx, lb & g, lb | g);
+        }
+        return ~g;
+    };
+    // per-lane masks of positions i0 .. i0+count-1, stored at dst[s * 32]
     auto fill_masks = [&](int i0, uint32_t *dst, int count) {
         for (int s = 0; s < count; s++) {
             const int xpos = i0 + s;
-            uint32_t inv;
-            if (uniform) {
-                inv = xpos >= m_max ? ~0u : 0u;
-            } else {
-                uint32_t g = 0u;  // g = (length > xpos), bit-sliced over the 32 pairs
-#pragma unroll
-                for (int b = 0; b < kLenBits; b++) {
-                    const uint32_t sx = ((xpos >> b) & 1) ? ~0u : 0u;
-                    const uint32_t lb = lbv[b * kPairLanes];
-                    g = mux(sx, lb & g, lb | g);
-                }
-                inv = ~g;
-            }
-            dst[s * kPairLanes] = inv;
+            dst[s * kPairLanes] = uniform ? (xpos >= m_max ? ~0u : 0u) : past_end(xpos, lbv);
+        }
+    };
+    // TWO: text masks of i0 .. i0+C-1 and pattern masks of i0-Ee .. i0+C-1+Ee
+    // (a negative pattern position is outside the read)
+    auto fill_masks2 = [&](int i0, uint32_t *dst, uint32_t *dstp, int C) {
+        for (int s = 0; s < C; s++) dst[s * kPairLanes] = past_end(i0 + s, lbv);
+        for (int s = 0; s < C + 2 * Ee; s++) {
+            const int xpos = i0 - Ee + s;
+            dstp[s * kPairLanes] = xpos < 0 ? ~0u : past_end(xpos, lbvp);
         }
     };
 
@@ -509,13 +627,18 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
 #pragma unroll
             for (int t = 0; t < kCols; t++) { tl[t] = Tc[2 * t]; th[t] = Tc[2 * t + 1]; }
             const int sb = i0 % R;
-            if ((Ee > lo) || (hi_col + Ee >= m_min)) fill_masks(i0, nvh, kCols + Ee);
-            block_winners<kBlock>(W, ring, nvh, pl, i0, sb, Ee, R, lo, hi_col, m_min, tl, th);
+            if ((Ee > lo) || (hi_col + Ee >= m_min)) {
+                if constexpr (TWO)
+                    fill_masks2(i0, nvh, nvph, kCols);
+                else
+                    fill_masks(i0, nvh, kCols + Ee);
+            }
+            block_winners<kBlock, TWO>(W, ring, nvh, nvph, pl, i0, sb, Ee, R, lo, hi_col, m_min, tl, th);
         }
         // serial bit-vector update: block 2j on the low half, 2j+1 on the high
-        if (half == 0) block_update<kBlock>(F, W);
+        if (half == 0) block_update<kBlock, TWO>(F, W, X, lo);
         F.s0 = from_half0(F.s0); F.s1 = from_half0(F.s1); F.s2 = from_half0(F.s2);
-        if (half == 1) block_update<kBlock>(F, W);
+        if (half == 1) block_update<kBlock, TWO>(F, W, X, lo + kBlock);
         F.s0 = from_half1(F.s0); F.s1 = from_half1(F.s1); F.s2 = from_half1(F.s2);
         if (j + 1 < niter) {
             // after all reads of iteration j: the pattern word iteration j+1
@@ -541,12 +664,16 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
             th[t] = __builtin_amdgcn_permlane32_swap(Tc[2 * t + 1], Tc[2 * t + 1 + 2 * NB], false, false)[0];
         }
         uint32_t *nvs = nv + NB * half * kPairLanes + pl;
-        fill_masks(i0, nvs, C + Ee);
+        uint32_t *nvps = nvp + NB * half * kPairLanes + pl;
+        if constexpr (TWO)
+            fill_masks2(i0, nvs, nvps, C);
+        else
+            fill_masks(i0, nvs, C + Ee);
         Winner<NB> W;
-        block_winners<NB>(W, ring, nvs, pl, i0, i0 % R, Ee, R, lo, lo + NB + C - 1, m_min, tl, th);
-        if (half == 0) block_update<NB>(F, W);
+        block_winners<NB, TWO>(W, ring, nvs, nvps, pl, i0, i0 % R, Ee, R, lo, lo + NB + C - 1, m_min, tl, th);
+        if (half == 0) block_update<NB, TWO>(F, W, X, lo);
         F.s0 = from_half0(F.s0); F.s1 = from_half0(F.s1); F.s2 = from_half0(F.s2);
-        if (half == 1 && activeB) block_update<NB>(F, W);
+        if (half == 1 && activeB) block_update<NB, TWO>(F, W, X, lo + NB);
     };
     const int rem = m_max - kHalf * (niter - 1);        // windows of the last iteration
     const bool short_last = niter > 0 && rem <= kBlock;
@@ -581,6 +708,34 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
             cnt[b] = s_;
         }
     }
+    // TWO: the zeros' first and last positions over both halves' blocks
+    uint32_t pos[TWO ? 32 : 1];
+    if constexpr (TWO) {
+        uint32_t fh[kLenBits], lh[kLenBits];
+        const uint32_t seen_h = from_half1(X.seen);
+#pragma unroll
+        for (int b = 0; b < kLenBits; b++) { fh[b] = from_half1(X.first[b]); lh[b] = from_half1(X.last[b]); }
+        // fh < first and last < lh: borrow chains from the low bit
+        uint32_t flt = gate<kTTAndNotA>(fh[0], X.first[0], X.first[0]);
+        uint32_t lgt = gate<kTTAndNotA>(X.last[0], lh[0], lh[0]);
+#pragma unroll
+        for (int b = 1; b < kLenBits; b++) {
+            flt = gate<kTTMajNotA>(fh[b], X.first[b], flt);
+            lgt = gate<kTTMajNotA>(X.last[b], lh[b], lgt);
+        }
+        // take the high half's position if it has a zero and this one has
+        // none or a later first (earlier last) zero
+        const uint32_t tf = seen_h & (~X.seen | flt);
+        const uint32_t tl_ = seen_h & (~X.seen | lgt);
+#pragma unroll
+        for (int b = 0; b < 32; b++) pos[b] = 0u;
+#pragma unroll
+        for (int b = 0; b < kLenBits; b++) {
+            pos[b] = mux(tf, fh[b], X.first[b]);
+            pos[16 + b] = mux(tl_, lh[b], X.last[b]);
+        }
+        X.seen |= seen_h;
+    }
     if (half == 1) return;
     // rows 16.. carry each pair's length (unless all valid pairs have
     // length m_max) and valid bit through the transpose
@@ -588,7 +743,11 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     for (int b = 11; b < 32; b++)
         cnt[b] = (b >= 16 && b < 16 + kLenBits && !uniform) ? lbv[(b - 16) * kPairLanes] : 0u;
     cnt[16 + kLenBits] = valid;
-    transpose32(cnt);  // cnt[k]: ones of S over windows [0, nwin) | length << 16 | valid << 27
+    if constexpr (TWO) {
+        cnt[17 + kLenBits] = X.seen;
+        transpose32(pos);  // pos[k]: first zero | last zero << 16
+    }
+    transpose32(cnt);  // cnt[k]: ones of S over windows [0, nwin) | length << 16 | valid << 27 (| seen << 28)
 #pragma unroll
     for (int k = 0; k < 32; k++) {
         const int64_t p = base + (int64_t)k * kPairLanes + pl;
@@ -602,7 +761,16 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
             pc = -1;
         } else {
             // S stays 1 on [m, nwin): those ones are not part of the pair
-            const int ones = (int)(w & 0xFFFFu) - (nwin - m);
+            int ones = (int)(w & 0xFFFFu) - (nwin - m);
+            if constexpr (TWO) {
+                if ((w >> (17 + kLenBits)) & 1u) {
+                    // ones before the first zero, after the last zero
+                    const int first = (int)(pos[k] & ((1u << kLenBits) - 1));
+                    const int last = (int)((pos[k] >> 16) & ((1u << kLenBits) - 1));
+                    if (J.mode == 1 || J.mode == 2) ones -= first;
+                    if (J.mode == 1 || J.mode == 3) ones -= m - 1 - last;
+                }
+            }
             const int E = J.Edec ? J.Edec[p] : J.E;
             acc = ones <= E ? 1 : 0;
             pc = (int16_t)ones;
@@ -629,10 +797,38 @@ __global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_plain_kernel
     J.perm = nullptr;
     J.out_accept = prm.out_accept;
     J.out_popcount = prm.out_popcount;
+    J.ref_lengths = nullptr;
+    J.mode = 0;
     J.base = ((int64_t)blockIdx.x * kWavesPerGroup + wave) * kPairsPerWave;
     J.n = prm.n;
     if (J.base >= J.n) return;
-    filter_group(J, lds_all + (size_t)wave * (prm.lds_wave_bytes / 4), prm.R, lane);
+    filter_group<false>(J, lds_all + (size_t)wave * (prm.lds_wave_bytes / 4), prm.R, lane);
+}
+
+// Two-length form: reads and references of different lengths, local /
+// glocal / global counting.  Workgroups of waves_per_group wavefronts.
+__global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_local_kernel(LocalParams prm) {
+    extern __shared__ uint32_t lds_all[];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    GroupJob J;
+    J.reads = prm.reads;
+    J.refs = prm.refs;
+    J.ld = prm.ld;
+    J.lengths = prm.read_lengths;
+    J.ref_lengths = prm.ref_lengths;
+    J.mode = prm.mode;
+    J.max_len = prm.max_len;
+    J.Ee = prm.Ee;
+    J.E = prm.E;
+    J.Edec = nullptr;
+    J.perm = nullptr;
+    J.out_accept = prm.out_accept;
+    J.out_popcount = prm.out_popcount;
+    J.base = ((int64_t)blockIdx.x * prm.waves_per_group + wave) * kPairsPerWave;
+    J.n = prm.n;
+    if (wave >= prm.waves_per_group || J.base >= J.n) return;
+    filter_group<true>(J, lds_all + (size_t)wave * (prm.lds_wave_bytes / 4), prm.R, lane);
 }
 
 // Batched form: one wavefront per tile of at most 1024 pairs of one bin of
@@ -651,6 +847,8 @@ __global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_tiles_kernel
     J.refs = prm.brefs;
     J.ld = prm.ld;
     J.lengths = prm.blens;
+    J.ref_lengths = nullptr;
+    J.mode = 0;
     J.max_len = prm.max_len;
     J.Ee = tile.z;
     J.E = 0;
@@ -660,7 +858,7 @@ __global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_tiles_kernel
     J.out_popcount = prm.out_popcount;
     J.base = tile.x;
     J.n = (int64_t)tile.x + tile.y;
-    filter_group(J, lds_all + (size_t)wave * (prm.lds_wave_bytes / 4), prm.R, lane);
+    filter_group<false>(J, lds_all + (size_t)wave * (prm.lds_wave_bytes / 4), prm.R, lane);
 }
 
 }  // namespace shouji

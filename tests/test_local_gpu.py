@@ -1,0 +1,134 @@
+"""GPU parity of the two-length form (reads and references of different
+lengths; global, local and glocal counting) against the CPU oracle,
+bit-exact on every accept byte and count."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+import syninput
+from golden_io import read_sections
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sj():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1809_07858_amd as m
+    m.lib()
+    return m
+
+
+def _embedded(n, m_lo, m_hi, max_len, seed, r_max=0.10):
+    """Reads of length m placed at an offset 0..6 inside references with a
+    random prefix and tail (lengths up to max_len); edits as in the generator."""
+    p = syninput.generate(n, m_lo, m_hi, E=None, r_max=r_max, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    P = np.zeros((n, max_len), np.uint8)
+    T = rng.integers(0, 4, (n, max_len)).astype(np.uint8)
+    LP = p.lengths.astype(np.int32).copy()
+    LT = np.zeros(n, np.int32)
+    pre = rng.integers(0, 7, n)
+    tail = rng.integers(0, 30, n)
+    for i in range(n):
+        m = LP[i]
+        P[i, :m] = p.P[i, :m]
+        k = min(pre[i], max_len - m)
+        T[i, k:k + m] = p.T[i, :m]
+        LT[i] = min(max_len, k + m + tail[i])
+    # some pairs the other way round: reference shorter than the read
+    flip = rng.random(n) < 0.25
+    P[flip], T[flip] = T[flip].copy(), P[flip].copy()
+    LP[flip], LT[flip] = LT[flip].copy(), LP[flip].copy()
+    return P, T, LP, LT, p.E.astype(np.int32)
+
+
+def _run(sj, P, T, LP, LT, E, mode, max_len):
+    d = torch.device("cuda:0")
+    r = torch.from_numpy(sj.pack_words(P, max_len)).to(d)
+    t = torch.from_numpy(sj.pack_words(T, max_len)).to(d)
+    acc, pc = sj.shouji_filter_local(r, t, torch.from_numpy(LP).to(d), torch.from_numpy(LT).to(d), E,
+                                     mode=mode, max_len=max_len)
+    torch.cuda.synchronize()
+    return acc.cpu().numpy(), pc.cpu().numpy()
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+@pytest.mark.parametrize("E", [0, 3, 8])
+def test_modes_vs_oracle(sj, mode, E):
+    max_len = 200
+    P, T, LP, LT, _ = _embedded(6000, 60, 160, max_len, seed=500 + E)
+    print("local form mode=%d E=%d n=%d" % (mode, E, len(LP)), flush=True)
+    ga, gp = _run(sj, P, T, LP, LT, E, mode, max_len)
+    ea, ep = oracle.shouji_batch2(P, T, LP, LT, E=E, mode=mode)
+    bad = np.nonzero((ga != ea) | (gp != ep))[0]
+    assert bad.size == 0, "mismatches at %s: gpu %s/%s oracle %s/%s (mP %s mT %s)" % (
+        bad[:6], ga[bad[:6]], gp[bad[:6]], ea[bad[:6]], ep[bad[:6]], LP[bad[:6]], LT[bad[:6]])
+
+
+@pytest.mark.parametrize("E", [13, 20, 31])
+def test_large_E_and_short_sequences(sj, E):
+    # lengths 0..70 (many below 4 and below E), both orders of lengths
+    max_len = 70
+    rng = np.random.default_rng(E)
+    n = 3000
+    P = rng.integers(0, 4, (n, max_len)).astype(np.uint8)
+    T = P.copy()
+    T[rng.random((n, max_len)) < 0.08] = rng.integers(0, 4)
+    LP = rng.integers(0, max_len + 1, n).astype(np.int32)
+    LT = rng.integers(0, max_len + 1, n).astype(np.int32)
+    for mode in (0, 1, 2, 3):
+        ga, gp = _run(sj, P, T, LP, LT, E, mode, max_len)
+        ea, ep = oracle.shouji_batch2(P, T, LP, LT, E=E, mode=mode)
+        assert np.array_equal(ga, ea) and np.array_equal(gp, ep), (E, mode)
+
+
+def test_equal_lengths_global_equals_plain(sj):
+    p = syninput.generate(20_000, 100, E=5, seed=1005)
+    d = torch.device("cuda:0")
+    r = torch.from_numpy(sj.pack_words(p.P, 100)).to(d)
+    t = torch.from_numpy(sj.pack_words(p.T, 100)).to(d)
+    L = torch.from_numpy(p.lengths).to(d)
+    la, lp = sj.shouji_filter_local(r, t, L, L, 5, mode=0, max_len=100)
+    pa, pp = sj.shouji_filter(r, t, L, 5, max_len=100)
+    torch.cuda.synchronize()
+    assert torch.equal(la, pa) and torch.equal(lp, pp)
+
+
+def test_fig6c_local_on_gpu(sj):
+    g = read_sections("fig6c_local.txt")[""]
+    P = np.zeros((1, 100), np.uint8)
+    T = np.zeros((1, 100), np.uint8)
+    P[0, :68] = oracle.codes(g["read"])
+    T[0, :100] = oracle.codes(g["reference"])
+    counts = []
+    for mode in (0, 1, 2, 3):
+        ga, gp = _run(sj, P, T, np.array([68], np.int32), np.array([100], np.int32), 4, mode, 100)
+        counts.append(int(gp[0]))
+        assert gp[0] == oracle.shouji_pair2(g["read"], g["reference"], 4, mode)[0]
+    assert counts[1] == int(g["local_edits"])
+
+
+def test_invalid_lengths_get_sentinels(sj):
+    max_len = 64
+    P, T, LP, LT, _ = _embedded(2000, 20, 50, max_len, seed=77)
+    LP[::29] = max_len + 1
+    LT[3::31] = -1
+    ga, gp = _run(sj, P, T, LP, LT, 4, 1, max_len)
+    bad = (LP > max_len) | (LT < 0)
+    assert (ga[bad] == 0xFF).all() and (gp[bad] == -1).all()
+    ea, ep = oracle.shouji_batch2(P[~bad], T[~bad], LP[~bad], LT[~bad], E=4, mode=1)
+    assert np.array_equal(ga[~bad], ea) and np.array_equal(gp[~bad], ep)
+
+
+def test_argument_errors(sj):
+    d = torch.device("cuda:0")
+    r = torch.zeros((4, 10), dtype=torch.int32, device=d)
+    L = torch.full((10,), 50, dtype=torch.int32, device=d)
+    with pytest.raises(sj.ShoujiError):
+        sj.shouji_filter_local(r, r, L, L, 2, mode=4, max_len=64)
+    with pytest.raises(sj.ShoujiError):
+        sj.shouji_filter_local(r, r, L, L, 40, mode=1, max_len=64)
