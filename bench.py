@@ -100,6 +100,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-form leg (mixed lengths, per-pair E)")
     ap.add_argument("--batched-n", type=int, default=8_000_000)
+    ap.add_argument("--no-local", action="store_true",
+                    help="skip the two-length leg (reads inside longer references, local counting)")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving leg (Poisson request stream through the server)")
     ap.add_argument("--serving-pairs", type=int, default=40_000_000)
@@ -220,6 +222,8 @@ def main():
         out["parity_sample"] = ns
     if not args.no_batched:
         out["batched"] = bench_batched(args.batched_n, dev)
+    if not args.no_local:
+        out["local"] = bench_local(dev, args.n, args.E, ms_per_step, with_oracle=not args.no_cpu)
     if not args.no_serving:
         out["serving"] = bench_serving(dev, args.serving_pairs, args.serving_batch,
                                        args.serving_slots, with_oracle=not args.no_cpu)
@@ -309,6 +313,59 @@ def bench_batched(n, dev, steps=20):
             "plain_per_group_value": n / (plain_ms / 1e3), "plain_groups": len(groups),
             "plain_ms": plain_ms, "vs_plain": plain_ms / ms, "mismatches_vs_plain": same,
             "accept_rate": float(acc.float().mean().item())}
+
+
+def bench_local(dev, n, E, plain_ms, m=100, max_len=128, steps=50, with_oracle=True, seed=5000):
+    """Two-length form: reads of m bases (the headline generator, seed 5000) placed at
+    an offset 0..6 inside references of m+k+tail bases (k = offset, tail 0..21: up to
+    max_len), local counting, E as the headline.  Compared with the plain launch time
+    on equal-length pairs of the same read length."""
+    import numpy as np
+    import torch
+    import paper_1809_07858_amd as sj
+    import syninput
+    p = syninput.generate(n, m, E=E, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    k = rng.integers(0, 7, n)
+    tail = rng.integers(0, max_len - m - 6 + 1, n)
+    T = rng.integers(0, 4, (n, max_len), dtype=np.uint8)
+    for kk in range(7):
+        sel = k == kk
+        T[sel, kk:kk + m] = p.T[sel, :m]
+    LP = np.full(n, m, np.int32)
+    LT = (m + k + tail).astype(np.int32)
+    P = np.zeros((n, max_len), np.uint8)
+    P[:, :m] = p.P[:, :m]
+    r = sj.pack_words_device(P, max_len)
+    t = sj.pack_words_device(T, max_len)
+    lp = torch.from_numpy(LP).to(dev)
+    lt = torch.from_numpy(LT).to(dev)
+    acc = torch.empty(n, dtype=torch.uint8, device=dev)
+    pc = torch.empty(n, dtype=torch.int16, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        sj.shouji_filter_local(r, t, lp, lt, E, sj.COUNT_LOCAL, acc, pc, max_len=max_len, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        sj.shouji_filter_local(r, t, lp, lt, E, sj.COUNT_LOCAL, acc, pc, max_len=max_len, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    out = {"workload": "%d pairs, reads m=%d inside references of %d..%d bases (offset 0..6), local "
+                       "counting, E=%d, seed %d" % (n, m, m, max_len, E, seed),
+           "value": n / (ms / 1e3), "unit": "pairs/s", "ms_per_step": ms,
+           "plain_same_reads_ms": plain_ms, "vs_plain": plain_ms / ms,
+           "accept_rate": float((acc == 1).float().mean().item())}
+    if with_oracle:
+        import oracle
+        ns = 50_000
+        ea, ep = oracle.shouji_batch2(P[:ns], T[:ns], LP[:ns], LT[:ns], E=E, mode=oracle.LOCAL)
+        ga, gp = acc[:ns].cpu().numpy(), pc[:ns].cpu().numpy()
+        out["mismatches_vs_oracle_sample"] = int(((ga != ea) | (gp != ep)).sum())
+        out["oracle_sample"] = ns
+    return out
 
 
 def bench_serving(dev, total_pairs, batch_pairs, slots, distinct=1_000_000, load=0.8,

@@ -140,7 +140,10 @@ extern "C" int shouji_filter_local(const uint32_t *reads, const uint32_t *refs, 
     prm.n = n_pairs;
     // As many wavefronts per CU as LDS allows, up to two per SIMD: workgroups
     // of four wavefronts when two of them fit, else of one.
-    const size_t wave_lds = shouji::local_lds_wave_bytes(Ee);
+    int len_bits = 1;
+    while ((1 << len_bits) <= max_len) len_bits++;   // bits of max_len
+    prm.len_bits = len_bits;
+    const size_t wave_lds = shouji::local_lds_wave_bytes(Ee, len_bits);
     if (wave_lds > shouji::kLdsPerCU) return fail(SHOUJI_ERR_RANGE, "E %d needs more LDS than one CU holds", E);
     const int wpg = 8 * wave_lds <= shouji::kLdsPerCU ? shouji::kWavesPerGroup : 1;
     const size_t lds = wave_lds * wpg;

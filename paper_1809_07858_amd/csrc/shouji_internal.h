@@ -45,6 +45,7 @@ struct LocalParams {
     int32_t Ee;
     int32_t R;
     int32_t mode;
+    int32_t len_bits;         // bit planes stored per length: bits of max_len
     int32_t waves_per_group;
     uint8_t *out_accept;
     int16_t *out_popcount;
@@ -130,6 +131,7 @@ struct GroupJob {
     const int32_t *lengths;   // or null: every pair has max_len bases (read lengths in the two-length form)
     const int32_t *ref_lengths;  // two-length form only: reference (text) lengths
     int32_t mode;             // two-length form only: counting mode
+    int32_t len_bits;         // two-length form only: bit planes per length
     int32_t max_len;
     int32_t Ee;               // diagonals built on each side
     int32_t E;                // decision threshold when Edec is null
@@ -180,11 +182,11 @@ inline size_t plain_lds_wave_bytes(int Ee) {
            (size_t)(kLenBits + 1) * kPairLanes * 4;
 }
 
-// LDS of one wavefront in the two-length form: ring, text masks, pattern
-// masks, and the bit planes of both lengths.
-inline size_t local_lds_wave_bytes(int Ee) {
-    return (size_t)(ring_slots(Ee) + kMirror) * kRingStride * 8 + (size_t)mask_slots(Ee) * kPairLanes * 4 +
-           (size_t)pattern_mask_slots(Ee) * kPairLanes * 4 + (size_t)(2 * kLenBits) * kPairLanes * 4;
+// LDS of one wavefront in the two-length form: ring, text masks of the 19
+// text columns, pattern masks, and len_bits bit planes of both lengths.
+inline size_t local_lds_wave_bytes(int Ee, int len_bits) {
+    return (size_t)(ring_slots(Ee) + kMirror) * kRingStride * 8 + (size_t)(kBlock + kCols) * kPairLanes * 4 +
+           (size_t)pattern_mask_slots(Ee) * kPairLanes * 4 + (size_t)(2 * len_bits) * kPairLanes * 4;
 }
 
 __global__ void shouji_plain_kernel(PlainParams prm);

@@ -61,6 +61,7 @@ constexpr unsigned kTTOrNotA = truth_table([](int a, int b, int) { return !a || 
 constexpr unsigned kTTMux = truth_table([](int a, int b, int c) { return a ? b : c; });
 constexpr unsigned kTTOr3 = truth_table([](int a, int b, int c) { return a | b | c; });
 constexpr unsigned kTTAnd3 = truth_table([](int a, int b, int c) { return a & b & c; });
+constexpr unsigned kTTAndXnor = truth_table([](int a, int b, int c) { return a & (b == c); });
 
 template <unsigned TT>
 __device__ __forceinline__ uint32_t gate(uint32_t a, uint32_t b, uint32_t c) {
@@ -413,10 +414,13 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     // nvp[s * 32 + pl], then the bit planes of the reference and read lengths.
     uint32_t *nv = lds + (R + kMirror) * kRingStride * 2;
     uint32_t *nvh = nv + kBlock * half * kPairLanes + pl;
-    uint32_t *nvp = nv + mask_slots(Ee) * kPairLanes;
+    // (TWO needs text masks of the 19 text columns only, and J.len_bits bit
+    // planes per length)
+    uint32_t *nvp = nv + (TWO ? kBlock + kCols : mask_slots(Ee)) * kPairLanes;
     uint32_t *nvph = nvp + kBlock * half * kPairLanes + pl;
     uint32_t *lbv = (TWO ? nvp + pattern_mask_slots(Ee) * kPairLanes : nvp) + pl;   // length bit planes
-    uint32_t *lbvp = lbv + kLenBits * kPairLanes;                               // TWO: read lengths
+    const int nlb = TWO ? J.len_bits : kLenBits;                                  // planes per length
+    uint32_t *lbvp = lbv + nlb * kPairLanes;                                      // TWO: read lengths
     const int64_t base = J.base;
     const int64_t n = J.n;
     const bool full = base + kPairsPerWave <= n;
@@ -490,11 +494,13 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
         // needed
         transpose32(lenw);             // lenw[b] = bit b of the 32 lengths
 #pragma unroll
-        for (int b = 0; b < kLenBits; b++) lbv[b * kPairLanes] = lenw[b];
+        for (int b = 0; b < kLenBits; b++)
+            if (b < nlb) lbv[b * kPairLanes] = lenw[b];
         if constexpr (TWO) {
             transpose32(lenr);
 #pragma unroll
-            for (int b = 0; b < kLenBits; b++) lbvp[b * kPairLanes] = lenr[b];
+            for (int b = 0; b < kLenBits; b++)
+                if (b < nlb) lbvp[b * kPairLanes] = lenr[b];
         }
     }
     Ends X;
@@ -515,33 +521,52 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     const int nhalves = (m_words + kHalf - 1) / kHalf;  // words holding positions < m_words
     const int H0 = (kBlock + kCols - 1 + Ee) / kHalf; // last pattern word iteration 0 reads
 
-    // "position xpos is past the pair's end" for the lengths whose bit planes
-    // are at planes[b * 32], bit-sliced over the 32 pairs
-    auto past_end = [&](int xpos, const uint32_t *planes) {
-        uint32_t g = 0u;  // g = (length > xpos)
+    // Masks "position x is past the pair's end" (x < 0 counts as past) for
+    // positions x0 .. x0+count-1, stored at dst[s * 32], from the length bit
+    // planes at planes[b * 32] (nlb of them, higher bits zero), bit-sliced
+    // over the 32 pairs.  The first non-negative position takes a full
+    // compare (length <= x); each next one adds the pairs whose length
+    // equals it, one gate per length bit.
+    auto fill_range = [&](int x0, int count, const uint32_t *planes, uint32_t *dst) {
+        uint32_t lb[kLenBits];
 #pragma unroll
-        for (int b = 0; b < kLenBits; b++) {
-            const uint32_t sx = ((xpos >> b) & 1) ? ~0u : 0u;
-            const uint32_t lb = planes[b * kPairLanes];
-            g = mux(sx, lb & g, lb | g);
+        for (int b = 0; b < kLenBits; b++) lb[b] = b < nlb ? planes[b * kPairLanes] : 0u;
+        uint32_t msk = ~0u;
+        for (int s = 0; s < count; s++) {
+            const int x = x0 + s;
+            if (x == max(x0, 0)) {
+                uint32_t g = 0u;  // g = (length > x)
+#pragma unroll
+                for (int b = 0; b < kLenBits; b++) {
+                    const uint32_t sx = ((x >> b) & 1) ? ~0u : 0u;
+                    g = mux(sx, lb[b] & g, lb[b] | g);
+                }
+                msk = ~g;
+            } else if (x > 0) {
+                uint32_t e = ~0u;  // e = (length == x)
+#pragma unroll
+                for (int b = 0; b < kLenBits; b++) {
+                    const uint32_t sx = ((x >> b) & 1) ? ~0u : 0u;
+                    e = gate<kTTAndXnor>(e, lb[b], sx);
+                }
+                msk |= e;
+            }
+            dst[s * kPairLanes] = x < 0 ? ~0u : msk;
         }
-        return ~g;
     };
     // per-lane masks of positions i0 .. i0+count-1, stored at dst[s * 32]
     auto fill_masks = [&](int i0, uint32_t *dst, int count) {
-        for (int s = 0; s < count; s++) {
-            const int xpos = i0 + s;
-            dst[s * kPairLanes] = uniform ? (xpos >= m_max ? ~0u : 0u) : past_end(xpos, lbv);
+        if (uniform) {
+            for (int s = 0; s < count; s++) dst[s * kPairLanes] = i0 + s >= m_max ? ~0u : 0u;
+        } else {
+            fill_range(i0, count, lbv, dst);
         }
     };
     // TWO: text masks of i0 .. i0+C-1 and pattern masks of i0-Ee .. i0+C-1+Ee
     // (a negative pattern position is outside the read)
     auto fill_masks2 = [&](int i0, uint32_t *dst, uint32_t *dstp, int C) {
-        for (int s = 0; s < C; s++) dst[s * kPairLanes] = past_end(i0 + s, lbv);
-        for (int s = 0; s < C + 2 * Ee; s++) {
-            const int xpos = i0 - Ee + s;
-            dstp[s * kPairLanes] = xpos < 0 ? ~0u : past_end(xpos, lbvp);
-        }
+        fill_range(i0, C, lbv, dst);
+        fill_range(i0 - Ee, C + 2 * Ee, lbvp, dstp);
     };
 
     // One transpose pass: the low lane half turns pattern word pw into ring
@@ -741,7 +766,7 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     // length m_max) and valid bit through the transpose
 #pragma unroll
     for (int b = 11; b < 32; b++)
-        cnt[b] = (b >= 16 && b < 16 + kLenBits && !uniform) ? lbv[(b - 16) * kPairLanes] : 0u;
+        cnt[b] = (b >= 16 && b < 16 + nlb && !uniform) ? lbv[(b - 16) * kPairLanes] : 0u;
     cnt[16 + kLenBits] = valid;
     if constexpr (TWO) {
         cnt[17 + kLenBits] = X.seen;
@@ -798,6 +823,7 @@ __global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_plain_kernel
     J.out_accept = prm.out_accept;
     J.out_popcount = prm.out_popcount;
     J.ref_lengths = nullptr;
+    J.len_bits = kLenBits;
     J.mode = 0;
     J.base = ((int64_t)blockIdx.x * kWavesPerGroup + wave) * kPairsPerWave;
     J.n = prm.n;
@@ -818,6 +844,7 @@ __global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_local_kernel
     J.lengths = prm.read_lengths;
     J.ref_lengths = prm.ref_lengths;
     J.mode = prm.mode;
+    J.len_bits = prm.len_bits;
     J.max_len = prm.max_len;
     J.Ee = prm.Ee;
     J.E = prm.E;
@@ -848,6 +875,7 @@ __global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_tiles_kernel
     J.ld = prm.ld;
     J.lengths = prm.blens;
     J.ref_lengths = nullptr;
+    J.len_bits = kLenBits;
     J.mode = 0;
     J.max_len = prm.max_len;
     J.Ee = tile.z;
