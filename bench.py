@@ -100,6 +100,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-form leg (mixed lengths, per-pair E)")
     ap.add_argument("--batched-n", type=int, default=8_000_000)
+    ap.add_argument("--no-verify", action="store_true",
+                    help="skip the filter + verifier leg (banded edit distance of accepted pairs)")
     ap.add_argument("--no-local", action="store_true",
                     help="skip the two-length leg (reads inside longer references, local counting)")
     ap.add_argument("--no-serving", action="store_true",
@@ -222,6 +224,8 @@ def main():
         out["parity_sample"] = ns
     if not args.no_batched:
         out["batched"] = bench_batched(args.batched_n, dev)
+    if not args.no_verify:
+        out["verify"] = bench_verify(reads, refs, lens, acc, pairs, E, ms_per_step, with_oracle=not args.no_cpu)
     if not args.no_local:
         out["local"] = bench_local(dev, args.n, args.E, ms_per_step, with_oracle=not args.no_cpu)
     if not args.no_serving:
@@ -313,6 +317,56 @@ def bench_batched(n, dev, steps=20):
             "plain_per_group_value": n / (plain_ms / 1e3), "plain_groups": len(groups),
             "plain_ms": plain_ms, "vs_plain": plain_ms / ms, "mismatches_vs_plain": same,
             "accept_rate": float(acc.float().mean().item())}
+
+
+def bench_verify(reads, refs, lens, acc, pairs, E, filter_ms, steps=20, with_oracle=True):
+    """Filter + verifier on the headline batch: the banded edit distance of the pairs
+    the filter accepted, against verifying every pair (the effect Table 3 measures
+    with CPU aligners).  False accepts / rejects are counted against the verifier's
+    distances of all pairs (a sample is checked against the oracle)."""
+    import numpy as np
+    import torch
+    import paper_1809_07858_amd as sj
+    n = acc.numel()
+    stream = torch.cuda.current_stream()
+    dist_all = torch.empty(n, dtype=torch.int16, device=acc.device)
+    dist_acc = torch.empty(n, dtype=torch.int16, device=acc.device)
+    ws = torch.empty(sj.lib().shouji_verify_workspace_bytes(n), dtype=torch.uint8, device=acc.device)
+    max_len = int(lens.max().item())
+
+    def timed(fa, out):
+        for _ in range(2):
+            sj.shouji_verify(reads, refs, lens, E, fa, out, max_len=max_len, workspace=ws, stream=stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            sj.shouji_verify(reads, refs, lens, E, fa, out, max_len=max_len, workspace=ws, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ms_all = timed(None, dist_all)
+    ms_acc = timed(acc, dist_acc)
+    a = acc.cpu().numpy()
+    d = dist_all.cpu().numpy().astype(np.int32)
+    similar = d >= 0
+    out = {"workload": "the plain headline batch (%d pairs, m=%d, E=%d): banded edit distance of the "
+                       "pairs the filter accepted" % (n, max_len, E),
+           "value": n / ((filter_ms + ms_acc) / 1e3), "unit": "pairs/s (filter + verify accepted)",
+           "verify_accepted_ms": ms_acc, "filter_ms": filter_ms, "verify_all_ms": ms_all,
+           "verify_all_pairs_per_s": n / (ms_all / 1e3),
+           "speedup_vs_verify_all": ms_all / (filter_ms + ms_acc),
+           "accepted": int((a == 1).sum()), "similar": int(similar.sum()),
+           "false_accepts": int(((a == 1) & ~similar).sum()),
+           "false_rejects": int(((a != 1) & similar).sum())}
+    if with_oracle:
+        import oracle
+        ns = 20_000
+        want = oracle.edit_distance_batch(pairs.P[:ns], pairs.T[:ns], pairs.lengths[:ns], k=E)
+        out["mismatches_vs_oracle_sample"] = int((want != d[:ns]).sum())
+        out["oracle_sample"] = ns
+    return out
 
 
 def bench_local(dev, n, E, plain_ms, m=100, max_len=128, steps=50, with_oracle=True, seed=5000):

@@ -174,6 +174,32 @@ int shouji_tune_batched(const uint32_t *reads, const uint32_t *refs, const int32
                         float *best_ms);
 
 /*
+ * Verifier: the aligner's threshold test for the pairs a filter accepted.
+ *
+ * A filtered pair goes on to alignment (Sec. 1; Sec. 3.3 and Table 3 measure
+ * the filter in front of aligners).  This computes, on the GPU, the
+ * unit-cost global edit distance of read and reference (equal lengths) for
+ * the pairs with filter_accept[p] == 1 (every pair when filter_accept is
+ * NULL), by the textbook recurrence restricted to the band |i - j| <= K,
+ * K >= E (exact for the test "distance <= E").
+ *
+ *   reads, refs, lengths, ld, max_len, n_pairs, stream: as for shouji_filter.
+ *   E             threshold, 0..SHOUJI_MAX_E (else SHOUJI_ERR_ARG / _RANGE).
+ *   filter_accept n_pairs bytes from a filter (device), or NULL.
+ *   out_distance  n_pairs int16 (device): the distance if it is <= E, -1 if
+ *                 it is larger, -2 for a pair not accepted by the filter (not
+ *                 verified), -3 for a length outside [0, max_len].
+ *   workspace     device buffer of shouji_verify_workspace_bytes(n_pairs)
+ *                 bytes (a list of the pairs to verify), owned by the caller;
+ *                 nothing is allocated.
+ */
+int64_t shouji_verify_workspace_bytes(int64_t n_pairs);
+
+int shouji_verify(const uint32_t *reads, const uint32_t *refs, const int32_t *lengths, int32_t E,
+                  const uint8_t *filter_accept, int16_t *out_distance, int64_t n_pairs, int32_t max_len,
+                  int64_t ld, void *workspace, int64_t workspace_bytes, void *stream);
+
+/*
  * Serving form: a request server with continuous batching.
  *
  * Same filter (Sec. 2.2, Eq. 1, Algorithm 1) served to a stream of requests

@@ -63,6 +63,10 @@ def lib():
         L.shouji_filter.argtypes = [vp, vp, vp, i32, vp, vp, i64, i32, i64, vp]
         L.shouji_filter_local.restype = ctypes.c_int
         L.shouji_filter_local.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp, i64, i32, i64, vp]
+        L.shouji_verify_workspace_bytes.restype = ctypes.c_int64
+        L.shouji_verify_workspace_bytes.argtypes = [i64]
+        L.shouji_verify.restype = ctypes.c_int
+        L.shouji_verify.argtypes = [vp, vp, vp, i32, vp, vp, i64, i32, i64, vp, i64, vp]
         L.shouji_batched_workspace_bytes.restype = ctypes.c_int64
         L.shouji_batched_workspace_bytes.argtypes = [i64, i32]
         L.shouji_filter_batched.restype = ctypes.c_int
@@ -223,6 +227,46 @@ def shouji_filter_local(reads, refs, read_lengths, ref_lengths, E, mode=COUNT_LO
         None if out_popcount is None else ctypes.c_void_p(out_popcount.data_ptr()),
         int(n_pairs), int(max_len), int(ld), _stream_handle(stream)))
     return out_accept, out_popcount
+
+
+def shouji_verify(reads, refs, lengths, E, filter_accept=None, out_distance=None, n_pairs=None,
+                  max_len=None, workspace=None, stream=None):
+    """Banded edit distance of the pairs a filter accepted (all pairs when filter_accept is
+    None): int16 per pair, distance if <= E, -1 above, -2 not verified, -3 invalid length."""
+    import torch
+    if reads.dim() != 2 or refs.shape != reads.shape:
+        raise ValueError("reads/refs must be [nwords, ld] tensors of the same shape")
+    for t in (reads, refs):
+        if not t.is_cuda or t.dtype != torch.int32 or not t.is_contiguous():
+            raise ValueError("reads/refs must be contiguous int32 CUDA tensors")
+    ld = reads.shape[1]
+    if n_pairs is None:
+        n_pairs = ld
+    if max_len is None:
+        max_len = reads.shape[0] * BASES_PER_WORD
+    if reads.shape[0] < nwords(max_len):
+        raise ValueError("reads hold fewer words than max_len needs")
+    if lengths is not None and (not lengths.is_cuda or lengths.dtype != torch.int32 or lengths.numel() < n_pairs):
+        raise ValueError("lengths must be an int32 CUDA tensor with n_pairs entries")
+    if filter_accept is not None and (not filter_accept.is_cuda or filter_accept.dtype != torch.uint8
+                                      or filter_accept.numel() < n_pairs):
+        raise ValueError("filter_accept must be a uint8 CUDA tensor with n_pairs entries")
+    dev = reads.device
+    if out_distance is None:
+        out_distance = torch.empty(n_pairs, dtype=torch.int16, device=dev)
+    need = lib().shouji_verify_workspace_bytes(int(n_pairs))
+    if need < 0:
+        _check(int(need))
+    if workspace is None:
+        workspace = torch.empty(int(need), dtype=torch.uint8, device=dev)
+    _check(lib().shouji_verify(
+        ctypes.c_void_p(reads.data_ptr()), ctypes.c_void_p(refs.data_ptr()),
+        None if lengths is None else ctypes.c_void_p(lengths.data_ptr()), int(E),
+        None if filter_accept is None else ctypes.c_void_p(filter_accept.data_ptr()),
+        ctypes.c_void_p(out_distance.data_ptr()), int(n_pairs), int(max_len), int(ld),
+        ctypes.c_void_p(workspace.data_ptr()), int(workspace.numel() * workspace.element_size()),
+        _stream_handle(stream)))
+    return out_distance
 
 
 class BatchedConfig(ctypes.Structure):

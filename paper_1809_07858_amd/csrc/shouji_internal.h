@@ -53,6 +53,19 @@ struct LocalParams {
     int32_t lds_wave_bytes;
 };
 
+// Verifier of filtered pairs (banded edit distance, one pair per lane).
+struct VerifyParams {
+    const uint32_t *reads;
+    const uint32_t *refs;
+    int64_t ld;
+    const int32_t *lengths;
+    int32_t max_len;
+    int32_t E;
+    const int64_t *list;              // pairs to verify
+    const unsigned long long *count;  // entries in list
+    int16_t *out;
+};
+
 // ---- batched form
 constexpr int kMaxE = 31;                     // largest E (after clamping to m-1)
 constexpr int kBinE = kMaxE + 1;              // E values per length bucket
