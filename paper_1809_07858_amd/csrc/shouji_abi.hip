@@ -289,9 +289,9 @@ extern "C" int shouji_filter_batched(const uint32_t *reads, const uint32_t *refs
     static size_t tlimit = 0;
     const int Emax_len = max_len > 0 ? max_len - 1 : 0;
     for (int c = shouji::kEClasses - 1; c >= 0; c--) {
-        int Ecls = c == 0 ? shouji::kEClassBound0 : shouji::kMaxE;
+        if (c > 0 && Emax_len <= shouji::e_class_bound(c - 1)) continue;   // the class is empty
+        int Ecls = shouji::e_class_bound(c);
         if (Ecls > Emax_len) Ecls = Emax_len;
-        if (c == 1 && Emax_len <= shouji::kEClassBound0) continue;   // class 1 is empty
         shouji::TilesParams tp;
         tp.breads = sp.breads;
         tp.brefs = sp.brefs;
@@ -304,9 +304,15 @@ extern "C" int shouji_filter_batched(const uint32_t *reads, const uint32_t *refs
         tp.max_len = max_len;
         tp.R = shouji::ring_slots(Ecls);
         const size_t wave_lds = shouji::plain_lds_wave_bytes(Ecls);
-        int wpg = cfg.waves_per_group;
-        while (wpg > 1 && wave_lds * wpg > shouji::kLdsPerCU) wpg >>= 1;
-        if (wave_lds * wpg > shouji::kLdsPerCU) return fail(SHOUJI_ERR_RANGE, "LDS too small for E %d", Ecls);
+        // the workgroup size (at most the configured one) that lets a CU hold
+        // the most wavefronts (two per SIMD at most)
+        int wpg = 0, best_waves = 0;
+        for (int g = cfg.waves_per_group; g >= 1; g >>= 1) {
+            int waves = (int)(shouji::kLdsPerCU / (wave_lds * g)) * g;
+            if (waves > 8) waves = 8;
+            if (waves > best_waves) { best_waves = waves; wpg = g; }
+        }
+        if (wpg == 0) return fail(SHOUJI_ERR_RANGE, "LDS too small for E %d", Ecls);
         tp.lds_wave_bytes = (int32_t)wave_lds;
         tp.waves_per_group = wpg;
         if (int rc = raise_lds_limit((const void *)shouji::shouji_tiles_kernel, tlimit, wave_lds * wpg))

@@ -98,7 +98,7 @@ __global__ __launch_bounds__(kPlanThreads) void bin_plan_kernel(
         const int c = counts[b];
         if (!c) continue;
         const int Ee = b % kBinE, mb = b / kBinE;
-        const int cls = Ee <= kEClassBound0 ? 0 : 1;
+        const int cls = e_class(Ee);
         const uint32_t cost = (uint32_t)(mb + 1) * (uint32_t)(2 * Ee + 1);
         const int cb = kCostBuckets - 1 - min(kCostBuckets - 1, 31 - __builtin_clz(cost));
         atomicAdd(&npos[cls * kCostBuckets + cb], (c + kPairsPerWave - 1) / kPairsPerWave);
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(kPlanThreads) void bin_plan_kernel(
         const int c = counts[b];
         if (!c) continue;
         const int Ee = b % kBinE, mb = b / kBinE;
-        const int cls = Ee <= kEClassBound0 ? 0 : 1;
+        const int cls = e_class(Ee);
         const uint32_t cost = (uint32_t)(mb + 1) * (uint32_t)(2 * Ee + 1);
         const int cb = kCostBuckets - 1 - min(kCostBuckets - 1, 31 - __builtin_clz(cost));
         const int nt = (c + kPairsPerWave - 1) / kPairsPerWave;

@@ -71,8 +71,11 @@ constexpr int kMaxE = 31;                     // largest E (after clamping to m-
 constexpr int kBinE = kMaxE + 1;              // E values per length bucket
 constexpr int kPlanThreads = 1024;
 constexpr int kCostBuckets = 16;
-constexpr int kEClasses = 2;                  // tiles launched per E class
-constexpr int kEClassBound0 = 12;             // class 0: Ee <= 12 (two wavefronts per SIMD fit)
+// Tiles are launched per E class, each with the LDS its largest E needs:
+// Ee <= 13 fits two wavefronts per SIMD, Ee <= 31 one.
+constexpr int kEClasses = 2;
+__host__ __device__ inline int e_class(int Ee) { return Ee <= 13 ? 0 : 1; }
+__host__ __device__ inline int e_class_bound(int c) { return c == 0 ? 13 : 31; }
 constexpr int kMinBinWidth = 4;
 constexpr int kScatterChunk = 8192;           // pairs per workgroup of the staged scatter
 constexpr int kScatterThreads = 1024;

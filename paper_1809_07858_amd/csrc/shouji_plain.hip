@@ -631,9 +631,11 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
         uint32_t raw1[32];
         pass_finish(0, nhalves, raw0);
         start_text(TA, raw0);
-        pass(1, 1, raw1);
-        finish_text(TA, raw1);
-        start_text(TB, raw1);
+        if (nhalves > 1) {       // else word 1 holds no position of any pair
+            pass(1, 1, raw1);
+            finish_text(TA, raw1);
+            start_text(TB, raw1);
+        }
         for (int hp = 2; hp <= H0; hp++) pass(hp, -1, raw1);
     }
 
@@ -665,9 +667,10 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
         F.s0 = from_half0(F.s0); F.s1 = from_half0(F.s1); F.s2 = from_half0(F.s2);
         if (half == 1) block_update<kBlock, TWO>(F, W, X, lo + kBlock);
         F.s0 = from_half1(F.s0); F.s1 = from_half1(F.s1); F.s2 = from_half1(F.s2);
-        if (j + 1 < niter) {
-            // after all reads of iteration j: the pattern word iteration j+1
-            // first needs, and text word j+2
+        // after all reads of iteration j: the pattern word iteration j+1
+        // first needs, and text word j+2 (a pass whose two words both lie
+        // past every pair's end is skipped: their planes are never unmasked)
+        if (j + 1 < niter && (j + 1 + H0 < nhalves || j + 2 < nhalves)) {
             uint32_t raw[32];
             pass(j + 1 + H0, j + 2, raw);
             finish_text(Tn, raw);
@@ -718,7 +721,9 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     // windows whose final S bit went into the counter
     const int nwin = short_last ? kHalf * nlong + (rem > 4 ? kBlock : kBlock / 2) : kHalf * niter;
 
-    // ---- add the high half's ones counter to the low half's, then output
+    // ---- add the two halves' ones counters (each half then holds the
+    // total), then each half writes 16 of the 32 pairs of its lanes
+    auto other_half = [](uint32_t v) { return (uint32_t)__shfl_xor((int)v, 32, kWave); };
     uint32_t cnt[32];
     cnt[0] = F.ones; cnt[1] = F.twos; cnt[2] = F.fours;
 #pragma unroll
@@ -727,7 +732,7 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
         uint32_t cy = 0u;
 #pragma unroll
         for (int b = 0; b < 11; b++) {
-            const uint32_t o = from_half1(cnt[b]);
+            const uint32_t o = other_half(cnt[b]);
             const uint32_t s_ = gate<kTTXor3>(cnt[b], o, cy);
             cy = gate<kTTMaj>(cnt[b], o, cy);
             cnt[b] = s_;
@@ -737,9 +742,9 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     uint32_t pos[TWO ? 32 : 1];
     if constexpr (TWO) {
         uint32_t fh[kLenBits], lh[kLenBits];
-        const uint32_t seen_h = from_half1(X.seen);
+        const uint32_t seen_h = other_half(X.seen);
 #pragma unroll
-        for (int b = 0; b < kLenBits; b++) { fh[b] = from_half1(X.first[b]); lh[b] = from_half1(X.last[b]); }
+        for (int b = 0; b < kLenBits; b++) { fh[b] = other_half(X.first[b]); lh[b] = other_half(X.last[b]); }
         // fh < first and last < lh: borrow chains from the low bit
         uint32_t flt = gate<kTTAndNotA>(fh[0], X.first[0], X.first[0]);
         uint32_t lgt = gate<kTTAndNotA>(X.last[0], lh[0], lh[0]);
@@ -748,7 +753,7 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
             flt = gate<kTTMajNotA>(fh[b], X.first[b], flt);
             lgt = gate<kTTMajNotA>(X.last[b], lh[b], lgt);
         }
-        // take the high half's position if it has a zero and this one has
+        // take the other half's position if it has a zero and this one has
         // none or a later first (earlier last) zero
         const uint32_t tf = seen_h & (~X.seen | flt);
         const uint32_t tl_ = seen_h & (~X.seen | lgt);
@@ -761,7 +766,6 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
         }
         X.seen |= seen_h;
     }
-    if (half == 1) return;
     // rows 16.. carry each pair's length (unless all valid pairs have
     // length m_max) and valid bit through the transpose
 #pragma unroll
@@ -773,9 +777,17 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
         transpose32(pos);  // pos[k]: first zero | last zero << 16
     }
     transpose32(cnt);  // cnt[k]: ones of S over windows [0, nwin) | length << 16 | valid << 27 (| seen << 28)
+    // both halves hold the same rows: the low half writes pairs k < 16, the
+    // high half pairs k >= 16 (a lane swap brings row 16+k to register k)
 #pragma unroll
-    for (int k = 0; k < 32; k++) {
-        const int64_t p = base + (int64_t)k * kPairLanes + pl;
+    for (int k = 0; k < 16; k++) {
+        cnt[k] = __builtin_amdgcn_permlane32_swap(cnt[k], cnt[16 + k], false, false)[0];
+        if constexpr (TWO) pos[k] = __builtin_amdgcn_permlane32_swap(pos[k], pos[16 + k], false, false)[0];
+    }
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        const int kk = k + 16 * half;
+        const int64_t p = base + (int64_t)kk * kPairLanes + pl;
         if (!full && p >= n) continue;
         const uint32_t w = cnt[k];
         const int m = uniform ? m_max : (int)((w >> 16) & ((1u << kLenBits) - 1));
