@@ -55,6 +55,10 @@ def _load():
         lib.oracle_shouji_pair2.argtypes = [vp, i32, vp, i32, i32, i32, i32, vp]
         lib.oracle_shouji_batch2.restype = ctypes.c_int
         lib.oracle_shouji_batch2.argtypes = [vp, vp, i64, vp, vp, i64, i32, vp, i32, i32, vp, vp]
+        lib.oracle_shouji_pair_w.restype = ctypes.c_int
+        lib.oracle_shouji_pair_w.argtypes = [vp, vp, i32, i32, i32, vp]
+        lib.oracle_shouji_batch_w.restype = ctypes.c_int
+        lib.oracle_shouji_batch_w.argtypes = [vp, vp, i64, vp, i64, i32, i32, i32, vp, vp]
         lib.oracle_shouji_map_row.restype = ctypes.c_int
         lib.oracle_shouji_map_row.argtypes = [vp, vp, i32, i32, vp]
         lib.oracle_default_threads.restype = ctypes.c_int
@@ -92,6 +96,35 @@ def shouji_pair(P, T, E, reading=READING_B):
     if ones < 0:
         raise ValueError("bad arguments")
     return ones, "".join(str(int(b)) for b in S[:m])
+
+
+def shouji_pair_w(P, T, E, W):
+    """Filter one equal-length pair with W-column windows.  Returns (popcount, S string)."""
+    P = codes(P) if isinstance(P, str) else _c(P, np.uint8)
+    T = codes(T) if isinstance(T, str) else _c(T, np.uint8)
+    if len(P) != len(T):
+        raise ValueError("global filtering needs equal lengths")
+    m = len(T)
+    S = np.zeros(max(m, 1), dtype=np.uint8)
+    ones = _load().oracle_shouji_pair_w(P.ctypes.data, T.ctypes.data, m, int(E), int(W), S.ctypes.data)
+    if ones < 0:
+        raise ValueError("bad arguments")
+    return ones, "".join(str(int(b)) for b in S[:m])
+
+
+def shouji_batch_w(P, T, lengths, E, W, nthreads=0):
+    """Batch with W-column windows.  Returns (accept, popcount)."""
+    P = _c(P, np.uint8)
+    T = _c(T, np.uint8)
+    L = _c(lengths, np.int32)
+    n, stride = P.shape
+    acc = np.empty(n, dtype=np.uint8)
+    pc = np.empty(n, dtype=np.int16)
+    rc = _load().oracle_shouji_batch_w(P.ctypes.data, T.ctypes.data, stride, L.ctypes.data, n, int(E), int(W),
+                                       nthreads, acc.ctypes.data, pc.ctypes.data)
+    if rc != 0:
+        raise ValueError("bad arguments")
+    return acc, pc
 
 
 def shouji_pair2(P, T, E, mode=GLOBAL, reading=READING_B):

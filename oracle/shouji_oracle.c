@@ -118,6 +118,67 @@ int oracle_shouji_pair(const uint8_t *P, const uint8_t *T, int32_t m, int32_t E,
 }
 
 /*
+ * Window width W instead of 4 (Suppl. Sec. 6.1, Fig. 4 compares widths): the
+ * same steps with W-column windows: every window i in [0, m) examines the
+ * W-bit segment of each diagonal at text columns i..i+W-1, the winner (most
+ * zeros, then a leading zero, then the evaluation order) is copied into
+ * S[i..i+W-1] when it has strictly more zeros, and the ones of S[0..m) are
+ * counted.  W = 4 is oracle_shouji_pair.  Returns the ones (or -1).
+ */
+int oracle_shouji_pair_w(const uint8_t *P, const uint8_t *T, int32_t m, int32_t E, int32_t W,
+                         uint8_t *S_out) {
+    if (m < 0 || E < 0 || W < 1) return -1;
+    int nd = 2 * E + 1, w = m + W - 1;
+    uint8_t *N = (uint8_t *)malloc((size_t)nd * (size_t)w + 1);
+    uint8_t *S = (uint8_t *)malloc((size_t)w + 1);
+    for (int d = -E; d <= E; d++)
+        for (int j = 0; j < w; j++)
+            N[(size_t)(d + E) * w + j] = (uint8_t)map_cell(P, T, m, d, j);
+    for (int j = 0; j < w; j++) S[j] = 1;
+    for (int i = 0; i < m; i++) {
+        const uint8_t *Z = NULL;
+        int best_key = -1;
+        for (int k = 1; k <= E; k++) {
+            for (int s2 = 0; s2 < 2; s2++) {
+                int d = s2 == 0 ? k : -k;
+                const uint8_t *seg = N + (size_t)(d + E) * w + i;
+                int key = 2 * count_zeros(seg, W) + (seg[0] == 0 ? 1 : 0);
+                if (key > best_key) { best_key = key; Z = seg; }
+            }
+        }
+        const uint8_t *M = N + (size_t)E * w + i;
+        int key = 2 * count_zeros(M, W) + (M[0] == 0 ? 1 : 0);
+        if (key > best_key) { best_key = key; Z = M; }
+        if (count_zeros(Z, W) > count_zeros(S + i, W))
+            for (int t = 0; t < W; t++) S[i + t] = Z[t];
+    }
+    int ones = 0;
+    for (int j = 0; j < m; j++) ones += S[j];
+    if (S_out) memcpy(S_out, S, (size_t)m);
+    free(N); free(S);
+    return ones;
+}
+
+int oracle_shouji_batch_w(const uint8_t *P, const uint8_t *T, int64_t stride, const int32_t *lengths,
+                          int64_t n, int32_t E, int32_t W, int32_t nthreads, uint8_t *out_accept,
+                          int16_t *out_popcount) {
+    if (n < 0 || stride < 0 || E < 0 || W < 1) return -1;
+    #pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : omp_get_max_threads())
+    for (int64_t p = 0; p < n; p++) {
+        int32_t m = lengths[p];
+        if (m < 0 || m > stride) {
+            out_accept[p] = 0xFF;
+            if (out_popcount) out_popcount[p] = -1;
+            continue;
+        }
+        int ones = oracle_shouji_pair_w(P + p * stride, T + p * stride, m, E, W, NULL);
+        out_accept[p] = (uint8_t)(ones <= E ? 1 : 0);
+        if (out_popcount) out_popcount[p] = (int16_t)ones;
+    }
+    return 0;
+}
+
+/*
  * Counting modes of the final step (Sec. 2.2.3: local filtering ignores the
  * ones at both ends of the bit-vector, glocal filtering those at one end;
  * Suppl. Sec. 8, Fig. 6(c)).  The ones "at an end" are the run of ones
