@@ -45,6 +45,7 @@ extern "C" {
 #define SHOUJI_BASES_PER_WORD 16
 #define SHOUJI_MAX_LEN 1024 /* longest supported sequence (bases)            */
 #define SHOUJI_MAX_E 31     /* largest edit threshold after clamping to m-1  */
+#define SHOUJI_MAX_WINDOW 16 /* widest window of shouji_filter_window        */
 
 typedef enum {
     SHOUJI_OK = 0,
@@ -172,6 +173,25 @@ int shouji_tune_batched(const uint32_t *reads, const uint32_t *refs, const int32
                         int64_t n_pairs, int32_t max_len, int64_t ld, void *workspace,
                         int64_t workspace_bytes, void *stream, shouji_batched_config *best,
                         float *best_ms);
+
+/*
+ * Window-width variant: W-column search windows instead of 4.
+ *
+ * Suppl. Sec. 6.1 and Fig. 4 compare the accuracy of window widths (4 is the
+ * paper's choice).  Same steps as shouji_filter with W in place of 4: window
+ * i examines the W-bit segment of every diagonal at text columns i..i+W-1,
+ * the winner (most zeros, then a leading zero, then the order of
+ * shouji_filter) is copied into S[i..i+W-1] when it has strictly more zeros,
+ * and accept = ones(S[0..m)) <= E.  With W = 4 the results equal
+ * shouji_filter's.  A study variant (one pair per lane), far slower than the
+ * W = 4 kernel.
+ *
+ *   W             1..SHOUJI_MAX_WINDOW, else SHOUJI_ERR_RANGE.
+ *   other arguments, sentinels and errors as for shouji_filter.
+ */
+int shouji_filter_window(const uint32_t *reads, const uint32_t *refs, const int32_t *lengths, int32_t E,
+                         int32_t W, uint8_t *out_accept, int16_t *out_popcount, int64_t n_pairs,
+                         int32_t max_len, int64_t ld, void *stream);
 
 /*
  * Verifier: the aligner's threshold test for the pairs a filter accepted.

@@ -53,6 +53,21 @@ struct LocalParams {
     int32_t lds_wave_bytes;
 };
 
+// Window-width variant (one pair per lane).
+struct WindowParams {
+    const uint32_t *reads;
+    const uint32_t *refs;
+    int64_t ld;
+    const int32_t *lengths;
+    int32_t max_len;
+    int32_t E;
+    int32_t Ee;
+    int32_t W;
+    uint8_t *out_accept;
+    int16_t *out_popcount;
+    int64_t n;
+};
+
 // Verifier of filtered pairs (banded edit distance, one pair per lane).
 struct VerifyParams {
     const uint32_t *reads;
