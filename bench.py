@@ -102,6 +102,8 @@ def main():
     ap.add_argument("--batched-n", type=int, default=8_000_000)
     ap.add_argument("--no-verify", action="store_true",
                     help="skip the filter + verifier leg (banded edit distance of accepted pairs)")
+    ap.add_argument("--no-window", action="store_true",
+                    help="skip the window-width leg (false accept rate against W)")
     ap.add_argument("--no-local", action="store_true",
                     help="skip the two-length leg (reads inside longer references, local counting)")
     ap.add_argument("--no-serving", action="store_true",
@@ -226,6 +228,8 @@ def main():
         out["batched"] = bench_batched(args.batched_n, dev)
     if not args.no_verify:
         out["verify"] = bench_verify(reads, refs, lens, acc, pairs, E, ms_per_step, with_oracle=not args.no_cpu)
+    if not args.no_window:
+        out["window"] = bench_window(reads, refs, lens, pairs, E, with_oracle=not args.no_cpu)
     if not args.no_local:
         out["local"] = bench_local(dev, args.n, args.E, ms_per_step, with_oracle=not args.no_cpu)
     if not args.no_serving:
@@ -366,6 +370,56 @@ def bench_verify(reads, refs, lens, acc, pairs, E, filter_ms, steps=20, with_ora
         want = oracle.edit_distance_batch(pairs.P[:ns], pairs.T[:ns], pairs.lengths[:ns], k=E)
         out["mismatches_vs_oracle_sample"] = int((want != d[:ns]).sum())
         out["oracle_sample"] = ns
+    return out
+
+
+def bench_window(reads, refs, lens, pairs, E, widths=(1, 2, 3, 4, 5, 6, 8, 12, 16), steps=5,
+                 with_oracle=True):
+    """Window width against accuracy (Suppl. Sec. 6.1, Fig. 4) on the headline batch:
+    per width W the false accept rate (dissimilar pairs accepted, over all dissimilar
+    pairs) and the false rejects (pairs within E rejected), labels from the GPU
+    verifier's banded edit distance of every pair; with the time of the one-pair-per-lane
+    window kernel.  A sample is checked against the oracle's window-width filter."""
+    import numpy as np
+    import torch
+    import paper_1809_07858_amd as sj
+    n = lens.numel()
+    dev = lens.device
+    max_len = int(lens.max().item())
+    stream = torch.cuda.current_stream()
+    ws = torch.empty(sj.lib().shouji_verify_workspace_bytes(n), dtype=torch.uint8, device=dev)
+    dist = sj.shouji_verify(reads, refs, lens, E, None, max_len=max_len, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+    similar = dist.cpu().numpy() >= 0
+    acc = torch.empty(n, dtype=torch.uint8, device=dev)
+    pc = torch.empty(n, dtype=torch.int16, device=dev)
+    rows = []
+    mism = 0
+    ns = 5_000
+    for W in widths:
+        sj.shouji_filter_window(reads, refs, lens, E, W, acc, pc, max_len=max_len, stream=stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            sj.shouji_filter_window(reads, refs, lens, E, W, acc, pc, max_len=max_len, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        a = acc.cpu().numpy() == 1
+        rows.append({"W": W, "false_accept_rate": float((a & ~similar).sum() / max(1, (~similar).sum())),
+                     "false_rejects": int((~a & similar).sum()), "accepted": int(a.sum()),
+                     "ms": ms, "pairs_per_s": n / (ms / 1e3)})
+        if with_oracle:
+            import oracle
+            wa, wp = oracle.shouji_batch_w(pairs.P[:ns], pairs.T[:ns], pairs.lengths[:ns], E, W)
+            mism += int(((acc[:ns].cpu().numpy() != wa) | (pc[:ns].cpu().numpy() != wp)).sum())
+    out = {"workload": "the plain headline batch (%d pairs, m=%d, E=%d) with W-column windows"
+                       % (n, max_len, E),
+           "similar": int(similar.sum()), "dissimilar": int((~similar).sum()), "widths": rows}
+    if with_oracle:
+        out["mismatches_vs_oracle_sample"] = mism
+        out["oracle_sample"] = "first %d pairs, every width" % ns
     return out
 
 

@@ -110,3 +110,21 @@ def test_batch_w_matches_pairwise():
                 continue
             c, _ = oracle.shouji_pair_w(P[p, :L[p]], T[p, :L[p]], 3, W)
             assert pc[p] == c and acc[p] == (1 if c <= 3 else 0)
+
+
+def test_width2_equals_width1():
+    # With 2-column windows a zero of S is never overwritten (a copy into
+    # S[i..i+1] needs more zeros than S holds there, and S[i+1] is still 1),
+    # and window i picks a segment with a zero at column i whenever one exists
+    # (most zeros first, then a leading zero).  So S[i] = 0 exactly when some
+    # diagonal matches at column i: the W = 1 vector, for every input.
+    rng = np.random.default_rng(16)
+    for _ in range(500):
+        m = int(rng.integers(0, 50))
+        E = int(rng.integers(0, 7))
+        P = rng.integers(0, 4, m).astype(np.uint8)
+        T = P.copy()
+        T[rng.random(m) < 0.3] = rng.integers(0, 4)
+        c1, S1 = oracle.shouji_pair_w(P, T, E, 1)
+        c2, S2 = oracle.shouji_pair_w(P, T, E, 2)
+        assert c1 == c2 and S1 == S2
