@@ -36,7 +36,8 @@ def build():
     tmp = _SO + ".tmp%d" % os.getpid()
     subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
                            os.path.join(_HERE, "shouji_oracle.c"),
-                           os.path.join(_HERE, "levenshtein.c"), "-o", tmp])
+                           os.path.join(_HERE, "levenshtein.c"),
+                           os.path.join(_HERE, "magnet_oracle.c"), "-o", tmp])
     os.replace(tmp, _SO)
 
 
@@ -59,6 +60,10 @@ def _load():
         lib.oracle_shouji_pair_w.argtypes = [vp, vp, i32, i32, i32, vp]
         lib.oracle_shouji_batch_w.restype = ctypes.c_int
         lib.oracle_shouji_batch_w.argtypes = [vp, vp, i64, vp, i64, i32, i32, i32, vp, vp]
+        lib.oracle_magnet_pair.restype = ctypes.c_int
+        lib.oracle_magnet_pair.argtypes = [vp, vp, i32, i32, vp]
+        lib.oracle_magnet_batch.restype = ctypes.c_int
+        lib.oracle_magnet_batch.argtypes = [vp, vp, i64, vp, i64, i32, i32, vp, vp]
         lib.oracle_shouji_map_row.restype = ctypes.c_int
         lib.oracle_shouji_map_row.argtypes = [vp, vp, i32, i32, vp]
         lib.oracle_default_threads.restype = ctypes.c_int
@@ -122,6 +127,37 @@ def shouji_batch_w(P, T, lengths, E, W, nthreads=0):
     pc = np.empty(n, dtype=np.int16)
     rc = _load().oracle_shouji_batch_w(P.ctypes.data, T.ctypes.data, stride, L.ctypes.data, n, int(E), int(W),
                                        nthreads, acc.ctypes.data, pc.ctypes.data)
+    if rc != 0:
+        raise ValueError("bad arguments")
+    return acc, pc
+
+
+def magnet_pair(P, T, E):
+    """MAGNET (Suppl. Sec. 7, Algorithms 3-4) on one equal-length pair.
+    Returns (ones of the MAGNET bit-vector, the vector as a string)."""
+    P = codes(P) if isinstance(P, str) else _c(P, np.uint8)
+    T = codes(T) if isinstance(T, str) else _c(T, np.uint8)
+    if len(P) != len(T):
+        raise ValueError("MAGNET needs equal lengths")
+    m = len(T)
+    V = np.zeros(max(m, 1), dtype=np.uint8)
+    ones = _load().oracle_magnet_pair(P.ctypes.data, T.ctypes.data, m, int(E), V.ctypes.data)
+    if ones < 0:
+        raise ValueError("bad arguments")
+    return ones, "".join(str(int(b)) for b in V[:m])
+
+
+def magnet_batch(P, T, lengths, E, nthreads=0):
+    """MAGNET over a batch (rows of P and T, lengths[p] bases each).  Returns
+    (accept, popcount) with the filter's sentinels for invalid lengths."""
+    P = _c(P, np.uint8)
+    T = _c(T, np.uint8)
+    L = _c(lengths, np.int32)
+    n, stride = P.shape
+    acc = np.empty(n, dtype=np.uint8)
+    pc = np.empty(n, dtype=np.int16)
+    rc = _load().oracle_magnet_batch(P.ctypes.data, T.ctypes.data, stride, L.ctypes.data, n, int(E), nthreads,
+                                     acc.ctypes.data, pc.ctypes.data)
     if rc != 0:
         raise ValueError("bad arguments")
     return acc, pc

@@ -1,0 +1,298 @@
+"""Pins of the MAGNET oracle (Suppl. Sec. 7.1, Algorithms 3-4).
+
+MAGNET has no worked example in the paper; the pins below are results that
+follow from the algorithm's definition (each derivation is in its test),
+invariants of any run of it, and an independent implementation written
+against the listings' own matrix indexing on small inputs."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+
+ACGT = np.array([0, 1, 2, 3], np.uint8)
+
+
+def _periodic(m):
+    return np.resize(ACGT, m).astype(np.uint8)
+
+
+def _substitute(T, pos):
+    P = T.copy()
+    for k in pos:
+        P[k] = (T[k] + 2) % 4
+    return P
+
+
+def test_E0_is_identity():
+    # E = 0: only the main diagonal, at most one run, and the first call needs
+    # a run of ceil(m / 1) = m zeros: accept iff identical, else all ones.
+    rng = np.random.default_rng(20)
+    for _ in range(300):
+        m = int(rng.integers(1, 40))
+        T = rng.integers(0, 4, m).astype(np.uint8)
+        P = T.copy()
+        if rng.random() < 0.7:
+            P[rng.integers(0, m)] ^= 1
+        same = bool((P == T).all())
+        ones, V = oracle.magnet_pair(P, T, 0)
+        assert ones == (0 if same else m)
+
+
+def test_identical_and_large_E():
+    rng = np.random.default_rng(21)
+    for _ in range(200):
+        m = int(rng.integers(0, 60))
+        T = rng.integers(0, 4, m).astype(np.uint8)
+        for E in (0, 1, 3, 9):
+            assert oracle.magnet_pair(T, T, E)[0] == 0
+        # E >= m: the threshold m - E is not positive, every pair is accepted
+        P = rng.integers(0, 4, m).astype(np.uint8)
+        assert oracle.magnet_pair(P, T, m)[0] <= m
+
+
+@pytest.mark.parametrize("E", [1, 2, 3])
+def test_substitutions_closed_form(E):
+    # Text (ACGT)^*, read = text with s substitutions at positions in
+    # [2, m-3] at least 3 apart.  For 0 < |d| <= 3 an unsubstituted read base
+    # never matches (the period is 4), so off-diagonals hold isolated zeros
+    # only; the main diagonal's zero runs (s+1 of them, each >= 2 long) are
+    # separated by single mismatches, so every subproblem [e+2, EI] /
+    # [SI, s-2] is a union of whole main runs and each call extracts one.
+    # With s <= E all s+1 runs are taken (and the longest is at least
+    # ceil((m-E)/(E+1))): ones = s.  With s > E at most E+1 runs: ones > E.
+    rng = np.random.default_rng(22 + E)
+    for _ in range(300):
+        m = int(rng.integers(12, 120))
+        T = _periodic(m)
+        pos, k = [], 2 + int(rng.integers(0, 4))
+        while k <= m - 3:
+            pos.append(k)
+            k += 3 + int(rng.integers(0, 12))
+        s = int(rng.integers(0, len(pos) + 1))
+        pos = sorted(rng.choice(pos, size=s, replace=False).tolist()) if s else []
+        ones, V = oracle.magnet_pair(_substitute(T, pos), T, E)
+        if s <= E:
+            assert ones == s and [i for i, c in enumerate(V) if c == "1"] == pos
+        else:
+            assert ones > E
+
+
+def _runs(v):
+    """Maximal runs of zeros of a 0/1 sequence: list of (start, length)."""
+    out, j = [], 0
+    while j < len(v):
+        if v[j] == 0:
+            s = j
+            while j < len(v) and v[j] == 0:
+                j += 1
+            out.append((s, j - s))
+        else:
+            j += 1
+    return out
+
+
+def _diag(P, T, d):
+    m = len(T)
+    return [1 if not (0 <= j - d < m) else int(P[j - d] != T[j]) for j in range(m)]
+
+
+@pytest.mark.parametrize("E", [1, 2, 3, 5])
+def test_single_insertion_costs_two(E):
+    # Read = text with one base inserted at k (last base dropped).  The main
+    # diagonal matches on [0, k-1], diagonal d = -1 on [k, m-2]: the two runs
+    # touch.  Whichever is taken first, encapsulation removes one position
+    # next to it, so the other is taken one shorter: ones = 2 (k-1 or k, and
+    # m-1).  At E = 1 MAGNET rejects a pair at edit distance 1 -- the false
+    # rejects the paper reports for MAGNET (Sec. 3.2).  Preconditions (no
+    # other run of 8 or more zeros anywhere) are checked directly.
+    rng = np.random.default_rng(30 + E)
+    m, done = 60, 0
+    while done < 40:
+        T = rng.integers(0, 4, m).astype(np.uint8)
+        k = int(rng.integers(12, 29))
+        b = int(rng.integers(0, 4))
+        if b == T[k] or b == T[k - 1]:
+            continue
+        P = np.concatenate([T[:k], [b], T[k:m - 1]]).astype(np.uint8)
+        ok = True
+        for d in range(-E, E + 1):
+            for s, ln in _runs(_diag(P, T, d)):
+                if (d, s, ln) in ((0, 0, k), (-1, k, m - 1 - k)):
+                    continue
+                ok &= ln < 8
+        if not ok:
+            continue
+        done += 1
+        ones, V = oracle.magnet_pair(P, T, E)
+        assert ones == 2 and V[m - 1] == "1" and (V[k - 1] == "1") != (V[k] == "1")
+
+
+@pytest.mark.parametrize("E", [1, 2, 3, 5])
+def test_single_deletion_costs_one(E):
+    # Read = text with base k deleted (a base appended).  The main diagonal
+    # matches on [0, k-1], diagonal d = +1 on [k+1, m-1]; the mismatch at k
+    # is also the encapsulation position, so both runs are taken whole:
+    # ones = 1 at position k.
+    rng = np.random.default_rng(40 + E)
+    m, done = 60, 0
+    while done < 40:
+        T = rng.integers(0, 4, m).astype(np.uint8)
+        k = int(rng.integers(12, 29))
+        if T[k + 1] == T[k] or T[k - 1] == T[k]:
+            continue
+        P = np.concatenate([T[:k], T[k + 1:], [int(rng.integers(0, 4))]]).astype(np.uint8)
+        ok = True
+        for d in range(-E, E + 1):
+            for s, ln in _runs(_diag(P, T, d)):
+                if (d, s, ln) in ((0, 0, k), (1, k + 1, m - 1 - k)):
+                    continue
+                ok &= ln < 8
+        if not ok:
+            continue
+        done += 1
+        ones, V = oracle.magnet_pair(P, T, E)
+        assert ones == 1 and V[k] == "1"
+
+
+def test_worked_cases():
+    # Text (ACGT)^*; main-diagonal runs as listed; off-diagonals hold isolated
+    # zeros only (see test_substitutions_closed_form).
+    # E=1, m=30, substitutions 5 and 22: runs [0,4] [6,21] [23,29].  The first
+    # call takes [6,21] (16 >= ceil(29/2) = 15), the right part comes first
+    # and takes [23,29]; the budget of E+1 = 2 runs is then spent, so [0,4]
+    # stays ones: ones = 6 + 1 = 7 (left first would give 9).
+    T = _periodic(30)
+    ones, V = oracle.magnet_pair(_substitute(T, [5, 22]), T, 1)
+    assert ones == 7 and V == "1" * 6 + "0" * 16 + "1" + "0" * 7
+    # E=2, m=30, substitutions 10, 14, 18, 22: runs [0,9] (10 = ceil(28/3),
+    # the threshold exactly), then [23,29], then the leftmost 3-run [11,13].
+    ones, V = oracle.magnet_pair(_substitute(T, [10, 14, 18, 22]), T, 2)
+    assert ones == 10 and V == "0" * 10 + "1" + "000" + "1" * 9 + "0" * 7
+    # E=2, m=30, substitutions 9, 18, 27: longest run 9 < 10: the first call
+    # stops and the vector stays all ones.
+    ones, V = oracle.magnet_pair(_substitute(T, [9, 18, 27]), T, 2)
+    assert ones == 30
+    # E=1, m=31, substitution 15: runs of 15 and 15 (threshold ceil(30/2) = 15)
+    ones, V = oracle.magnet_pair(_substitute(_periodic(31), [15]), _periodic(31), 1)
+    assert ones == 1
+
+
+def test_invariants():
+    # zeros of V lie on matches of some diagonal |d| <= E; every maximal zero
+    # run of V lies on one diagonal; at most E+1 of them.
+    rng = np.random.default_rng(50)
+    for _ in range(400):
+        m = int(rng.integers(0, 50))
+        E = int(rng.integers(0, 6))
+        T = rng.integers(0, 4, m).astype(np.uint8)
+        P = T.copy()
+        P[rng.random(m) < 0.15] = rng.integers(0, 4)
+        ones, V = oracle.magnet_pair(P, T, E)
+        v = [int(c) for c in V]
+        assert ones == sum(v)
+        diags = {d: _diag(P, T, d) for d in range(-E, E + 1)}
+        runs = _runs(v)
+        assert len(runs) <= E + 1
+        for s, ln in runs:
+            assert any(all(diags[d][j] == 0 for j in range(s, s + ln)) for d in diags)
+        if ones > 0 and ones < m:
+            assert ones <= m
+
+
+def _magnet_matrix(Pseq, Tseq, E):
+    """Independent version, written against the listings' indexing: the map
+    as an m x m matrix N[t][p] (text row t, pattern column p), diagonals
+    walked cell by cell, the recursion replaced by an explicit stack
+    (right part popped before the left one)."""
+    m = len(Tseq)
+    N = [[0 if (abs(t - p) <= E and Pseq[p] == Tseq[t]) else 1 for p in range(m)] for t in range(m)]
+
+    def longest(off, lo, hi):
+        # off > 0: cells N[t][t-off] (lower); off < 0: N[t][t-off] (upper)
+        best, bs, cur = 0, -1, 0
+        for t in range(lo, hi + 1):
+            p = t - off
+            z = 0 <= p < m and N[t][p] == 0
+            cur = cur + 1 if z else 0
+            if cur > best:
+                best, bs = cur, t - cur + 1
+        return best, bs
+
+    a = -(-(m - E) // (E + 1)) if m > E else 0
+    V = [1] * m
+    taken = 0
+    stack = [(0, m - 1, True)]
+    while stack:
+        lo, hi, first = stack.pop()
+        if lo > hi or taken >= E + 1:
+            continue
+        cand = (0, -1)
+        for k in range(1, E + 1):
+            x = longest(k, lo, hi)
+            y = longest(-k, lo, hi)
+            pick = x if x[0] > y[0] else y
+            if pick[0] > cand[0]:
+                cand = pick
+        mn = longest(0, lo, hi)
+        if mn[0] > cand[0]:
+            cand = mn
+        ln, s = cand
+        if first and ln < a:
+            return m, V
+        if ln == 0:
+            continue
+        for t in range(s, s + ln):
+            V[t] = 0
+        taken += 1
+        stack.append((lo, s - 2, False))      # left, popped after the right one
+        stack.append((s + ln + 1, hi, False))  # right
+    return sum(V), V
+
+
+def test_exhaustive_tiny_vs_matrix():
+    seqs = [s for n in (1, 2, 3, 4) for s in itertools.product(range(3), repeat=n)]
+    for E in range(0, 4):
+        for a in seqs:
+            for b in seqs:
+                if len(a) != len(b):
+                    continue
+                got = oracle.magnet_pair(np.array(a, np.uint8), np.array(b, np.uint8), E)
+                want = _magnet_matrix(a, b, E)
+                assert got[0] == want[0] and got[1] == "".join(map(str, want[1])), (a, b, E)
+
+
+def test_random_vs_matrix():
+    rng = np.random.default_rng(51)
+    for _ in range(600):
+        m = int(rng.integers(1, 40))
+        E = int(rng.integers(0, 7))
+        alpha = int(rng.integers(2, 5))
+        T = rng.integers(0, alpha, m).astype(np.uint8)
+        P = T.copy()
+        P[rng.random(m) < rng.random() * 0.4] = rng.integers(0, alpha)
+        if rng.random() < 0.3:
+            k = int(rng.integers(0, m))
+            P = np.concatenate([P[:k], rng.integers(0, alpha, 1), P[k:m - 1]]).astype(np.uint8)
+        got = oracle.magnet_pair(P, T, E)
+        want = _magnet_matrix(list(P), list(T), E)
+        assert got[0] == want[0] and got[1] == "".join(map(str, want[1])), (P, T, E)
+
+
+def test_batch_matches_pairwise():
+    rng = np.random.default_rng(52)
+    n, stride = 300, 50
+    P = rng.integers(0, 4, (n, stride)).astype(np.uint8)
+    T = P.copy()
+    T[rng.random((n, stride)) < 0.08] = 3
+    L = rng.integers(0, stride + 1, n).astype(np.int32)
+    L[::23] = stride + 2
+    for E in (0, 2, 5):
+        acc, pc = oracle.magnet_batch(P, T, L, E)
+        for p in range(n):
+            if L[p] > stride:
+                assert acc[p] == 0xFF and pc[p] == -1
+                continue
+            c, _ = oracle.magnet_pair(P[p, :L[p]], T[p, :L[p]], E)
+            assert pc[p] == c and acc[p] == (1 if c <= E else 0)
