@@ -194,6 +194,31 @@ int shouji_filter_window(const uint32_t *reads, const uint32_t *refs, const int3
                          int32_t max_len, int64_t ld, void *stream);
 
 /*
+ * MAGNET: the divide-and-conquer filter of Suppl. Sec. 7.1 (Algorithms 3
+ * and 4) over the same neighbourhood map (Eq. 1, diagonals indexed by text
+ * position, cells outside the map are ones).
+ *
+ * Per pair: the longest run of zeros over all diagonals inside the whole
+ * sequence is taken (per diagonal the leftmost of equal runs; across
+ * diagonals the order d = -1, +1, ..., -E, +E, main, a later run replacing
+ * the kept one only when strictly longer); if it is shorter than
+ * ceil((m-E)/(E+1)) the pair is rejected with all m positions counted as
+ * ones.  Otherwise it counts as matched, and the parts right of it and left
+ * of it, each without the one position next to the run, are solved the same
+ * way (right part first, no threshold), until E+1 runs are taken; a part with
+ * no zero on any diagonal takes none.  popcount = m - total length of the
+ * runs taken; accept = popcount <= E.  MAGNET rejects some pairs within E
+ * (a single insertion costs 2), as the paper reports for it.
+ *
+ *   arguments, layout, sentinels and errors as for shouji_filter (E is
+ *   clamped to m-1 for the diagonals only; E > SHOUJI_MAX_E after that
+ *   clamp is SHOUJI_ERR_RANGE).  One pair per lane; no workspace.
+ */
+int shouji_filter_magnet(const uint32_t *reads, const uint32_t *refs, const int32_t *lengths, int32_t E,
+                         uint8_t *out_accept, int16_t *out_popcount, int64_t n_pairs, int32_t max_len,
+                         int64_t ld, void *stream);
+
+/*
  * Verifier: the aligner's threshold test for the pairs a filter accepted.
  *
  * A filtered pair goes on to alignment (Sec. 1; Sec. 3.3 and Table 3 measure

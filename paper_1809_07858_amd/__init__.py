@@ -65,6 +65,8 @@ def lib():
         L.shouji_filter_local.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp, i64, i32, i64, vp]
         L.shouji_filter_window.restype = ctypes.c_int
         L.shouji_filter_window.argtypes = [vp, vp, vp, i32, i32, vp, vp, i64, i32, i64, vp]
+        L.shouji_filter_magnet.restype = ctypes.c_int
+        L.shouji_filter_magnet.argtypes = [vp, vp, vp, i32, vp, vp, i64, i32, i64, vp]
         L.shouji_verify_workspace_bytes.restype = ctypes.c_int64
         L.shouji_verify_workspace_bytes.argtypes = [i64]
         L.shouji_verify.restype = ctypes.c_int
@@ -257,6 +259,38 @@ def shouji_filter_window(reads, refs, lengths, E, W, out_accept=None, out_popcou
     _check(lib().shouji_filter_window(
         ctypes.c_void_p(reads.data_ptr()), ctypes.c_void_p(refs.data_ptr()),
         None if lengths is None else ctypes.c_void_p(lengths.data_ptr()), int(E), int(W),
+        ctypes.c_void_p(out_accept.data_ptr()),
+        None if out_popcount is None else ctypes.c_void_p(out_popcount.data_ptr()),
+        int(n_pairs), int(max_len), int(ld), _stream_handle(stream)))
+    return out_accept, out_popcount
+
+
+def shouji_filter_magnet(reads, refs, lengths, E, out_accept=None, out_popcount=None, n_pairs=None,
+                         max_len=None, stream=None, want_popcount=True):
+    """MAGNET filter (divide-and-conquer runs of matches) on equal-length pairs."""
+    import torch
+    if reads.dim() != 2 or refs.shape != reads.shape:
+        raise ValueError("reads/refs must be [nwords, ld] tensors of the same shape")
+    for t in (reads, refs):
+        if not t.is_cuda or t.dtype != torch.int32 or not t.is_contiguous():
+            raise ValueError("reads/refs must be contiguous int32 CUDA tensors")
+    ld = reads.shape[1]
+    if n_pairs is None:
+        n_pairs = ld
+    if max_len is None:
+        max_len = reads.shape[0] * BASES_PER_WORD
+    if reads.shape[0] < nwords(max_len):
+        raise ValueError("reads hold fewer words than max_len needs")
+    if lengths is not None and (not lengths.is_cuda or lengths.dtype != torch.int32 or lengths.numel() < n_pairs):
+        raise ValueError("lengths must be an int32 CUDA tensor with n_pairs entries")
+    dev = reads.device
+    if out_accept is None:
+        out_accept = torch.empty(n_pairs, dtype=torch.uint8, device=dev)
+    if out_popcount is None and want_popcount:
+        out_popcount = torch.empty(n_pairs, dtype=torch.int16, device=dev)
+    _check(lib().shouji_filter_magnet(
+        ctypes.c_void_p(reads.data_ptr()), ctypes.c_void_p(refs.data_ptr()),
+        None if lengths is None else ctypes.c_void_p(lengths.data_ptr()), int(E),
         ctypes.c_void_p(out_accept.data_ptr()),
         None if out_popcount is None else ctypes.c_void_p(out_popcount.data_ptr()),
         int(n_pairs), int(max_len), int(ld), _stream_handle(stream)))

@@ -6,7 +6,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "libshouji.so")
 SOURCES = ["csrc/shouji_plain.hip", "csrc/shouji_batched.hip", "csrc/shouji_abi.hip",
-           "csrc/shouji_server.hip", "csrc/shouji_verify.hip", "csrc/shouji_window.hip"]
+           "csrc/shouji_server.hip", "csrc/shouji_verify.hip", "csrc/shouji_window.hip",
+           "csrc/shouji_magnet.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # no packed-FP32 instructions anywhere in the device code

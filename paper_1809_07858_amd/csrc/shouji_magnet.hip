@@ -1,0 +1,178 @@
+// MAGNET pre-alignment filter (Suppl. Sec. 7.1, Algorithms 3 and 4): the
+// variant of the Shouji paper that shares its neighbourhood map (Eq. 1) and
+// replaces the window search by a divide-and-conquer extraction of the
+// longest runs of matches.
+//
+// Per pair: the 2E+1 diagonals are indexed by text position.  Starting from
+// the whole range, a subproblem [lo, hi] takes the longest run of zeros over
+// all diagonals (per diagonal the leftmost of equally long runs; across
+// diagonals the order d = -1, +1, -2, +2, ..., -E, +E, then the main
+// diagonal, a later one replacing the kept run only when strictly longer),
+// counts it as zeros of the MAGNET bit-vector, and splits into the parts
+// right of it and left of it, each shortened by one encapsulating position;
+// the right part is solved first.  At most E+1 runs are taken; a part with no
+// zero on any diagonal takes none; the first subproblem stops the pair at
+// once when its run is shorter than ceil((m-E)/(E+1)).  Accept iff the
+// vector has at most E ones.  Runs taken lie in disjoint parts, so only
+// their total length is kept.
+//
+// One pair per lane: the recursion is a stack of pending parts in LDS (the
+// right part pushed last, so that its whole subtree is solved before the
+// left part).  A diagonal's run search walks 16 text positions per step: the
+// reference word, the read's two words around the diagonal's offset joined
+// with v_alignbit, one XOR and a fold give the 16 mismatch bits, and only
+// the mismatches inside the part are visited (each closes a run of zeros).
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/shouji.h"
+#include "shouji_internal.h"
+
+namespace shouji {
+
+namespace {
+
+// even-bit mask of the 2-bit fields 0..n-1 (n in [0, 16])
+__device__ __forceinline__ uint32_t field_mask(int n) {
+    return n >= 16 ? 0x55555555u : (0x55555555u & ((1u << (2 * n)) - 1u));
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kMagnetBlock) void magnet_kernel(MagnetParams prm) {
+    __shared__ uint32_t stack[kMagnetStack * kMagnetBlock];
+    const int tid = threadIdx.x;
+    const int64_t p = (int64_t)blockIdx.x * kMagnetBlock + tid;
+    if (p >= prm.n) return;
+    const int m = prm.lengths ? prm.lengths[p] : prm.max_len;
+    if (m < 0 || m > prm.max_len) {
+        prm.out_accept[p] = 0xFF;
+        if (prm.out_popcount) prm.out_popcount[p] = -1;
+        return;
+    }
+    const int E = prm.E;
+    const int Ee = prm.Ee;
+    const uint32_t *P = prm.reads + p;
+    const uint32_t *T = prm.refs + p;
+    const int64_t ld = prm.ld;
+    const int nw = (m + 15) >> 4;                       // words holding the pair's bases
+    const int thr = m > E ? (m - E + (E + 1) - 1) / (E + 1) : 0;   // ceil((m-E)/(E+1))
+
+    // longest run of zeros of diagonal d inside text positions [lo, hi]
+    auto longest = [&](int d, int lo, int hi, int &start) -> int {
+        const int a = lo > d ? lo : d;                       // pattern index j-d >= 0
+        const int b = hi < m - 1 + d ? hi : m - 1 + d;       // pattern index j-d < m
+        int best = 0;
+        start = 0;
+        if (a > b) return 0;
+        int rs = a;                                          // start of the current run
+        for (int w = a >> 4; w <= (b >> 4); w++) {
+            const uint32_t tw = T[(int64_t)w * ld];
+            const int q0 = 16 * w - d;                       // read position of the word's field 0
+            const int qw = q0 >> 4;                          // floor division
+            const int ob = (q0 & 15) * 2;
+            const uint32_t lo_w = (qw >= 0 && qw < nw) ? P[(int64_t)qw * ld] : 0u;
+            const uint32_t hi_w = (qw + 1 >= 0 && qw + 1 < nw) ? P[(int64_t)(qw + 1) * ld] : 0u;
+            const uint32_t pv = __builtin_amdgcn_alignbit(hi_w, lo_w, ob);
+            const uint32_t x = tw ^ pv;
+            const int klo = a - 16 * w > 0 ? a - 16 * w : 0;
+            const int khi = b - 16 * w < 15 ? b - 16 * w : 15;
+            uint32_t z = ((x | (x >> 1)) & field_mask(khi + 1)) & ~field_mask(klo);
+            while (z) {
+                const int q = 16 * w + (__builtin_ctz(z) >> 1);   // a mismatch closes the run
+                if (q - rs > best) {
+                    best = q - rs;
+                    start = rs;
+                }
+                rs = q + 1;
+                z &= z - 1u;
+            }
+        }
+        if (b + 1 - rs > best) {
+            best = b + 1 - rs;
+            start = rs;
+        }
+        return best;
+    };
+
+    uint32_t *stk = stack + tid;                              // entry k at stk[k * kMagnetBlock]
+    int sp = 0;
+    if (m > 0) {
+        stk[0] = (uint32_t)(m - 1) << 16;                    // [0, m-1]
+        sp = 1;
+    }
+    int zeros = 0, taken = 0;
+    bool first = true;
+    while (sp > 0) {
+        sp--;
+        const uint32_t e = stk[sp * kMagnetBlock];
+        const int lo = (int)(e & 0xFFFFu), hi = (int)(e >> 16);
+        int len = 0, s = 0;
+        for (int r = 0; r < 2 * Ee + 1; r++) {
+            const int d = r == 2 * Ee ? 0 : ((r & 1) ? (r >> 1) + 1 : -((r >> 1) + 1));
+            int st;
+            const int l = longest(d, lo, hi, st);
+            if (l > len) {
+                len = l;
+                s = st;
+            }
+        }
+        if (first && len < thr) {                            // early termination: all ones
+            zeros = 0;
+            break;
+        }
+        first = false;
+        if (len == 0) continue;                              // no zero in this part
+        zeros += len;
+        if (++taken == E + 1) break;                         // E+1 runs taken
+        // left part [lo, s-2], then right part [s+len+1, hi] on top
+        if (lo <= s - 2 && sp < kMagnetStack) stk[(sp++) * kMagnetBlock] = (uint32_t)lo | ((uint32_t)(s - 2) << 16);
+        if (s + len + 1 <= hi && sp < kMagnetStack)
+            stk[(sp++) * kMagnetBlock] = (uint32_t)(s + len + 1) | ((uint32_t)hi << 16);
+    }
+    const int ones = m - zeros;
+    prm.out_accept[p] = ones <= E ? 1 : 0;
+    if (prm.out_popcount) prm.out_popcount[p] = (int16_t)ones;
+}
+
+}  // namespace shouji
+
+extern "C" int shouji_filter_magnet(const uint32_t *reads, const uint32_t *refs, const int32_t *lengths, int32_t E,
+                                    uint8_t *out_accept, int16_t *out_popcount, int64_t n_pairs, int32_t max_len,
+                                    int64_t ld, void *stream) {
+    using shouji::set_error;
+    if (n_pairs < 0) return set_error(SHOUJI_ERR_ARG, "shouji_filter_magnet: n_pairs < 0");
+    if (E < 0) return set_error(SHOUJI_ERR_ARG, "shouji_filter_magnet: E < 0 (%d)", E);
+    if (max_len < 0 || max_len > SHOUJI_MAX_LEN)
+        return set_error(SHOUJI_ERR_RANGE, "shouji_filter_magnet: max_len %d outside [0, %d]", max_len,
+                         SHOUJI_MAX_LEN);
+    const int32_t Ee = max_len > 0 ? (E < max_len - 1 ? E : max_len - 1) : 0;
+    if (Ee > SHOUJI_MAX_E)
+        return set_error(SHOUJI_ERR_RANGE, "shouji_filter_magnet: E %d (clamped %d) above %d", E, Ee, SHOUJI_MAX_E);
+    if (n_pairs == 0) return shouji::clear_error();
+    if (!reads || !refs || !out_accept)
+        return set_error(SHOUJI_ERR_NULL, "shouji_filter_magnet: reads, refs and out_accept are required");
+    if (ld < n_pairs)
+        return set_error(SHOUJI_ERR_ARG, "shouji_filter_magnet: ld %lld < n_pairs %lld", (long long)ld,
+                         (long long)n_pairs);
+    if ((n_pairs + shouji::kMagnetBlock - 1) / shouji::kMagnetBlock > 0x7fffffff)
+        return set_error(SHOUJI_ERR_ARG, "shouji_filter_magnet: n_pairs too large");
+    shouji::MagnetParams prm;
+    prm.reads = reads;
+    prm.refs = refs;
+    prm.ld = ld;
+    prm.lengths = lengths;
+    prm.max_len = max_len;
+    prm.E = E < max_len ? E : max_len;   // E >= m behaves as E = m: no early stop, every run, accepted
+    prm.Ee = Ee;
+    prm.out_accept = out_accept;
+    prm.out_popcount = out_popcount;
+    prm.n = n_pairs;
+    const unsigned grid = (unsigned)((n_pairs + shouji::kMagnetBlock - 1) / shouji::kMagnetBlock);
+    hipLaunchKernelGGL(shouji::magnet_kernel, dim3(grid), dim3(shouji::kMagnetBlock), 0, (hipStream_t)stream, prm);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return set_error(SHOUJI_ERR_DEVICE, "shouji_filter_magnet: launch failed: %s", hipGetErrorString(e));
+    return shouji::clear_error();
+}
