@@ -104,6 +104,8 @@ def main():
                     help="skip the filter + verifier leg (banded edit distance of accepted pairs)")
     ap.add_argument("--no-window", action="store_true",
                     help="skip the window-width leg (false accept rate against W)")
+    ap.add_argument("--no-magnet", action="store_true",
+                    help="skip the MAGNET leg (Suppl. Sec. 7 filter on the headline batch)")
     ap.add_argument("--no-local", action="store_true",
                     help="skip the two-length leg (reads inside longer references, local counting)")
     ap.add_argument("--no-serving", action="store_true",
@@ -230,6 +232,8 @@ def main():
         out["verify"] = bench_verify(reads, refs, lens, acc, pairs, E, ms_per_step, with_oracle=not args.no_cpu)
     if not args.no_window:
         out["window"] = bench_window(reads, refs, lens, pairs, E, with_oracle=not args.no_cpu)
+    if not args.no_magnet:
+        out["magnet"] = bench_magnet(reads, refs, lens, acc, pairs, E, ms_per_step, with_oracle=not args.no_cpu)
     if not args.no_local:
         out["local"] = bench_local(dev, args.n, args.E, ms_per_step, with_oracle=not args.no_cpu)
     if not args.no_serving:
@@ -420,6 +424,53 @@ def bench_window(reads, refs, lens, pairs, E, widths=(1, 2, 3, 4, 5, 6, 8, 12, 1
     if with_oracle:
         out["mismatches_vs_oracle_sample"] = mism
         out["oracle_sample"] = "first %d pairs, every width" % ns
+    return out
+
+
+def bench_magnet(reads, refs, lens, shouji_acc, pairs, E, shouji_ms, steps=10, with_oracle=True):
+    """MAGNET (Suppl. Sec. 7, Algorithms 3-4) on the headline batch: throughput of the
+    one-pair-per-lane kernel and its false accepts / false rejects next to Shouji's, labels
+    from the GPU verifier's distances of every pair (the comparison of Sec. 3.2 / Table 3
+    on synthetic pairs).  A sample is checked against the oracle's MAGNET."""
+    import numpy as np
+    import torch
+    import paper_1809_07858_amd as sj
+    n = lens.numel()
+    dev = lens.device
+    max_len = int(lens.max().item())
+    stream = torch.cuda.current_stream()
+    ws = torch.empty(sj.lib().shouji_verify_workspace_bytes(n), dtype=torch.uint8, device=dev)
+    dist = sj.shouji_verify(reads, refs, lens, E, None, max_len=max_len, workspace=ws, stream=stream)
+    acc = torch.empty(n, dtype=torch.uint8, device=dev)
+    pc = torch.empty(n, dtype=torch.int16, device=dev)
+    for _ in range(2):
+        sj.shouji_filter_magnet(reads, refs, lens, E, acc, pc, max_len=max_len, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        sj.shouji_filter_magnet(reads, refs, lens, E, acc, pc, max_len=max_len, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    similar = dist.cpu().numpy() >= 0
+    a = acc.cpu().numpy() == 1
+    s_a = shouji_acc.cpu().numpy() == 1
+    nd = max(1, int((~similar).sum()))
+    out = {"workload": "the plain headline batch (%d pairs, m=%d, E=%d), MAGNET" % (n, max_len, E),
+           "value": n / (ms / 1e3), "unit": "pairs/s", "ms": ms, "shouji_ms": shouji_ms,
+           "similar": int(similar.sum()), "dissimilar": int((~similar).sum()),
+           "magnet_false_accept_rate": float((a & ~similar).sum() / nd),
+           "magnet_false_rejects": int((~a & similar).sum()),
+           "shouji_false_accept_rate": float((s_a & ~similar).sum() / nd),
+           "shouji_false_rejects": int((~s_a & similar).sum())}
+    if with_oracle:
+        import oracle
+        ns = 50_000
+        wa, wp = oracle.magnet_batch(pairs.P[:ns], pairs.T[:ns], pairs.lengths[:ns], E)
+        out["mismatches_vs_oracle_sample"] = int(((acc[:ns].cpu().numpy() != wa) |
+                                                  (pc[:ns].cpu().numpy() != wp)).sum())
+        out["oracle_sample"] = ns
     return out
 
 

@@ -53,37 +53,6 @@ struct LocalParams {
     int32_t lds_wave_bytes;
 };
 
-// Window-width variant (one pair per lane).
-struct WindowParams {
-    const uint32_t *reads;
-    const uint32_t *refs;
-    int64_t ld;
-    const int32_t *lengths;
-    int32_t max_len;
-    int32_t E;
-    int32_t Ee;
-    int32_t W;
-    uint8_t *out_accept;
-    int16_t *out_popcount;
-    int64_t n;
-};
-
-// MAGNET filter (one pair per lane, LDS stack of pending subproblems).
-constexpr int kMagnetBlock = 256;
-constexpr int kMagnetStack = 32;     // entries per lane; at most min(E+1, 17) are ever live
-struct MagnetParams {
-    const uint32_t *reads;
-    const uint32_t *refs;
-    int64_t ld;
-    const int32_t *lengths;
-    int32_t max_len;
-    int32_t E;       // min(E, max_len): the same results as E for every pair
-    int32_t Ee;      // diagonals examined: min(E, max_len - 1)
-    uint8_t *out_accept;
-    int16_t *out_popcount;
-    int64_t n;
-};
-
 // Verifier of filtered pairs (banded edit distance, one pair per lane).
 struct VerifyParams {
     const uint32_t *reads;

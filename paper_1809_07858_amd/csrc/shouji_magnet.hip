@@ -28,6 +28,7 @@
 
 #include "../../include/shouji.h"
 #include "shouji_internal.h"
+#include "shouji_variants.h"
 
 namespace shouji {
 

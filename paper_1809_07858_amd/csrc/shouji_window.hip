@@ -19,6 +19,7 @@
 
 #include "../../include/shouji.h"
 #include "shouji_internal.h"
+#include "shouji_variants.h"
 
 namespace shouji {
 
