@@ -31,22 +31,52 @@ constexpr int32_t kBandInf = 0x3FFF;   // cells outside the map / band
 }
 
 // out: -2 for pairs the filter did not accept, -3 for invalid lengths;
-// pairs to verify are appended to list (count in *count).
-__global__ void verify_collect_kernel(const uint8_t *__restrict__ accept, const int32_t *__restrict__ lengths,
-                                      int32_t max_len, int64_t n, int16_t *__restrict__ out,
-                                      int64_t *__restrict__ list, unsigned long long *__restrict__ count) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const int32_t m = lengths ? lengths[p] : max_len;
-    if (m < 0 || m > max_len) {
-        out[p] = -3;
-        return;
+// pairs to verify are appended to list (count in *count).  A workgroup
+// handles kCollectPairs pairs and reserves its slice of the list with one
+// atomic (one per 64 lanes serialises on the counter's address).
+constexpr int kCollectBlock = 256;
+constexpr int kCollectPer = 16;
+constexpr int kCollectPairs = kCollectBlock * kCollectPer;
+
+__global__ __launch_bounds__(kCollectBlock) void verify_collect_kernel(
+        const uint8_t *__restrict__ accept, const int32_t *__restrict__ lengths, int32_t max_len, int64_t n,
+        int16_t *__restrict__ out, int64_t *__restrict__ list, unsigned long long *__restrict__ count) {
+    __shared__ int wave_total[kCollectBlock / 64];
+    __shared__ unsigned long long block_base;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kCollectPairs + tid;
+    uint32_t want = 0u;                        // bit i: pair base + i * kCollectBlock is verified
+#pragma unroll
+    for (int i = 0; i < kCollectPer; i++) {
+        const int64_t p = base + (int64_t)i * kCollectBlock;
+        if (p >= n) break;
+        const int32_t m = lengths ? lengths[p] : max_len;
+        if (m < 0 || m > max_len)
+            out[p] = -3;
+        else if (accept && accept[p] != 1)
+            out[p] = -2;
+        else
+            want |= 1u << i;
     }
-    if (accept && accept[p] != 1) {
-        out[p] = -2;
-        return;
+    // exclusive prefix of the per-lane counts over the workgroup
+    const int c = __popc(want);
+    int incl = c;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
     }
-    list[atomicAdd(count, 1ull)] = p;
+    if (lane == 63) wave_total[wave] = incl;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int w = 0; w < kCollectBlock / 64; w++) {
+        before += w < wave ? wave_total[w] : 0;
+        total += wave_total[w];
+    }
+    if (tid == 0) block_base = total ? atomicAdd(count, (unsigned long long)total) : 0ull;
+    __syncthreads();
+    int64_t slot = (int64_t)block_base + before + incl - c;
+    for (int i = 0; i < kCollectPer; i++)
+        if (want & (1u << i)) list[slot++] = base + (int64_t)i * kCollectBlock;
 }
 
 __global__ void zero_counter_kernel(unsigned long long *count) { *count = 0ull; }
@@ -172,9 +202,10 @@ extern "C" int shouji_verify(const uint32_t *reads, const uint32_t *refs, const 
     auto *count = reinterpret_cast<unsigned long long *>(workspace);
     auto *list = reinterpret_cast<int64_t *>(reinterpret_cast<char *>(workspace) + 256);
     const unsigned grid = (unsigned)((n_pairs + 255) / 256);
+    const unsigned cgrid = (unsigned)((n_pairs + shouji::kCollectPairs - 1) / shouji::kCollectPairs);
     hipLaunchKernelGGL(shouji::zero_counter_kernel, dim3(1), dim3(1), 0, st, count);
-    hipLaunchKernelGGL(shouji::verify_collect_kernel, dim3(grid), dim3(256), 0, st, filter_accept, lengths,
-                       max_len, n_pairs, out_distance, list, count);
+    hipLaunchKernelGGL(shouji::verify_collect_kernel, dim3(cgrid), dim3(shouji::kCollectBlock), 0, st,
+                       filter_accept, lengths, max_len, n_pairs, out_distance, list, count);
     shouji::VerifyParams prm;
     prm.reads = reads;
     prm.refs = refs;
