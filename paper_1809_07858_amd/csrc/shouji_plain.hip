@@ -37,6 +37,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "shouji_internal.h"
 
 namespace shouji {
@@ -277,7 +279,7 @@ struct Ends {
 // multiple of NB, uniform) into the tracker.
 template <int NB>
 __device__ __forceinline__ void track_ends(Ends &X, const uint32_t (&o)[NB], int start) {
-    constexpr int LB = NB == 8 ? 3 : 2;   // index bits within the block
+    constexpr int LB = NB == 8 ? 3 : (NB == 4 ? 2 : 1);   // index bits within the block
     uint32_t any, f[LB], l[LB];
     if constexpr (NB == 8) {
         const uint32_t all_lo = gate<kTTAnd3>(o[0], o[1], o[2]) & o[3];   // no zero in 0..3
@@ -297,14 +299,18 @@ __device__ __forceinline__ void track_ends(Ends &X, const uint32_t (&o)[NB], int
         for (int j = 0; j < 4; j++) r[j] = mux(all_hi, o[j], o[4 + j]);
         l[1] = ~(r[2] & r[3]);
         l[0] = ~mux(l[1], r[3], r[1]);
-    } else {
-        static_assert(NB == 4, "blocks of 8 or 4 windows");
+    } else if constexpr (NB == 4) {
         const uint32_t all = gate<kTTAnd3>(o[0], o[1], o[2]) & o[3];
         any = ~all;
         f[1] = o[0] & o[1];
         f[0] = mux(f[1], o[2], o[0]);
         l[1] = ~(o[2] & o[3]);
         l[0] = ~mux(l[1], o[3], o[1]);
+    } else {
+        static_assert(NB == 2, "blocks of 8, 4 or 2 windows");
+        any = ~(o[0] & o[1]);
+        f[0] = o[0];
+        l[0] = ~o[1];
     }
     const uint32_t nf = any & ~X.seen;    // this block holds the first zero
 #pragma unroll
@@ -316,12 +322,11 @@ __device__ __forceinline__ void track_ends(Ends &X, const uint32_t (&o)[NB], int
     X.seen |= any;
 }
 
-// Shouji bit-vector update over the NB windows of a block, then carry-save
-// accumulation of the NB bits that became final (and, with TWO, the
-// positions of their zeros; the block starts at position `start`).
-template <int NB, bool TWO>
-__device__ __forceinline__ void block_update(FsmState &F, const Winner<NB> &W, Ends &X, int start) {
-    uint32_t o[NB];
+// Shouji bit-vector update over the NB windows of a block: the serial part
+// (one lane half at a time).  o[w] receives the bit S[start+w] that became
+// final at window start+w.
+template <int NB>
+__device__ __forceinline__ void block_fsm(FsmState &F, const Winner<NB> &W, uint32_t (&o)[NB]) {
 #pragma unroll
     for (int w = 0; w < NB; w++) {
         const uint32_t q0 = gate<kTTXor3>(F.s0, F.s1, F.s2);  // ones(S[i..i+2]) = q1 q0
@@ -337,6 +342,13 @@ __device__ __forceinline__ void block_update(FsmState &F, const Winner<NB> &W, E
         const uint32_t n3 = gate<kTTOrNotA>(wr, W.Z3[w], W.Z3[w]);
         F.s0 = n1; F.s1 = n2; F.s2 = n3;
     }
+}
+
+// Carry-save accumulation of the NB final bits o[] of a block (and, with
+// TWO, the positions of their zeros; the block starts at position `start`).
+// Independent per lane half, so both halves run it together.
+template <int NB, bool TWO>
+__device__ __forceinline__ void block_count(FsmState &F, const uint32_t (&o)[NB], Ends &X, int start) {
     uint32_t t1, t2, f1, f2, g;
 #define SHOUJI_CSA(h, l, a_, b_, c_)                       \
     {                                                      \
@@ -345,15 +357,23 @@ __device__ __forceinline__ void block_update(FsmState &F, const Winner<NB> &W, E
         l = gate<kTTXor3>(aa_, bb_, cc_);                  \
     }
     SHOUJI_CSA(t1, F.ones, F.ones, o[0], o[1])
-    SHOUJI_CSA(t2, F.ones, F.ones, o[2], o[3])
-    SHOUJI_CSA(f1, F.twos, F.twos, t1, t2)
+    if constexpr (NB == 2) {
+        f1 = F.twos & t1;                 // weight 4
+        F.twos ^= t1;
+    } else {
+        SHOUJI_CSA(t2, F.ones, F.ones, o[2], o[3])
+        SHOUJI_CSA(f1, F.twos, F.twos, t1, t2)
+    }
     if constexpr (NB == 8) {
         SHOUJI_CSA(t1, F.ones, F.ones, o[4], o[5])
         SHOUJI_CSA(t2, F.ones, F.ones, o[6], o[7])
         SHOUJI_CSA(f2, F.twos, F.twos, t1, t2)
         SHOUJI_CSA(g, F.fours, F.fours, f1, f2)
+    } else if constexpr (NB == 4) {
+        g = F.fours & f1;
+        F.fours ^= f1;
     } else {
-        static_assert(NB == 4, "blocks of 8 or 4 windows");
+        static_assert(NB == 2, "blocks of 8, 4 or 2 windows");
         g = F.fours & f1;
         F.fours ^= f1;
     }
@@ -368,17 +388,22 @@ __device__ __forceinline__ void block_update(FsmState &F, const Winner<NB> &W, E
 }
 
 // One 16-base word of 32 pairs (pair = base + 32k + pl for bit k) from row
-// `row` (= seq + w*ld + base).  `full`: all 1024 pairs of the wavefront exist,
-// so no per-pair range check is needed.
-__device__ __forceinline__ void load_word(const uint32_t *__restrict__ row, bool full,
-                                          int64_t left, int pl, uint32_t (&raw)[32]) {
+// `row` (= seq + w*ld + base).  `full`: all 1024 pairs of the wavefront exist.
+// Otherwise only row[0 .. left-1] exist: a missing pair reads the last one
+// (its bits are never written out), so no load is predicated; the bound is
+// made opaque so that the per-pair indices are not hoisted out of the
+// caller's loop and kept live in registers.
+__device__ __forceinline__ void load_word(const uint32_t *__restrict__ row, bool full, int left, int pl,
+                                          uint32_t (&raw)[32]) {
     const uint32_t *q = row + pl;
     if (full) {
 #pragma unroll
         for (int k = 0; k < 32; k++) raw[k] = q[k * kPairLanes];
     } else {
+        int last = left - 1 - pl;            // q[last] is the wavefront's last pair
+        asm volatile("" : "+v"(last));
 #pragma unroll
-        for (int k = 0; k < 32; k++) raw[k] = (k * kPairLanes + pl < left) ? q[k * kPairLanes] : 0u;
+        for (int k = 0; k < 32; k++) raw[k] = q[min(k * kPairLanes, last)];
     }
 }
 
@@ -435,43 +460,63 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     uint32_t lenw[32], lenr[TWO ? 32 : 1];
     uint32_t valid = 0u;
     int lmin = 0x7fffffff, lmax = -1, rmin = 0x7fffffff, rmax = -1;
-    {
-        const int32_t *lp = J.lengths ? J.lengths + base + pl : nullptr;
-        const int32_t *tp = TWO ? J.ref_lengths + base + pl : nullptr;
+    // pairs of this wavefront: lane pair q = 32k + pl exists iff q < left
+    const int left = (int)min(n - base, (int64_t)kPairsPerWave);
+    // Loads are never predicated (a missing pair reads the last one and is
+    // then replaced by -1), and each length is materialised at once, so that
+    // no per-pair lane mask stays live into the window loop.  All loads are
+    // issued first: the lengths, then text / pattern word 0 (which does not
+    // depend on them).
+    const int32_t *lp = J.lengths ? J.lengths + base : nullptr;
+    const int32_t *tp = TWO ? J.ref_lengths + base : nullptr;
+    int mv[32], mtv[TWO ? 32 : 1];
+    if (full) {
 #pragma unroll
         for (int k = 0; k < 32; k++) {
-            int m = J.max_len;
-            const bool in = full || (base + (int64_t)k * kPairLanes + pl < n);
-            if (lp) m = in ? lp[k * kPairLanes] : -1;
-            if constexpr (TWO) {
-                const int mt = in ? tp[k * kPairLanes] : -1;
-                const bool ok = in && m >= 0 && m <= J.max_len && mt >= 0 && mt <= J.max_len;
-                lenw[k] = ok ? (uint32_t)mt : 0u;
-                lenr[k] = ok ? (uint32_t)m : 0u;
-                valid |= ok ? (1u << k) : 0u;
-                if (ok) {
-                    lmin = min(lmin, mt); lmax = max(lmax, mt);
-                    rmin = min(rmin, m); rmax = max(rmax, m);
-                }
-            } else {
-                const bool ok = in && m >= 0 && m <= J.max_len;
-                lenw[k] = ok ? (uint32_t)m : 0u;
-                valid |= ok ? (1u << k) : 0u;
-                if (ok) { lmin = min(lmin, m); lmax = max(lmax, m); }
-            }
+            mv[k] = lp ? lp[k * kPairLanes + pl] : J.max_len;
+            if constexpr (TWO) mtv[k] = tp[k * kPairLanes + pl];
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 32; k++) {
+            const int qi = min(k * kPairLanes + pl, left - 1);
+            mv[k] = lp ? lp[qi] : J.max_len;
+            if constexpr (TWO) mtv[k] = tp[qi];
         }
     }
-    // the first words do not depend on the lengths: load them before waiting
     const int nwords = (J.max_len + kHalf - 1) / kHalf;
     uint32_t raw0[32];
-    {
-        const int w = 0;
-        if (w < nwords) {
-            const uint32_t *row = seq + base;
-            load_word(row, full, n - base, pl, raw0);
-        } else {
+    if (nwords > 0) {
+        load_word(seq + base, full, left, pl, raw0);
+    } else {
 #pragma unroll
-            for (int k = 0; k < 32; k++) raw0[k] = 0u;
+        for (int k = 0; k < 32; k++) raw0[k] = 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < 32; k++) {
+        const int q = k * kPairLanes + pl;
+        const uint32_t inm = (full || q < left) ? ~0u : 0u;
+        const int m = (int)(((uint32_t)mv[k] & inm) | ~inm);   // -1 for a missing pair
+        if constexpr (TWO) {
+            const int mt = (int)(((uint32_t)mtv[k] & inm) | ~inm);
+            const bool ok = m >= 0 && m <= J.max_len && mt >= 0 && mt <= J.max_len;
+            lenw[k] = ok ? (uint32_t)mt : 0u;
+            lenr[k] = ok ? (uint32_t)m : 0u;
+            valid |= ok ? (1u << k) : 0u;
+            if (ok) {
+                lmin = min(lmin, mt); lmax = max(lmax, mt);
+                rmin = min(rmin, m); rmax = max(rmax, m);
+            }
+            asm volatile("" : "+v"(lenw[k]), "+v"(lenr[k]), "+v"(valid), "+v"(lmin), "+v"(lmax), "+v"(rmin),
+                         "+v"(rmax));
+        } else {
+            // all-ones iff 0 <= m <= max_len
+            const uint32_t okm = (uint32_t)m <= (uint32_t)J.max_len ? ~0u : 0u;
+            lenw[k] = (uint32_t)m & okm;
+            valid |= okm & (1u << k);
+            lmin = min(lmin, (int)(((uint32_t)m & okm) | (~okm & 0x7fffffffu)));
+            lmax = max(lmax, (int)(((uint32_t)m & okm) | ~okm));
+            asm volatile("" : "+v"(lenw[k]), "+v"(valid), "+v"(lmin), "+v"(lmax));
         }
     }
     // wave-uniform after the reductions: keep them in scalar registers so
@@ -578,7 +623,7 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     auto pass_load = [&](int pw, int tw, int limit, uint32_t (&raw)[32]) {
         const int w = min(max(half ? tw : pw, 0), limit - 1);
         const uint32_t *row = seq + (int64_t)w * J.ld + base;
-        load_word(row, full, n - base, pl, raw);
+        load_word(row, full, left, pl, raw);
     };
     auto pass_finish = [&](int pw, int limit, uint32_t (&raw)[32]) {
         transpose32(raw);
@@ -662,11 +707,14 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
             }
             block_winners<kBlock, TWO>(W, ring, nvh, nvph, pl, i0, sb, Ee, R, lo, hi_col, m_min, tl, th);
         }
-        // serial bit-vector update: block 2j on the low half, 2j+1 on the high
-        if (half == 0) block_update<kBlock, TWO>(F, W, X, lo);
+        // serial bit-vector update: block 2j on the low half, 2j+1 on the
+        // high; then both halves count their final bits at once
+        uint32_t o[kBlock];
+        if (half == 0) block_fsm<kBlock>(F, W, o);
         F.s0 = from_half0(F.s0); F.s1 = from_half0(F.s1); F.s2 = from_half0(F.s2);
-        if (half == 1) block_update<kBlock, TWO>(F, W, X, lo + kBlock);
+        if (half == 1) block_fsm<kBlock>(F, W, o);
         F.s0 = from_half1(F.s0); F.s1 = from_half1(F.s1); F.s2 = from_half1(F.s2);
+        block_count<kBlock, TWO>(F, o, X, lo + kBlock * half);
         // after all reads of iteration j: the pattern word iteration j+1
         // first needs, and text word j+2 (a pass whose two words both lie
         // past every pair's end is skipped: their planes are never unmasked)
@@ -677,12 +725,13 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
             start_text(Tc, raw);
         }
     };
-    // A last iteration with at most 8 windows left runs blocks of 4 windows:
-    // the low half's at lo, the high half's at lo+4 (if any window is left
-    // there).  Its text planes: the low half's positions 0..6 of word j are
-    // its own, the high half's positions 4..10 are the low half's.
-    auto short_iteration = [&](int j, const uint32_t (&Tc)[2 * kCols], bool activeB) {
-        constexpr int NB = 4, C = NB + 3;
+    // A last iteration with at most 8 windows left runs blocks of NB = 4
+    // windows (at most 4 left: NB = 2): the low half's at lo, the high half's
+    // at lo+NB (if any window is left there).  Its text planes: the low half's
+    // positions 0..NB+2 of word j are its own, the high half's positions
+    // NB..2NB+2 are the low half's.
+    auto short_iteration = [&](auto nb, int j, const uint32_t (&Tc)[2 * kCols], bool activeB) {
+        constexpr int NB = decltype(nb)::value, C = NB + 3;
         const int lo = kHalf * j;
         const int i0 = lo + NB * half;
         uint32_t tl[C], th[C];
@@ -699,9 +748,11 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
             fill_masks(i0, nvs, C + Ee);
         Winner<NB> W;
         block_winners<NB, TWO>(W, ring, nvs, nvps, pl, i0, i0 % R, Ee, R, lo, lo + NB + C - 1, m_min, tl, th);
-        if (half == 0) block_update<NB, TWO>(F, W, X, lo);
+        uint32_t o[NB];
+        if (half == 0) block_fsm<NB>(F, W, o);
         F.s0 = from_half0(F.s0); F.s1 = from_half0(F.s1); F.s2 = from_half0(F.s2);
-        if (half == 1 && activeB) block_update<NB, TWO>(F, W, X, lo + NB);
+        if (half == 1 && activeB) block_fsm<NB>(F, W, o);
+        if (half == 0 || activeB) block_count<NB, TWO>(F, o, X, lo + NB * half);
     };
     const int rem = m_max - kHalf * (niter - 1);        // windows of the last iteration
     const bool short_last = niter > 0 && rem <= kBlock;
@@ -716,10 +767,14 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
         uint32_t Tl[2 * kCols];
 #pragma unroll
         for (int t = 0; t < 2 * kCols; t++) Tl[t] = (nlong & 1) ? TB[t] : TA[t];
-        short_iteration(nlong, Tl, rem > 4);
+        if (rem > 4)
+            short_iteration(std::integral_constant<int, 4>(), nlong, Tl, true);
+        else
+            short_iteration(std::integral_constant<int, 2>(), nlong, Tl, rem > 2);
     }
     // windows whose final S bit went into the counter
-    const int nwin = short_last ? kHalf * nlong + (rem > 4 ? kBlock : kBlock / 2) : kHalf * niter;
+    const int nwin = !short_last ? kHalf * niter
+                                 : kHalf * nlong + (rem > 4 ? kBlock : (rem > 2 ? kBlock / 2 : kBlock / 4));
 
     // ---- add the two halves' ones counters (each half then holds the
     // total), then each half writes 16 of the 32 pairs of its lanes
@@ -784,11 +839,15 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
         cnt[k] = __builtin_amdgcn_permlane32_swap(cnt[k], cnt[16 + k], false, false)[0];
         if constexpr (TWO) pos[k] = __builtin_amdgcn_permlane32_swap(pos[k], pos[16 + k], false, false)[0];
     }
+    // the pair-count bound again, opaque to the compiler here, so that the
+    // stores' range checks are not computed (and kept live) before the loop
+    int left_out = __builtin_amdgcn_readfirstlane(left);
+    asm volatile("" : "+s"(left_out));
 #pragma unroll
     for (int k = 0; k < 16; k++) {
         const int kk = k + 16 * half;
         const int64_t p = base + (int64_t)kk * kPairLanes + pl;
-        if (!full && p >= n) continue;
+        if (!full && kk * kPairLanes + pl >= left_out) continue;
         const uint32_t w = cnt[k];
         const int m = uniform ? m_max : (int)((w >> 16) & ((1u << kLenBits) - 1));
         uint8_t acc;
