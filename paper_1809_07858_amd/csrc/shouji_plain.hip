@@ -348,7 +348,7 @@ __device__ __forceinline__ void block_fsm(FsmState &F, const Winner<NB> &W, uint
 // TWO, the positions of their zeros; the block starts at position `start`).
 // Independent per lane half, so both halves run it together.
 template <int NB, bool TWO>
-__device__ __forceinline__ void block_count(FsmState &F, const uint32_t (&o)[NB], Ends &X, int start) {
+__device__ __forceinline__ void block_count(FsmState &F, const uint32_t (&o)[NB], Ends &X, int start, int ebits) {
     uint32_t t1, t2, f1, f2, g;
 #define SHOUJI_CSA(h, l, a_, b_, c_)                       \
     {                                                      \
@@ -378,11 +378,15 @@ __device__ __forceinline__ void block_count(FsmState &F, const uint32_t (&o)[NB]
         F.fours ^= f1;
     }
 #undef SHOUJI_CSA
+    // the eights counter: one pulse per block at most, so (uniform) ebits
+    // bits hold every count of this half
 #pragma unroll
     for (int b = 0; b < 8; b++) {
-        const uint32_t cy = F.e[b] & g;
-        F.e[b] ^= g;
-        g = cy;
+        if (b < ebits) {
+            const uint32_t cy = F.e[b] & g;
+            F.e[b] ^= g;
+            g = cy;
+        }
     }
     if constexpr (TWO) track_ends<NB>(X, o, start);
 }
@@ -563,6 +567,7 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
 
     const int nblocks = (m_max + kBlock - 1) / kBlock;
     const int niter = (nblocks + 1) / 2;
+    const int ebits = 32 - __builtin_clz((unsigned)niter | 1u);   // bits of niter (each half: <= niter blocks)
     const int nhalves = (m_words + kHalf - 1) / kHalf;  // words holding positions < m_words
     const int H0 = (kBlock + kCols - 1 + Ee) / kHalf; // last pattern word iteration 0 reads
 
@@ -573,6 +578,9 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     // compare (length <= x); each next one adds the pairs whose length
     // equals it, one gate per length bit.
     auto fill_range = [&](int x0, int count, const uint32_t *planes, uint32_t *dst) {
+        // x0 opaque: its bit tests are not strength-reduced into values
+        // carried through the window loop
+        asm volatile("" : "+v"(x0));
         uint32_t lb[kLenBits];
 #pragma unroll
         for (int b = 0; b < kLenBits; b++) lb[b] = b < nlb ? planes[b * kPairLanes] : 0u;
@@ -714,7 +722,7 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
         F.s0 = from_half0(F.s0); F.s1 = from_half0(F.s1); F.s2 = from_half0(F.s2);
         if (half == 1) block_fsm<kBlock>(F, W, o);
         F.s0 = from_half1(F.s0); F.s1 = from_half1(F.s1); F.s2 = from_half1(F.s2);
-        block_count<kBlock, TWO>(F, o, X, lo + kBlock * half);
+        block_count<kBlock, TWO>(F, o, X, lo + kBlock * half, ebits);
         // after all reads of iteration j: the pattern word iteration j+1
         // first needs, and text word j+2 (a pass whose two words both lie
         // past every pair's end is skipped: their planes are never unmasked)
@@ -752,7 +760,7 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
         if (half == 0) block_fsm<NB>(F, W, o);
         F.s0 = from_half0(F.s0); F.s1 = from_half0(F.s1); F.s2 = from_half0(F.s2);
         if (half == 1 && activeB) block_fsm<NB>(F, W, o);
-        if (half == 0 || activeB) block_count<NB, TWO>(F, o, X, lo + NB * half);
+        if (half == 0 || activeB) block_count<NB, TWO>(F, o, X, lo + NB * half, ebits);
     };
     const int rem = m_max - kHalf * (niter - 1);        // windows of the last iteration
     const bool short_last = niter > 0 && rem <= kBlock;
