@@ -170,6 +170,16 @@ def main():
     wall = time.perf_counter() - t_start
     ms_per_step = ev0.elapsed_time(ev1) / args.steps
     value = n / (ms_per_step / 1e3)
+    # After the timed region: an event pair around each of 20 launches, the
+    # kernel's own duration with its ramp-up and drain (a kernel trace
+    # reports this; in the back-to-back stream they overlap the neighbours').
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
+    for a, b in evs:
+        a.record(stream)
+        sj.shouji_filter(reads, refs, lens, E, acc, pc, n_pairs=n, max_len=m, stream=stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    launch_ms = sum(a.elapsed_time(b) for a, b in evs) / len(evs)
 
     ops_pair = algorithmic_lane_ops_per_pair(m, E)
     achieved_tops = ops_pair * n / (ms_per_step / 1e3) / 1e12
@@ -196,6 +206,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": VALU_PEAK_TOPS,
                      "unit": "Tlane-op/s (32-bit integer VALU)",
                      "frac": achieved_tops / VALU_PEAK_TOPS,
+                     "ms_per_launch": ms_per_step,
+                     "ms_per_launch_isolated": launch_ms,
                      "traffic": traffic,
                      "algorithmic_lane_ops_per_pair": ops_pair,
                      "hbm_algorithmic_GBs": algorithmic_bytes_per_pair(m) * value / 1e9,
