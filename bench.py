@@ -59,11 +59,21 @@ def algorithmic_bytes_per_pair(m):
     return 2 * m / 4.0 + 4 + 1 + 2
 
 
+def strip_comments(src):
+    """C++ source without comments and blank space: what the compiler sees."""
+    import re
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
 def kernel_source_hash():
+    """Hash of the plain kernel's code (comments and layout excluded), which
+    ties a committed counter summary to the code it was taken on."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            h.update(strip_comments(f.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -4,20 +4,25 @@
 // Algorithm 1 (with Algorithm 2 as the zero counter).  Everything is exact
 // integer bit work; no MFMA, no floating point.
 //
-// Data layout in registers ("pair-sliced" bit planes).  A lane owns 32 pairs
-// (pairs base + 64k + lane, k = 0..31) and every 32-bit register holds one
-// bit of one quantity for those 32 pairs: bit k belongs to pair k.  A
-// wavefront therefore filters 2048 pairs, and one VALU instruction evaluates
-// one gate of the filter's circuit for 2048 pairs at once.  The window loop
-// (the only serial dependence of the method) becomes the instruction stream.
+// Data layout in registers ("pair-sliced" bit planes).  Every 32-bit
+// register holds one bit of one quantity for 32 pairs: bit k belongs to pair
+// base + 32k + (lane & 31).  Lanes l and l+32 hold the same 32 pairs, so a
+// wavefront filters 1024 pairs; its low lane half searches the even blocks of
+// 8 windows and its high half the odd ones, and one VALU instruction
+// evaluates one gate of the filter's circuit for two blocks of 32 x 32 pairs.
+// The window loop (the only serial dependence of the method) becomes the
+// instruction stream.
 //
-// Per lane:
+// Per wavefront:
 //  * sequences arrive as 2-bit packed words, 16 bases per dword, word-major,
-//    so a wavefront load reads one word of 64 consecutive pairs (256 B);
-//  * a 32x32 bit transpose turns the 32 dwords of one 16-base half-chunk into
-//    32 planes: plane 2u = low code bit of base u, plane 2u+1 = high bit;
-//  * pattern planes go to a per-lane ring in LDS (the diagonals need pattern
-//    positions up to E away from the text column); text planes stay in VGPRs;
+//    so a load of one word for 32 lanes reads 32 consecutive pairs (128 B);
+//  * a 32x32 bit transpose turns the 32 dwords of one 16-base word into 32
+//    planes: plane 2u = low code bit of base u, plane 2u+1 = high bit.  One
+//    transpose pass handles a pattern word on the low half and a text word
+//    on the high half;
+//  * pattern planes go to a ring in LDS shared by both halves (the diagonals
+//    need pattern positions up to E away from the text column); text planes
+//    stay in VGPRs and reach the low half by lane swaps;
 //  * windows are processed in blocks of 8.  For each candidate diagonal (in
 //    Algorithm 1's order d = +1, -1, ..., +E, -E, main) the 11 cells of
 //    the block's columns are built (XOR of code planes, OR of the two bits:
@@ -26,9 +31,12 @@
 //    ones first, then a leading zero -- keeping the earliest on full ties;
 //  * then the Shouji bit-vector update runs as a bit-sliced 8-state machine
 //    whose state is S[i..i+2] (S[i+3] is still 1 when window i runs): write iff
-//    ones(Z) <= ones(S[i..i+2]), which is "more zeros" for the 4-bit window;
-//    S[i] is final after window i and is added to a carry-save ones counter;
-//  * the counter planes are transposed back to one count per pair.
+//    ones(Z) <= ones(S[i..i+2]), which is "more zeros" for the 4-bit window.
+//    It is serial: the low half updates block 2j, hands the 3-plane state to
+//    the high half for block 2j+1, and gets it back.  S[i] is final after
+//    window i; both halves add their final bits to carry-save counters;
+//  * the two halves' counters are added and transposed back to one count per
+//    pair.
 //
 // Cells outside the m x m map (pattern or text index outside [0, m)) are
 // mismatches, in the interior blocks no such cell exists and no mask is
