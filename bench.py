@@ -249,7 +249,7 @@ def main():
         out["parity_mismatches"] = int(((ga != ea) | (gp != ep)).sum())
         out["parity_sample"] = ns
     if not args.no_batched:
-        out["batched"] = bench_batched(args.batched_n, dev)
+        out["batched"] = bench_batched(args.batched_n, dev, with_oracle=not args.no_cpu)
     if not args.no_verify:
         out["verify"] = bench_verify(reads, refs, lens, acc, pairs, E, ms_per_step, with_oracle=not args.no_cpu)
     if not args.no_window:
@@ -264,7 +264,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def bench_batched(n, dev, steps=20):
+def bench_batched(n, dev, steps=20, with_oracle=True):
     """Batched form on a mixed workload: n pairs, lengths uniform in 64..300,
     per-pair E_p = floor(r*m) with r uniform in [0, 0.10] (seed 3000), unsorted.
     One step = one shouji_filter_batched call (binning, scatter, filter), inputs
@@ -340,13 +340,22 @@ def bench_batched(n, dev, steps=20):
     torch.cuda.synchronize()
     plain_ms = e0.elapsed_time(e1) / reps
     same = int((acc[order_t] != g_acc).sum().item() + (pc[order_t] != g_pc).sum().item())
-    return {"workload": "%d pairs, lengths uniform 64..300, E_p=floor(r*m) r~U[0,0.10], "
-                        "unsorted, seed 3000" % n,
-            "value": n / (ms / 1e3), "unit": "pairs/s", "ms_per_step": ms,
-            "tuned_config": {"bin_width": bw, "waves_per_group": wpg}, "tune_ms": tune_ms,
-            "plain_per_group_value": n / (plain_ms / 1e3), "plain_groups": len(groups),
-            "plain_ms": plain_ms, "vs_plain": plain_ms / ms, "mismatches_vs_plain": same,
-            "accept_rate": float(acc.float().mean().item())}
+    out = {"workload": "%d pairs, lengths uniform 64..300, E_p=floor(r*m) r~U[0,0.10], "
+                       "unsorted, seed 3000" % n,
+           "value": n / (ms / 1e3), "unit": "pairs/s", "ms_per_step": ms,
+           "tuned_config": {"bin_width": bw, "waves_per_group": wpg}, "tune_ms": tune_ms,
+           "plain_per_group_value": n / (plain_ms / 1e3), "plain_groups": len(groups),
+           "plain_ms": plain_ms, "vs_plain": plain_ms / ms, "mismatches_vs_plain": same,
+           "accept_rate": float(acc.float().mean().item())}
+    if with_oracle:
+        # the full-size batch against the oracle on a strided sample
+        import oracle
+        idx = np.arange(0, n, 151)
+        ea, ep = oracle.shouji_batch(pairs.P[idx], pairs.T[idx], pairs.lengths[idx], E_per_pair=pairs.E[idx])
+        ga, gp = acc.cpu().numpy()[idx], pc.cpu().numpy()[idx]
+        out["mismatches_vs_oracle_sample"] = int(((ga != ea) | (gp != ep)).sum())
+        out["oracle_sample"] = "every 151st pair (%d)" % idx.size
+    return out
 
 
 def bench_verify(reads, refs, lens, acc, pairs, E, filter_ms, steps=20, with_oracle=True):
