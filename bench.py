@@ -28,9 +28,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "filtered pairs/sec at m=100,E=5 (1 GPU) vs plain; serving p50/p99 latency"
-# MI355X: 256 CUs x 64 lanes x 2.4 GHz peak engine clock, one 32-bit VALU op
-# per lane per cycle.
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# MI355X: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz peak engine clock: a wave64
+# VALU instruction every 2 cycles per SIMD (the 157.3 TFLOP/s FP32 vector
+# figure is this rate with an FMA counted as 2 FLOPs).
+VALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_1809_07858_amd/csrc/shouji_plain.hip",
                   "paper_1809_07858_amd/csrc/shouji_internal.h"]
