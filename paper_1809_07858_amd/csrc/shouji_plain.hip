@@ -146,14 +146,11 @@ struct Winner {
 // one length per pair, nv[s] masks position i0+s; with two (TWO), nv[s]
 // masks text position i0+s and nvp[s] pattern position i0-Ee+s.
 template <bool FIRST, int NB, bool TWO>
-__device__ __forceinline__ void candidate(Winner<NB> &W, const uint2 *__restrict__ rp,
+__device__ __forceinline__ void candidate(Winner<NB> &W, const uint2 (&pv)[NB + 3],
                                           const uint32_t *__restrict__ nv, const uint32_t *__restrict__ nvp,
                                           int Ee, int i0, int d, bool masked,
                                           const uint32_t (&tl)[NB + 3], const uint32_t (&th)[NB + 3]) {
     constexpr int C = NB + 3;
-    uint2 pv[C];
-#pragma unroll
-    for (int t = 0; t < C; t++) pv[t] = rp[t * kRingStride];
     uint32_t cell[C];
 #pragma unroll
     for (int t = 0; t < C; t++) {
@@ -228,13 +225,13 @@ __device__ __forceinline__ bool needs_mask(int d, int lo, int hi_col, int m_min)
     return (d > lo) || (hi_col >= m_min) || (hi_col - d >= m_min);
 }
 
-template <bool FIRST, int NB, bool TWO>
-__device__ __forceinline__ void candidate_any(bool masked, Winner<NB> &W, const uint2 *__restrict__ rp,
-                                              const uint32_t *__restrict__ nv,
-                                              const uint32_t *__restrict__ nvp, int Ee, int i0, int d,
-                                              const uint32_t (&tl)[NB + 3],
-                                              const uint32_t (&th)[NB + 3]) {
-    candidate<FIRST, NB, TWO>(W, rp, nv, nvp, Ee, i0, d, masked, tl, th);
+// The C ring entries (pattern planes of C consecutive positions) of one
+// candidate, starting at ring slot `slot`.
+template <int C>
+__device__ __forceinline__ void ring_load(const uint2 *__restrict__ rb, int slot, uint2 (&pv)[C]) {
+    const uint2 *rp = rb + slot * kRingStride;
+#pragma unroll
+    for (int t = 0; t < C; t++) pv[t] = rp[t * kRingStride];
 }
 
 // Window search of one block of NB windows at i0 (sb = ring slot of i0): the
@@ -249,29 +246,38 @@ __device__ __forceinline__ void block_winners(Winner<NB> &W, const uint2 *__rest
     // evaluation order (Algorithm 1): d = +1, -1, +2, -2, ..., +E, -E, then
     // the main diagonal (d > 0: text index exceeds pattern index by d, the
     // diagonal Algorithm 1 calls lower j, drawn as upper in Fig. 6); diagonal
-    // d reads the pattern from position i0 - d, i.e. ring slot sb - d (mod R)
+    // d reads the pattern from position i0 - d, i.e. ring slot sb - d (mod R).
+    // The ring entries of the next candidate are loaded while the current one
+    // is evaluated (two register buffers, A and B, used in turn).
+    constexpr int C = NB + 3;
     const uint2 *rb = ring + pl;
+    uint2 A[C], B[C];
+    auto mk = [&](int d) { return needs_mask(d, lo, hi_col, m_min); };
     if (Ee == 0) {
-        candidate_any<true, NB, TWO>(needs_mask(0, lo, hi_col, m_min), W, rb + sb * kRingStride, nv, nvp, Ee,
-                                     i0, 0, tl, th);
+        ring_load<C>(rb, sb, A);
+        candidate<true, NB, TWO>(W, A, nv, nvp, Ee, i0, 0, mk(0), tl, th);
         return;
     }
     int sP = sb == 0 ? R - 1 : sb - 1;   // slot of d = +k
     int sN = sb + 1 == R ? 0 : sb + 1;   // slot of d = -k
-    candidate_any<true, NB, TWO>(needs_mask(1, lo, hi_col, m_min), W, rb + sP * kRingStride, nv, nvp, Ee, i0,
-                                 1, tl, th);
-    candidate_any<false, NB, TWO>(needs_mask(-1, lo, hi_col, m_min), W, rb + sN * kRingStride, nv, nvp, Ee,
-                                  i0, -1, tl, th);
+    ring_load<C>(rb, sP, A);
+    ring_load<C>(rb, sN, B);
+    candidate<true, NB, TWO>(W, A, nv, nvp, Ee, i0, 1, mk(1), tl, th);
+    // A <- the next d > 0 (or the main diagonal when E = 1)
+    sP = sP == 0 ? R - 1 : sP - 1;
+    ring_load<C>(rb, Ee >= 2 ? sP : sb, A);
+    candidate<false, NB, TWO>(W, B, nv, nvp, Ee, i0, -1, mk(-1), tl, th);
     for (int k = 2; k <= Ee; k++) {
-        sP = sP == 0 ? R - 1 : sP - 1;
+        // A holds d = +k; B <- d = -k
         sN = sN + 1 == R ? 0 : sN + 1;
-        candidate_any<false, NB, TWO>(needs_mask(k, lo, hi_col, m_min), W, rb + sP * kRingStride, nv, nvp, Ee,
-                                      i0, k, tl, th);
-        candidate_any<false, NB, TWO>(needs_mask(-k, lo, hi_col, m_min), W, rb + sN * kRingStride, nv, nvp,
-                                      Ee, i0, -k, tl, th);
+        ring_load<C>(rb, sN, B);
+        candidate<false, NB, TWO>(W, A, nv, nvp, Ee, i0, k, mk(k), tl, th);
+        // A <- d = +(k+1), or the main diagonal after the last k
+        sP = sP == 0 ? R - 1 : sP - 1;
+        ring_load<C>(rb, k < Ee ? sP : sb, A);
+        candidate<false, NB, TWO>(W, B, nv, nvp, Ee, i0, -k, mk(-k), tl, th);
     }
-    candidate_any<false, NB, TWO>(needs_mask(0, lo, hi_col, m_min), W, rb + sb * kRingStride, nv, nvp, Ee, i0,
-                                  0, tl, th);
+    candidate<false, NB, TWO>(W, A, nv, nvp, Ee, i0, 0, mk(0), tl, th);
 }
 
 // Where the zeros of the final bit-vector lie, for the local and glocal
