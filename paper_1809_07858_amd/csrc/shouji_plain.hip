@@ -236,7 +236,7 @@ __device__ __forceinline__ void ring_load(const uint2 *__restrict__ rb, int slot
 
 // Window search of one block of NB windows at i0 (sb = ring slot of i0): the
 // winner of every window over all 2E+1 diagonals.
-template <int NB, bool TWO>
+template <int NB, bool TWO, bool MASKS = true>
 __device__ __forceinline__ void block_winners(Winner<NB> &W, const uint2 *__restrict__ ring,
                                               const uint32_t *__restrict__ nv,
                                               const uint32_t *__restrict__ nvp, int pl, int i0,
@@ -252,7 +252,8 @@ __device__ __forceinline__ void block_winners(Winner<NB> &W, const uint2 *__rest
     constexpr int C = NB + 3;
     const uint2 *rb = ring + pl;
     uint2 A[C], B[C];
-    auto mk = [&](int d) { return needs_mask(d, lo, hi_col, m_min); };
+    // MASKS = false: the caller knows that no cell of the block leaves the map
+    auto mk = [&](int d) { return MASKS && needs_mask(d, lo, hi_col, m_min); };
     if (Ee == 0) {
         ring_load<C>(rb, sb, A);
         candidate<true, NB, TWO>(W, A, nv, nvp, Ee, i0, 0, mk(0), tl, th);
@@ -726,8 +727,12 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
                     fill_masks2(i0, nvh, nvph, kCols);
                 else
                     fill_masks(i0, nvh, kCols + Ee);
+                block_winners<kBlock, TWO>(W, ring, nvh, nvph, pl, i0, sb, Ee, R, lo, hi_col, m_min, tl, th);
+            } else {
+                // interior: every pattern index i0+t-d lies in [0, m_min) and every
+                // text column below m_min, so no candidate needs a mask
+                block_winners<kBlock, TWO, false>(W, ring, nvh, nvph, pl, i0, sb, Ee, R, lo, hi_col, m_min, tl, th);
             }
-            block_winners<kBlock, TWO>(W, ring, nvh, nvph, pl, i0, sb, Ee, R, lo, hi_col, m_min, tl, th);
         }
         // serial bit-vector update: block 2j on the low half, 2j+1 on the
         // high; then both halves count their final bits at once
