@@ -239,8 +239,14 @@ __global__ __launch_bounds__(kScatterThreads) void bin_scatter_lds_kernel(Scatte
         prm.blens[dst] = prm.lengths ? prm.lengths[src] : prm.max_len;
         prm.bE[dst] = prm.Ep[src];
     }
-    // word rows, one at a time through the LDS buffer
+    // word rows, one at a time through the LDS buffer.  A bin's tiles read
+    // no word past the longest length of its bucket (bucket b / kBinE holds
+    // lengths up to (b / kBinE) * bw), so a pair's rows from there on are
+    // neither loaded nor written.
     const int nw = (prm.max_len + kHalf - 1) / kHalf;
+    int rows[PER];
+#pragma unroll
+    for (int i = 0; i < PER; i++) rows[i] = bin[i] >= 0 ? ((bin[i] / kBinE) * prm.bw + kHalf - 1) / kHalf : 0;
     for (int seq = 0; seq < 2; seq++) {
         const uint32_t *in = seq ? prm.refs : prm.reads;
         uint32_t *outp = seq ? prm.brefs : prm.breads;
@@ -248,11 +254,12 @@ __global__ __launch_bounds__(kScatterThreads) void bin_scatter_lds_kernel(Scatte
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < PER; i++)
-                if (slot[i] >= 0) buf[slot[i]] = in[(int64_t)w * prm.ld + c0 + tid + (int64_t)i * kScatterThreads];
+                if (w < rows[i]) buf[slot[i]] = in[(int64_t)w * prm.ld + c0 + tid + (int64_t)i * kScatterThreads];
             __syncthreads();
             for (int q = tid; q < nvalid; q += kScatterThreads) {
                 const int b = slotbin[q];
-                outp[(int64_t)w * prm.bld + gbase[b] + (q - loff[b])] = buf[q];
+                if (w * kHalf < (b / kBinE) * prm.bw)
+                    outp[(int64_t)w * prm.bld + gbase[b] + (q - loff[b])] = buf[q];
             }
         }
     }
