@@ -129,9 +129,10 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X "
-              "(pairs are independent; see the design notes for how batches would "
-              "shard across GPUs).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs on a single MI355X. "
+              "Pairs are independent; a batch would be split into contiguous pair "
+              "ranges, one per GPU, with an order-preserving gather of the results.",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
