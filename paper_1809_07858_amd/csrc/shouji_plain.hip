@@ -511,40 +511,64 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
 #pragma unroll
         for (int k = 0; k < 32; k++) raw0[k] = 0u;
     }
+    // Fast path (one length per pair, a full wavefront, every length in
+    // range -- the usual case): the lengths are the planes' source as they
+    // are, every pair is valid, and min / max come from the raw values.
+    bool fast = false;
+    if constexpr (!TWO) {
+        int a = 0x7fffffff, b = -1;
 #pragma unroll
-    for (int k = 0; k < 32; k++) {
-        const int q = k * kPairLanes + pl;
-        const uint32_t inm = (full || q < left) ? ~0u : 0u;
-        const int m = (int)(((uint32_t)mv[k] & inm) | ~inm);   // -1 for a missing pair
-        if constexpr (TWO) {
-            const int mt = (int)(((uint32_t)mtv[k] & inm) | ~inm);
-            const bool ok = m >= 0 && m <= J.max_len && mt >= 0 && mt <= J.max_len;
-            lenw[k] = ok ? (uint32_t)mt : 0u;
-            lenr[k] = ok ? (uint32_t)m : 0u;
-            valid |= ok ? (1u << k) : 0u;
-            if (ok) {
-                lmin = min(lmin, mt); lmax = max(lmax, mt);
-                rmin = min(rmin, m); rmax = max(rmax, m);
-            }
-            asm volatile("" : "+v"(lenw[k]), "+v"(lenr[k]), "+v"(valid), "+v"(lmin), "+v"(lmax), "+v"(rmin),
-                         "+v"(rmax));
-        } else {
-            // all-ones iff 0 <= m <= max_len
-            const uint32_t okm = (uint32_t)m <= (uint32_t)J.max_len ? ~0u : 0u;
-            lenw[k] = (uint32_t)m & okm;
-            valid |= okm & (1u << k);
-            lmin = min(lmin, (int)(((uint32_t)m & okm) | (~okm & 0x7fffffffu)));
-            lmax = max(lmax, (int)(((uint32_t)m & okm) | ~okm));
-            asm volatile("" : "+v"(lenw[k]), "+v"(valid), "+v"(lmin), "+v"(lmax));
+        for (int k = 0; k < 32; k++) {
+            a = min(a, mv[k]);
+            b = max(b, mv[k]);
+        }
+        a = __builtin_amdgcn_readfirstlane(wave_min(a));
+        b = __builtin_amdgcn_readfirstlane(wave_max(b));
+        if (full && a >= 0 && b <= J.max_len) {
+            fast = true;
+#pragma unroll
+            for (int k = 0; k < 32; k++) lenw[k] = (uint32_t)mv[k];
+            valid = ~0u;
+            lmin = a;
+            lmax = b;
         }
     }
-    // wave-uniform after the reductions: keep them in scalar registers so
-    // that every decision taken from them is a scalar branch
-    lmin = __builtin_amdgcn_readfirstlane(wave_min(lmin));
-    lmax = __builtin_amdgcn_readfirstlane(wave_max(lmax));
-    if constexpr (TWO) {
-        rmin = __builtin_amdgcn_readfirstlane(wave_min(rmin));
-        rmax = __builtin_amdgcn_readfirstlane(wave_max(rmax));
+    if (!fast) {
+#pragma unroll
+        for (int k = 0; k < 32; k++) {
+            const int q = k * kPairLanes + pl;
+            const uint32_t inm = (full || q < left) ? ~0u : 0u;
+            const int m = (int)(((uint32_t)mv[k] & inm) | ~inm);   // -1 for a missing pair
+            if constexpr (TWO) {
+                const int mt = (int)(((uint32_t)mtv[k] & inm) | ~inm);
+                const bool ok = m >= 0 && m <= J.max_len && mt >= 0 && mt <= J.max_len;
+                lenw[k] = ok ? (uint32_t)mt : 0u;
+                lenr[k] = ok ? (uint32_t)m : 0u;
+                valid |= ok ? (1u << k) : 0u;
+                if (ok) {
+                    lmin = min(lmin, mt); lmax = max(lmax, mt);
+                    rmin = min(rmin, m); rmax = max(rmax, m);
+                }
+                asm volatile("" : "+v"(lenw[k]), "+v"(lenr[k]), "+v"(valid), "+v"(lmin), "+v"(lmax), "+v"(rmin),
+                             "+v"(rmax));
+            } else {
+                // all-ones iff 0 <= m <= max_len
+                const uint32_t okm = (uint32_t)m <= (uint32_t)J.max_len ? ~0u : 0u;
+                lenw[k] = (uint32_t)m & okm;
+                valid |= okm & (1u << k);
+                lmin = min(lmin, (int)(((uint32_t)m & okm) | (~okm & 0x7fffffffu)));
+                lmax = max(lmax, (int)(((uint32_t)m & okm) | ~okm));
+                asm volatile("" : "+v"(lenw[k]), "+v"(valid), "+v"(lmin), "+v"(lmax));
+            }
+        }
+        // wave-uniform after the reductions: keep them in scalar registers so
+        // that every decision taken from them is a scalar branch
+        lmin = __builtin_amdgcn_readfirstlane(wave_min(lmin));
+        lmax = __builtin_amdgcn_readfirstlane(wave_max(lmax));
+        if constexpr (TWO) {
+            rmin = __builtin_amdgcn_readfirstlane(wave_min(rmin));
+            rmax = __builtin_amdgcn_readfirstlane(wave_max(rmax));
+        }
     }
     // m_max: windows (the reference's positions); m_min: shortest of both
     // sequences (below it no cell needs a mask); m_words: positions to load
