@@ -117,16 +117,23 @@ __device__ __forceinline__ void transpose32(uint32_t (&a)[32]) {
 #undef SHOUJI_TSTAGE
 }
 
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
-    return v;
+// Wave-wide maximum / minimum (all 64 lanes active), returned uniform: DPP
+// lane swaps within each row of 16 lanes (quad permutes, then the half-row
+// and row mirrors), then the four rows' values read into scalar registers.
+// No LDS traffic and no LDS latency.
+template <bool MAX>
+__device__ __forceinline__ int wave_reduce(int v) {
+    auto op = [](int a, int b) { return MAX ? max(a, b) : min(a, b); };
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));  // row_mirror
+    const int r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+    const int r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+    return op(op(r0, r1), op(r2, r3));
 }
-__device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
-    return v;
-}
+__device__ __forceinline__ int wave_max(int v) { return wave_reduce<true>(v); }
+__device__ __forceinline__ int wave_min(int v) { return wave_reduce<false>(v); }
 
 // Running winner of the window search for the NB windows of a block (8, or
 // 4 in a short last iteration), one register per plane and window: key
@@ -829,7 +836,11 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
 
     // ---- add the two halves' ones counters (each half then holds the
     // total), then each half writes 16 of the 32 pairs of its lanes
-    auto other_half = [](uint32_t v) { return (uint32_t)__shfl_xor((int)v, 32, kWave); };
+    // the same register of the other lane half (one lane swap, no LDS)
+    auto other_half = [half](uint32_t v) {
+        const auto sw = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return half ? (uint32_t)sw[0] : (uint32_t)sw[1];
+    };
     uint32_t cnt[32];
     cnt[0] = F.ones; cnt[1] = F.twos; cnt[2] = F.fours;
 #pragma unroll
