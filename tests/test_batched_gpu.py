@@ -121,3 +121,27 @@ def test_graph_capture_replays(sj):
         torch.cuda.synchronize()
         assert torch.equal(acc, ref_a) and torch.equal(pc, ref_p), "replay %d" % it
         del junk
+
+
+def test_full_size_sampled(sj):
+    # the full mixed workload: 8M pairs, lengths 64..300, E_p = floor(r m),
+    # unsorted, in one call with the tuned configuration; every 151st pair
+    # against the oracle, and on every pair: accept = popcount <= E_p,
+    # popcount in [0, m]
+    p = syninput.config3()
+    max_len = 300
+    print("batched full n=%d" % p.n, flush=True)
+    d = torch.device("cuda:0")
+    r = sj.pack_words_device(p.P, max_len)
+    t = sj.pack_words_device(p.T, max_len)
+    L = torch.from_numpy(p.lengths).to(d)
+    E = torch.from_numpy(p.E).to(d)
+    acc, pc = sj.shouji_filter_batched(r, t, L, E, max_len=max_len)
+    torch.cuda.synchronize()
+    ga, gp = acc.cpu().numpy(), pc.cpu().numpy().astype(np.int32)
+    assert ((gp >= 0) & (gp <= p.lengths)).all()
+    assert np.array_equal(ga, (gp <= p.E).astype(np.uint8))
+    idx = np.arange(0, p.n, 151)
+    ea, ep = oracle.shouji_batch(p.P[idx], p.T[idx], p.lengths[idx], E_per_pair=p.E[idx])
+    bad = np.nonzero((ga[idx] != ea) | (gp[idx] != ep))[0]
+    assert bad.size == 0, "mismatches at %s" % idx[bad[:8]]
