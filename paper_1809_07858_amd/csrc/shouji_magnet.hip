@@ -20,8 +20,9 @@
 // right part pushed last, so that its whole subtree is solved before the
 // left part).  A diagonal's run search walks 16 text positions per step: the
 // reference word, the read's two words around the diagonal's offset joined
-// with v_alignbit, one XOR and a fold give the 16 mismatch bits, and only
-// the mismatches inside the part are visited (each closes a run of zeros).
+// with v_alignbit, one XOR and a fold give the 16 match bits, and the
+// longest run of matches in the word is found with doubling masks and a
+// binary descent on its length (no loop over the mismatches).
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -61,13 +62,20 @@ __global__ __launch_bounds__(kMagnetBlock) void magnet_kernel(MagnetParams prm) 
     const int thr = m > E ? (m - E + (E + 1) - 1) / (E + 1) : 0;   // ceil((m-E)/(E+1))
 
     // longest run of zeros of diagonal d inside text positions [lo, hi]
+    // (leftmost of equal ones), one 16-position word at a time.  x marks the
+    // word's matches inside the range (2-bit fields, even bits); a run that
+    // reaches the word's end is carried into the next word.  In a word: the
+    // carried run ends at the first mismatch; the runs strictly between the
+    // first and the last mismatch are searched with doubling masks (r_k: a
+    // run of at least k starts here) and a binary descent on the length; the
+    // matches after the last mismatch are carried on.
     auto longest = [&](int d, int lo, int hi, int &start) -> int {
         const int a = lo > d ? lo : d;                       // pattern index j-d >= 0
         const int b = hi < m - 1 + d ? hi : m - 1 + d;       // pattern index j-d < m
         int best = 0;
         start = 0;
         if (a > b) return 0;
-        int rs = a;                                          // start of the current run
+        int carry = 0, cs = (a >> 4) * 16;                  // run reaching the word's start
         for (int w = a >> 4; w <= (b >> 4); w++) {
             const uint32_t tw = T[(int64_t)w * ld];
             const int q0 = 16 * w - d;                       // read position of the word's field 0
@@ -76,23 +84,45 @@ __global__ __launch_bounds__(kMagnetBlock) void magnet_kernel(MagnetParams prm) 
             const uint32_t lo_w = (qw >= 0 && qw < nw) ? P[(int64_t)qw * ld] : 0u;
             const uint32_t hi_w = (qw + 1 >= 0 && qw + 1 < nw) ? P[(int64_t)(qw + 1) * ld] : 0u;
             const uint32_t pv = __builtin_amdgcn_alignbit(hi_w, lo_w, ob);
-            const uint32_t x = tw ^ pv;
+            const uint32_t xr = tw ^ pv;
             const int klo = a - 16 * w > 0 ? a - 16 * w : 0;
             const int khi = b - 16 * w < 15 ? b - 16 * w : 15;
-            uint32_t z = ((x | (x >> 1)) & field_mask(khi + 1)) & ~field_mask(klo);
-            while (z) {
-                const int q = 16 * w + (__builtin_ctz(z) >> 1);   // a mismatch closes the run
-                if (q - rs > best) {
-                    best = q - rs;
-                    start = rs;
-                }
-                rs = q + 1;
-                z &= z - 1u;
+            const uint32_t x = ~(xr | (xr >> 1)) & field_mask(khi + 1) & ~field_mask(klo);   // matches
+            if (x == 0x55555555u) {                          // 16 matches: the run goes on
+                carry += 16;
+                continue;
             }
+            const uint32_t mis = ~x & 0x55555555u;           // mismatches (and positions out of range)
+            const int lead = __builtin_ctz(mis) >> 1;
+            if (carry + lead > best) {
+                best = carry + lead;
+                start = cs;
+            }
+            const int trail = 15 - ((31 - __builtin_clz(mis)) >> 1);
+            const uint32_t xi = x & ~field_mask(lead) & field_mask(16 - trail);
+            if (xi) {
+                const uint32_t r2 = xi & (xi >> 2), r4 = r2 & (r2 >> 4), r8 = r4 & (r4 >> 8);
+                int L = 1;
+                uint32_t cur = xi;
+                uint32_t cand = cur & (r8 >> (2 * L));
+                if (cand) { cur = cand; L += 8; }
+                cand = cur & (r4 >> (2 * L));
+                if (cand) { cur = cand; L += 4; }
+                cand = L < 15 ? cur & (r2 >> (2 * L)) : 0u;
+                if (cand) { cur = cand; L += 2; }
+                cand = L < 16 ? cur & (xi >> (2 * L)) : 0u;
+                if (cand) { cur = cand; L += 1; }
+                if (L > best) {
+                    best = L;
+                    start = 16 * w + (__builtin_ctz(cur) >> 1);
+                }
+            }
+            carry = trail;
+            cs = 16 * w + 16 - trail;
         }
-        if (b + 1 - rs > best) {
-            best = b + 1 - rs;
-            start = rs;
+        if (carry > best) {
+            best = carry;
+            start = cs;
         }
         return best;
     };
