@@ -157,3 +157,33 @@ def test_config2_full_size_sampled(sj, E):
     ea, ep = oracle.shouji_batch(p.P[idx], p.T[idx], p.lengths[idx], E=E)
     bad = np.nonzero((ga[idx] != ea) | (gp[idx] != ep))[0]
     assert bad.size == 0, "mismatches at %s" % idx[bad[:8]]
+
+
+def test_empty_sequences(sj):
+    # every pair of length 0 (max_len 0 and max_len 100), and max_len 0 with
+    # no lengths: nothing to filter, popcount 0, accepted at every E
+    d = torch.device("cuda:0")
+    n = 3000
+    for max_len in (0, 100):
+        words = max(1, (max_len + 15) // 16)
+        r = torch.zeros((words, n), dtype=torch.int32, device=d)
+        L = torch.zeros(n, dtype=torch.int32, device=d)
+        for E in (0, 3):
+            print("case empty max_len=%d E=%d" % (max_len, E), flush=True)
+            acc, pc = sj.shouji_filter(r, r, L, E, max_len=max_len)
+            torch.cuda.synchronize()
+            assert (acc.cpu().numpy() == 1).all() and (pc.cpu().numpy() == 0).all()
+    r = torch.zeros((1, n), dtype=torch.int32, device=d)
+    acc, pc = sj.shouji_filter(r, r, None, 2, max_len=0)
+    torch.cuda.synchronize()
+    assert (acc.cpu().numpy() == 1).all() and (pc.cpu().numpy() == 0).all()
+
+
+def test_lengths_around_word_and_block_edges(sj):
+    # lengths that end at and next to a 16-base word, an 8-window block and a
+    # 16-window iteration (tail iterations of 1..8 windows, blocks of 2 and 4)
+    for m in (1, 2, 3, 4, 5, 8, 9, 15, 16, 17, 18, 20, 24, 31, 32, 33, 34, 36, 40, 47, 48, 49, 97, 98, 99, 100,
+              101, 104, 112, 113):
+        p = syninput.generate(2_100, m, E=min(3, max(m - 1, 0)), seed=900 + m)
+        for E in (0, 1, 5):
+            _check(sj, p, E, m)
