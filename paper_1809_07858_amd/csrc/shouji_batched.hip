@@ -247,21 +247,34 @@ __global__ __launch_bounds__(kScatterThreads) void bin_scatter_lds_kernel(Scatte
     int rows[PER];
 #pragma unroll
     for (int i = 0; i < PER; i++) rows[i] = bin[i] >= 0 ? ((bin[i] / kBinE) * prm.bw + kHalf - 1) / kHalf : 0;
-    for (int seq = 0; seq < 2; seq++) {
-        const uint32_t *in = seq ? prm.refs : prm.reads;
-        uint32_t *outp = seq ? prm.brefs : prm.breads;
-        for (int w = 0; w < nw; w++) {
-            __syncthreads();
+    // rows of both sequences in turn; the loads of the next row are issued
+    // before the current one goes through LDS, so their latency overlaps it
+    const int nrows = 2 * nw;
+    uint32_t cur[PER], nxt[PER];
+    auto load_row = [&](int r, uint32_t (&v)[PER]) {
+        const int w = r < nw ? r : r - nw;
+        const uint32_t *in = r < nw ? prm.reads : prm.refs;
 #pragma unroll
-            for (int i = 0; i < PER; i++)
-                if (w < rows[i]) buf[slot[i]] = in[(int64_t)w * prm.ld + c0 + tid + (int64_t)i * kScatterThreads];
-            __syncthreads();
-            for (int q = tid; q < nvalid; q += kScatterThreads) {
-                const int b = slotbin[q];
-                if (w * kHalf < (b / kBinE) * prm.bw)
-                    outp[(int64_t)w * prm.bld + gbase[b] + (q - loff[b])] = buf[q];
-            }
+        for (int i = 0; i < PER; i++)
+            v[i] = w < rows[i] ? in[(int64_t)w * prm.ld + c0 + tid + (int64_t)i * kScatterThreads] : 0u;
+    };
+    if (nrows > 0) load_row(0, cur);
+    for (int r = 0; r < nrows; r++) {
+        const int w = r < nw ? r : r - nw;
+        uint32_t *outp = r < nw ? prm.breads : prm.brefs;
+        if (r + 1 < nrows) load_row(r + 1, nxt);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < PER; i++)
+            if (w < rows[i]) buf[slot[i]] = cur[i];
+        __syncthreads();
+        for (int q = tid; q < nvalid; q += kScatterThreads) {
+            const int b = slotbin[q];
+            if (w * kHalf < (b / kBinE) * prm.bw)
+                outp[(int64_t)w * prm.bld + gbase[b] + (q - loff[b])] = buf[q];
         }
+#pragma unroll
+        for (int i = 0; i < PER; i++) cur[i] = nxt[i];
     }
 }
 
