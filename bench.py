@@ -571,10 +571,12 @@ def bench_serving(dev, total_pairs, batch_pairs, slots, distinct=1_000_000, load
     segments); a request's pairs are a contiguous run of `distinct` generated
     pairs.  First the whole stream is submitted at once (peak pairs/s), then it
     is replayed with Poisson arrivals at `load` x that peak; latency = submit to
-    results in the caller's host buffers.  This runs twice: with request buffers
-    in pinned host memory (moved by DMA in place) and in pageable memory (staged
-    by the server).  Every served result is compared with the batched form run
-    on the same pairs resident on the device."""
+    results in the caller's host buffers.  This runs three times: with the reads
+    packed back to back (ceil(m/16) words each) in pinned host memory, and with
+    reads in rows of ceil(300/16) = 19 words in pinned memory (both moved by DMA
+    in place) and in pageable memory (staged by the server).  Every served
+    result is compared with the batched form run on the same pairs resident on
+    the device."""
     import threading
     import numpy as np
     import torch
@@ -600,6 +602,7 @@ def bench_serving(dev, total_pairs, batch_pairs, slots, distinct=1_000_000, load
     offsets = off + 16 * r0
     reads = sj.pack_pairs(pairs.P, max_len)
     lens, Ep = pairs.lengths, pairs.E
+    pwords, pwo = sj.pack_reads_packed(pairs.P, lens, max_len)
 
     # the batched form on the same pairs, device-resident: expected results, and
     # the autotuned config for full batches
@@ -640,21 +643,28 @@ def bench_serving(dev, total_pairs, batch_pairs, slots, distinct=1_000_000, load
         v[...] = a
         return t, v
     pin_src = [pinned(a) for a in (reads, offsets, lens, Ep)]
+    pin_packed = pinned(pwords)
     out_base = np.cumsum([0] + sizes)
     pin_out = [pinned(np.zeros(total_pairs, np.uint8)), pinned(np.zeros(total_pairs, np.int16))]
 
-    def run(mode):
+    def run(mode, nreq=None):
+        N = len(sizes) if nreq is None else nreq     # the first N requests of the stream
+        tot = int(sum(sizes[:N]))
         srv = sj.Server(pool, pool_words * 16, max_len, slots=slots, max_batch_pairs=batch_pairs,
                         memory_budget=16 << 30)
         state = {"bad": 0}
         try:
             def submit(i):
                 a, s_ = starts[i], sizes[i]
-                if mode == "pinned":
+                if mode in ("packed", "pinned"):
                     r, o, L, E = [v for _, v in pin_src]
+                    if mode == "packed":
+                        r = pin_packed[1][pwo[a]:pwo[a + s_]]
+                    else:
+                        r = r[a:a + s_]
                     b0 = out_base[i]
-                    return srv.submit(r[a:a + s_], o[a:a + s_], L[a:a + s_], E[a:a + s_], pinned=True,
-                                      out_accept=pin_out[0][1][b0:b0 + s_],
+                    return srv.submit(r, o[a:a + s_], L[a:a + s_], E[a:a + s_], pinned=True,
+                                      packed=mode == "packed", out_accept=pin_out[0][1][b0:b0 + s_],
                                       out_popcount=pin_out[1][1][b0:b0 + s_])
                 return srv.submit(reads[a:a + s_], offsets[a:a + s_], lens[a:a + s_], Ep[a:a + s_])
 
@@ -667,25 +677,25 @@ def bench_serving(dev, total_pairs, batch_pairs, slots, distinct=1_000_000, load
             # peak: the whole stream at once
             st0 = srv.stats()
             tb = time.perf_counter()
-            tickets = [submit(i) for i in range(len(sizes))]
+            tickets = [submit(i) for i in range(N)]
             for i, t in enumerate(tickets):
                 acc, pc, _ = srv.wait(t)
                 check(i, acc, pc)
             peak_s = time.perf_counter() - tb
-            peak = total_pairs / peak_s
+            peak = tot / peak_s
             st1 = srv.stats()
 
             # Poisson arrivals at load x peak
-            mean_size = total_pairs / len(sizes)
+            mean_size = tot / N
             rate = load * peak / mean_size             # requests per second
-            arrivals = np.cumsum(rng.exponential(1.0 / rate, len(sizes)))
-            lat = [None] * len(sizes)
-            sub_t = [None] * len(sizes)
+            arrivals = np.cumsum(rng.exponential(1.0 / rate, N))
+            lat = [None] * N
+            sub_t = [None] * N
             tq = []
             ready = threading.Condition()
 
             def waiter():
-                for i in range(len(sizes)):
+                for i in range(N):
                     with ready:
                         while len(tq) <= i:
                             ready.wait()
@@ -697,7 +707,7 @@ def bench_serving(dev, total_pairs, batch_pairs, slots, distinct=1_000_000, load
             wt = threading.Thread(target=waiter)
             wt.start()
             tp = time.perf_counter()
-            for i in range(len(sizes)):
+            for i in range(N):
                 d = tp + arrivals[i] - time.perf_counter()
                 if d > 0:
                     time.sleep(d)
@@ -707,13 +717,13 @@ def bench_serving(dev, total_pairs, batch_pairs, slots, distinct=1_000_000, load
                     tq.append(t)
                     ready.notify()
             wt.join()
-            end = max(sub_t[i] + lat[i] / 1e3 for i in range(len(sizes)))
+            end = max(sub_t[i] + lat[i] / 1e3 for i in range(N))
             poisson_s = end - sub_t[0]
             st2 = srv.stats()
         finally:
             srv.close()
         lat = np.array(lat)
-        return {"value": total_pairs / poisson_s, "unit": "pairs/s",
+        return {"value": tot / poisson_s, "unit": "pairs/s",
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
                 "offered_pairs_per_s": load * peak, "load": load,
@@ -723,12 +733,23 @@ def bench_serving(dev, total_pairs, batch_pairs, slots, distinct=1_000_000, load
                 "deferred_poisson": st2["requests_deferred"] - st1["requests_deferred"],
                 "mismatches_vs_batched": state["bad"]}
 
-    res = run("pinned")
+    # host-link bytes per pair: the reads, the segment offset, length and E
+    nw = sj.nwords(max_len)
+    # a short untimed pass first, so that first-use costs of the process stay
+    # out of the timed runs
+    run("pinned", nreq=min(40, len(sizes)))
+    rows_pinned = run("pinned")
+    res = run("packed")
+    res["host_bytes_per_pair"] = 4 * pwords.size / distinct + 16
+    res["rows_pinned"] = rows_pinned
+    res["rows_pinned"]["host_bytes_per_pair"] = 4 * nw + 16
     res["pageable"] = run("pageable")
+    res["pageable"]["host_bytes_per_pair"] = 4 * nw + 16
     res.update({"workload": "Poisson stream of %d requests, %d pairs in all, request size "
                             "U{1..200000}, lengths uniform 64..300, E_p=floor(r*m) r~U[0,0.10], "
                             "2 GiB device-resident packed reference pool (8 Gi bases), seed %d; "
-                            "request buffers pinned (the pageable run is nested)"
+                            "request buffers pinned, reads packed back to back (the runs with "
+                            "reads in rows of 19 words, pinned and pageable, are nested)"
                             % (len(sizes), total_pairs, seed),
                 "requests": len(sizes), "pairs": total_pairs, "distinct_pairs": distinct,
                 "batch_pairs": batch_pairs, "batched_vs_oracle_sample_mismatches": oracle_bad,

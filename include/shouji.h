@@ -283,8 +283,11 @@ typedef struct {
 typedef struct {
     const uint32_t *reads;      /* host, pair-major: read p in words
                                    [p*words_per_read, (p+1)*words_per_read), packed
-                                   as the pool (base j in word j/16)                 */
-    int32_t words_per_read;     /* > 0; words beyond ceil(max_len/16) are ignored     */
+                                   as the pool (base j in word j/16); with
+                                   SHOUJI_REQUEST_PACKED the reads back to back
+                                   instead (see there)                               */
+    int32_t words_per_read;     /* > 0; words beyond ceil(max_len/16) are ignored
+                                   (ignored for a packed request)                     */
     const int64_t *ref_offsets; /* host: pool base where pair p's reference begins     */
     const int32_t *lengths;     /* host: length m_p of read and reference              */
     const int32_t *E;           /* host: edit threshold of pair p                      */
@@ -296,9 +299,18 @@ typedef struct {
 } shouji_request;
 
 /* The request's buffers are pinned host memory (hipHostMalloc): when its read
- * rows are ceil(max_len/16) words wide they move by DMA straight to and from
- * the device, without a copy through the server's staging buffers. */
+ * rows are ceil(max_len/16) words wide, or the reads are packed, they move by
+ * DMA straight to and from the device, without a copy through the server's
+ * staging buffers. */
 #define SHOUJI_REQUEST_PINNED 1u
+
+/* The reads are stored back to back with no padding: read p takes
+ * ceil(m_p/16) words, none when m_p lies outside [1, max_len], and begins
+ * where read p-1 ends, so `reads` holds the sum of these counts.  The server
+ * moves only these words to the device (a read of m bases costs ceil(m/16)
+ * words on the host link instead of ceil(max_len/16)).  The server trusts the
+ * count: a shorter buffer is read past its end. */
+#define SHOUJI_REQUEST_PACKED 2u
 
 typedef struct {
     int32_t slots;          /* batch slots the memory budget allowed */

@@ -42,6 +42,7 @@ class Request(ctypes.Structure):
 
 
 REQUEST_PINNED = 1
+REQUEST_PACKED = 2
 
 
 class ServerStats(ctypes.Structure):
@@ -420,6 +421,35 @@ def pack_pairs(codes, max_len=None):
     return np.ascontiguousarray(pack_words(codes, max_len).view(np.uint32).T)
 
 
+def packed_read_words(lengths, max_len):
+    """Words each read takes in the packed request layout: ceil(m/16), none for a
+    length outside [1, max_len] (int64 [n])."""
+    lens = np.asarray(lengths, dtype=np.int64)
+    return np.where((lens >= 1) & (lens <= int(max_len)), (lens + BASES_PER_WORD - 1) // BASES_PER_WORD, 0)
+
+
+def _packed_words_total(lens, max_len):
+    """Sum of packed_read_words over an int32 length array (fast when every length is
+    in range, the usual case)."""
+    if lens.size == 0:
+        return 0
+    if int(lens.min()) >= 1 and int(lens.max()) <= int(max_len):
+        return int(np.add.reduce((lens + (BASES_PER_WORD - 1)) // BASES_PER_WORD, dtype=np.int64))
+    return int(packed_read_words(lens, max_len).sum())
+
+
+def pack_reads_packed(codes, lengths, max_len):
+    """Base codes [n, stride] (uint8 0..3) and lengths -> (words, offsets): the reads
+    back to back, read p in words[offsets[p]:offsets[p+1]] (ceil(m_p/16) words), the
+    packed read layout of a server request (SHOUJI_REQUEST_PACKED).  A request made of
+    pairs lo..hi-1 passes words[offsets[lo]:offsets[hi]]."""
+    rows = pack_pairs(codes, max_len)
+    k = packed_read_words(lengths, max_len)
+    offsets = np.concatenate([[0], np.cumsum(k)]).astype(np.int64)
+    mask = np.arange(rows.shape[1])[None, :] < k[:, None]
+    return np.ascontiguousarray(rows[mask]), offsets
+
+
 def pack_pool(codes):
     """Flat base codes (uint8 0..3) -> packed pool words (uint32): base b in bits
     2(b%16).. of word b/16, the reference-pool layout of the server."""
@@ -474,17 +504,27 @@ class Server:
         self._h = h
 
     def submit(self, reads, ref_offsets, lengths, E, want_popcount=True, pinned=False,
-               out_accept=None, out_popcount=None):
-        """Queue a request.  reads: uint32 [n, words_per_read] (pack_pairs); ref_offsets int64,
-        lengths int32, E int32 (scalar or per pair).  pinned=True declares that every buffer,
-        outputs included, is pinned host memory (e.g. numpy views of torch pin_memory tensors),
-        so the server moves it by DMA without staging.  Returns a Ticket."""
+               out_accept=None, out_popcount=None, packed=False):
+        """Queue a request.  reads: uint32 [n, words_per_read] (pack_pairs), or with
+        packed=True the reads back to back as one uint32 array (pack_reads_packed);
+        ref_offsets int64, lengths int32, E int32 (scalar or per pair).  pinned=True declares
+        that every buffer, outputs included, is pinned host memory (e.g. numpy views of torch
+        pin_memory tensors), so the server moves it by DMA without staging.  Returns a
+        Ticket."""
         reads = np.ascontiguousarray(reads, dtype=np.uint32)
-        if reads.ndim != 2:
-            raise ValueError("reads must be [n_pairs, words_per_read]")
-        n = reads.shape[0]
-        offs = np.ascontiguousarray(ref_offsets, dtype=np.int64)
         lens = np.ascontiguousarray(lengths, dtype=np.int32)
+        if packed:
+            if reads.ndim != 1:
+                raise ValueError("packed reads are one flat uint32 array")
+            n = lens.shape[0]
+            need = _packed_words_total(lens, self.max_len)
+            if reads.size != need:
+                raise ValueError("packed reads hold %d words, the lengths need %d" % (reads.size, need))
+        else:
+            if reads.ndim != 2:
+                raise ValueError("reads must be [n_pairs, words_per_read]")
+            n = reads.shape[0]
+        offs = np.ascontiguousarray(ref_offsets, dtype=np.int64)
         Ep = np.ascontiguousarray(np.broadcast_to(np.asarray(E, dtype=np.int32), (n,)))
         if offs.shape != (n,) or lens.shape != (n,):
             raise ValueError("ref_offsets and lengths need one entry per pair")
@@ -501,9 +541,10 @@ class Server:
         if acc.shape != (n,) or acc.dtype != np.uint8 or (pc is not None and (
                 pc.shape != (n,) or pc.dtype != np.int16)):
             raise ValueError("outputs must be uint8 / int16 arrays with one entry per pair")
-        req = Request(reads.ctypes.data, max(1, reads.shape[1]), offs.ctypes.data, lens.ctypes.data,
-                      Ep.ctypes.data, acc.ctypes.data, None if pc is None else pc.ctypes.data, n,
-                      REQUEST_PINNED if pinned else 0)
+        req = Request(reads.ctypes.data, 1 if packed else max(1, reads.shape[1]), offs.ctypes.data,
+                      lens.ctypes.data, Ep.ctypes.data, acc.ctypes.data,
+                      None if pc is None else pc.ctypes.data, n,
+                      (REQUEST_PINNED if pinned else 0) | (REQUEST_PACKED if packed else 0))
         t = ctypes.c_uint64()
         _check(lib().shouji_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
         return Ticket(t.value, (reads, offs, lens, Ep), acc, pc)

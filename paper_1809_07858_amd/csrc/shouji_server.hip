@@ -37,42 +37,51 @@
 
 namespace shouji {
 
-// pair-major packed reads in[n][wpr] -> word-major out[nw][ld]; words at or
-// beyond wpr are written as 0.
-__global__ void reads_to_word_major_kernel(const uint32_t *__restrict__ in, int wpr, int64_t n,
-                                           uint32_t *__restrict__ out, int nw, int64_t ld) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n * nw) return;
-    const int w = (int)(i / n);
-    const int64_t p = i - (int64_t)w * n;
-    out[(int64_t)w * ld + p] = w < wpr ? in[p * wpr + w] : 0u;
+// Reads of a batch, read p in words in[woff[p] .. woff[p+1]) (rows of nw
+// words, or packed reads of their own length) -> word-major out[nw][ld];
+// words past a read's own are written as 0.  One thread per pair: its reads
+// walk one contiguous run, and each of its writes is coalesced with the
+// neighbouring pairs' writes of the same word.
+__global__ __launch_bounds__(256) void reads_to_word_major_kernel(const uint32_t *__restrict__ in,
+                                                                  const int32_t *__restrict__ woff, int64_t n,
+                                                                  uint32_t *__restrict__ out, int nw, int64_t ld) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int32_t a = woff[p];
+    const int cnt = woff[p + 1] - a;
+    for (int w = 0; w < nw; w++) out[(int64_t)w * ld + p] = w < cnt ? in[a + w] : 0u;
 }
 
 // Reference segment of pair p = pool bases [off[p], off[p] + len[p]), written
-// word-major to out[nw][ld]; pool base b sits in bits 2(b%16).. of word b/16.
-// A segment that does not lie inside the pool makes the pair invalid
-// (len[p] = -1, so the filter gives it the sentinels).
-__global__ void pool_gather_kernel(const uint32_t *__restrict__ pool, int64_t pool_bases,
-                                   const int64_t *__restrict__ off, int32_t *__restrict__ len,
-                                   int64_t n, uint32_t *__restrict__ out, int nw, int64_t ld) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n * nw) return;
-    const int w = (int)(i / n);
-    const int64_t p = i - (int64_t)w * n;
-    int64_t o = off[p];
-    const bool inside = o >= 0 && o <= pool_bases;
-    if (w == 0) {
-        const int32_t m = len[p];
-        if (!inside || m < 0 || (int64_t)m > pool_bases - o) len[p] = -1;
-    }
-    if (!inside) o = 0;
+// word-major to out[nw][ld]; pool base b sits in bits 2(b%16).. of word b/16;
+// words past the segment's end are written as 0.  A segment that does not lie
+// inside the pool makes the pair invalid (len[p] = -1, so the filter gives it
+// the sentinels).  One thread per pair, as above.
+__global__ __launch_bounds__(256) void pool_gather_kernel(const uint32_t *__restrict__ pool, int64_t pool_bases,
+                                                          const int64_t *__restrict__ off, int32_t *__restrict__ len,
+                                                          int64_t n, uint32_t *__restrict__ out, int nw, int64_t ld) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int64_t o = off[p];
+    const int32_t m = len[p];
+    const bool ok = o >= 0 && o <= pool_bases && m >= 0 && (int64_t)m <= pool_bases - o;
+    if (!ok) len[p] = -1;
+    // words holding bases of the segment (none for an invalid pair)
+    const int nseg = ok ? (int)min((int64_t)nw, ((int64_t)m + kHalf - 1) / kHalf) : 0;
     const int64_t pool_words = (pool_bases + kHalf - 1) / kHalf;
-    const int64_t b = o + (int64_t)w * kHalf;   // first base of this word
-    const int64_t q = b >> 4;
-    const int sh = (int)(b & 15) * 2;
-    const uint32_t lo = q < pool_words ? pool[q] : 0u;
-    const uint32_t hi = (sh != 0 && q + 1 < pool_words) ? pool[q + 1] : 0u;
-    out[(int64_t)w * ld + p] = sh ? (uint32_t)((((uint64_t)hi << 32) | lo) >> sh) : lo;
+    const int sh = (int)(o & 15) * 2;
+    int64_t q = o >> 4;                              // pool word of the segment's first base
+    uint32_t lo = nseg > 0 && q < pool_words ? pool[q] : 0u;
+    for (int w = 0; w < nw; w++) {
+        uint32_t v = 0u;
+        if (w < nseg) {
+            const uint32_t hi = (sh != 0 && q + 1 < pool_words) ? pool[q + 1] : 0u;
+            v = sh ? (uint32_t)((((uint64_t)hi << 32) | lo) >> sh) : lo;
+            lo = sh ? hi : (q + 1 < pool_words ? pool[q + 1] : 0u);
+            q++;
+        }
+        out[(int64_t)w * ld + p] = v;
+    }
 }
 
 }  // namespace shouji
@@ -94,7 +103,13 @@ struct Part {
     Request *r;
     int64_t first;   // first pair of the request in this part
     int64_t count;
+    int64_t word_first = 0;   // packed request: word of the request's reads where pair `first` begins
 };
+
+// Words a packed request gives the read of a pair of length m.
+inline int64_t packed_words(int32_t m, int max_len) {
+    return (m >= 1 && m <= max_len) ? (m + shouji::kHalf - 1) / shouji::kHalf : 0;
+}
 
 struct Slot {
     hipStream_t stream = nullptr;
@@ -102,9 +117,11 @@ struct Slot {
     uint32_t *h_reads = nullptr;  // pinned staging
     int64_t *h_off = nullptr;
     int32_t *h_len = nullptr, *h_E = nullptr;
+    int32_t *h_woff = nullptr;    // word offset of each read in the read buffers (+ end)
     uint8_t *h_acc = nullptr;
     int16_t *h_pc = nullptr;
-    uint32_t *d_reads_pm = nullptr, *d_reads = nullptr, *d_refs = nullptr;
+    uint32_t *d_reads_in = nullptr, *d_reads = nullptr, *d_refs = nullptr;
+    int32_t *d_woff = nullptr;
     int64_t *d_off = nullptr;
     int32_t *d_len = nullptr, *d_E = nullptr;
     uint8_t *d_acc = nullptr;
@@ -118,7 +135,7 @@ struct Slot {
 };
 
 int64_t slot_device_bytes(int64_t B, int nw, int max_len) {
-    return 3 * B * nw * 4 + B * (8 + 4 + 4 + 1 + 2) + shouji_batched_workspace_bytes(B, max_len);
+    return 3 * B * nw * 4 + B * (8 + 4 + 4 + 1 + 2) + (B + 1) * 4 + shouji_batched_workspace_bytes(B, max_len);
 }
 
 void free_slot(Slot &s) {
@@ -128,9 +145,11 @@ void free_slot(Slot &s) {
     hipHostFree(s.h_off);
     hipHostFree(s.h_len);
     hipHostFree(s.h_E);
+    hipHostFree(s.h_woff);
     hipHostFree(s.h_acc);
     hipHostFree(s.h_pc);
-    hipFree(s.d_reads_pm);
+    hipFree(s.d_reads_in);
+    hipFree(s.d_woff);
     hipFree(s.d_reads);
     hipFree(s.d_refs);
     hipFree(s.d_off);
@@ -150,9 +169,11 @@ bool alloc_slot(Slot &s, int64_t B, int nw, int max_len) {
            hipHostMalloc((void **)&s.h_off, (size_t)B * 8, 0) == hipSuccess &&
            hipHostMalloc((void **)&s.h_len, (size_t)B * 4, 0) == hipSuccess &&
            hipHostMalloc((void **)&s.h_E, (size_t)B * 4, 0) == hipSuccess &&
+           hipHostMalloc((void **)&s.h_woff, (size_t)(B + 1) * 4, 0) == hipSuccess &&
            hipHostMalloc((void **)&s.h_acc, (size_t)B, 0) == hipSuccess &&
            hipHostMalloc((void **)&s.h_pc, (size_t)B * 2, 0) == hipSuccess &&
-           hipMalloc((void **)&s.d_reads_pm, (size_t)B * nw * 4) == hipSuccess &&
+           hipMalloc((void **)&s.d_reads_in, (size_t)B * nw * 4) == hipSuccess &&
+           hipMalloc((void **)&s.d_woff, (size_t)(B + 1) * 4) == hipSuccess &&
            hipMalloc((void **)&s.d_reads, (size_t)B * nw * 4) == hipSuccess &&
            hipMalloc((void **)&s.d_refs, (size_t)B * nw * 4) == hipSuccess &&
            hipMalloc((void **)&s.d_off, (size_t)B * 8) == hipSuccess &&
@@ -216,33 +237,65 @@ void run_copies(const std::vector<CopyJob> &jobs, int threads) {
     for (std::thread &t : pool) t.join();
 }
 
-// A part whose request buffers are pinned and whose read rows have the
-// server's width moves by DMA straight between the request and the device.
+// A part whose request buffers are pinned and whose reads are packed or in
+// rows of the server's width moves by DMA straight between the request and
+// the device.
 bool direct_part(const shouji_request &r, int nw) {
-    return (r.flags & SHOUJI_REQUEST_PINNED) && r.words_per_read == nw;
+    return (r.flags & SHOUJI_REQUEST_PINNED) && ((r.flags & SHOUJI_REQUEST_PACKED) || r.words_per_read == nw);
 }
 
 // Enqueue one batch on the slot's stream: parts in pageable memory are first
 // copied into the slot's pinned staging buffers (consecutive such parts then
-// move in one copy), pinned parts are copied directly.  Runs without the
-// server lock: the slot is marked busy and its requests stay alive until all
-// their pairs are delivered.
+// move in one copy), pinned parts are copied directly.  The batch's reads lie
+// back to back in the slot's read buffers, each part's where the previous one
+// ends: a packed part's reads take their own word counts, rows nw words each;
+// the word offset of every read goes to the device with them.  Runs without
+// the server lock: the slot is marked busy and its requests stay alive until
+// all their pairs are delivered.
 int enqueue_batch(shouji_server *S, Slot &s) {
     const int nw = S->nw;
+    const int max_len = S->cfg.max_len;
+    const size_t np = s.parts.size();
+    std::vector<int64_t> wpos(np + 1);   // first word of each part in the read buffers
+    int64_t at = 0, wcur = 0;
+    for (size_t i = 0; i < np; i++) {
+        const Part &pt = s.parts[i];
+        const shouji_request &r = pt.r->req;
+        wpos[i] = wcur;
+        int32_t *wo = s.h_woff + at;
+        if (r.flags & SHOUJI_REQUEST_PACKED) {
+            const int32_t *len = r.lengths + pt.first;
+            for (int64_t k = 0; k < pt.count; k++) {
+                wo[k] = (int32_t)wcur;
+                wcur += packed_words(len[k], max_len);
+            }
+        } else {
+            for (int64_t k = 0; k < pt.count; k++) wo[k] = (int32_t)(wcur + k * nw);
+            wcur += pt.count * nw;
+        }
+        at += pt.count;
+    }
+    wpos[np] = wcur;
+    s.h_woff[at] = (int32_t)wcur;
+
     std::vector<CopyJob> jobs;
-    int64_t at = 0;
-    for (const Part &pt : s.parts) {
+    at = 0;
+    for (size_t i = 0; i < np; i++) {
+        const Part &pt = s.parts[i];
         const shouji_request &r = pt.r->req;
         const int64_t c = pt.count, f = pt.first;
         if (!direct_part(r, nw)) {
-            if (r.words_per_read == nw) {
-                jobs.push_back(CopyJob{s.h_reads + at * nw, r.reads + f * nw, (size_t)c * nw * 4});
+            uint32_t *dst = s.h_reads + wpos[i];
+            if (r.flags & SHOUJI_REQUEST_PACKED) {
+                jobs.push_back(CopyJob{dst, r.reads + pt.word_first, (size_t)(wpos[i + 1] - wpos[i]) * 4});
+            } else if (r.words_per_read == nw) {
+                jobs.push_back(CopyJob{dst, r.reads + f * nw, (size_t)c * nw * 4});
             } else {
                 const int cw = std::min(nw, (int)r.words_per_read);
                 for (int64_t k = 0; k < c; k++) {
-                    uint32_t *dst = s.h_reads + (at + k) * nw;
-                    memcpy(dst, r.reads + (f + k) * r.words_per_read, (size_t)cw * 4);
-                    for (int w = cw; w < nw; w++) dst[w] = 0u;
+                    uint32_t *row = dst + k * nw;
+                    memcpy(row, r.reads + (f + k) * r.words_per_read, (size_t)cw * 4);
+                    for (int w = cw; w < nw; w++) row[w] = 0u;
                 }
             }
             jobs.push_back(CopyJob{s.h_off + at, r.ref_offsets + f, (size_t)c * 8});
@@ -260,37 +313,41 @@ int enqueue_batch(shouji_server *S, Slot &s) {
         if (good && bytes) good = hipMemcpyAsync(dst, src, bytes, kind, st) == hipSuccess;
     };
     // host -> device
-    int64_t run = -1;   // first pair of the current run of staged parts
-    auto flush_in = [&](int64_t e) {
+    int64_t run = -1, wrun = 0;   // first pair and first word of the current run of staged parts
+    auto flush_in = [&](int64_t e, int64_t we) {
         if (run < 0) return;
         const int64_t c = e - run;
-        copy(s.d_reads_pm + run * nw, s.h_reads + run * nw, (size_t)c * nw * 4, hipMemcpyHostToDevice);
+        copy(s.d_reads_in + wrun, s.h_reads + wrun, (size_t)(we - wrun) * 4, hipMemcpyHostToDevice);
         copy(s.d_off + run, s.h_off + run, (size_t)c * 8, hipMemcpyHostToDevice);
         copy(s.d_len + run, s.h_len + run, (size_t)c * 4, hipMemcpyHostToDevice);
         copy(s.d_E + run, s.h_E + run, (size_t)c * 4, hipMemcpyHostToDevice);
         run = -1;
     };
     at = 0;
-    for (const Part &pt : s.parts) {
+    for (size_t i = 0; i < np; i++) {
+        const Part &pt = s.parts[i];
         const shouji_request &r = pt.r->req;
         const int64_t c = pt.count, f = pt.first;
         if (direct_part(r, nw)) {
-            flush_in(at);
-            copy(s.d_reads_pm + at * nw, r.reads + f * nw, (size_t)c * nw * 4, hipMemcpyHostToDevice);
+            flush_in(at, wpos[i]);
+            const uint32_t *src = (r.flags & SHOUJI_REQUEST_PACKED) ? r.reads + pt.word_first : r.reads + f * nw;
+            copy(s.d_reads_in + wpos[i], src, (size_t)(wpos[i + 1] - wpos[i]) * 4, hipMemcpyHostToDevice);
             copy(s.d_off + at, r.ref_offsets + f, (size_t)c * 8, hipMemcpyHostToDevice);
             copy(s.d_len + at, r.lengths + f, (size_t)c * 4, hipMemcpyHostToDevice);
             copy(s.d_E + at, r.E + f, (size_t)c * 4, hipMemcpyHostToDevice);
         } else if (run < 0) {
             run = at;
+            wrun = wpos[i];
         }
         at += c;
     }
-    flush_in(at);
+    flush_in(at, wcur);
+    copy(s.d_woff, s.h_woff, (size_t)(n + 1) * 4, hipMemcpyHostToDevice);
     int rc = good ? SHOUJI_OK : SHOUJI_ERR_DEVICE;
     if (rc == SHOUJI_OK) {
-        const unsigned blocks = (unsigned)((n * nw + 255) / 256);
-        hipLaunchKernelGGL(shouji::reads_to_word_major_kernel, dim3(blocks), dim3(256), 0, st, s.d_reads_pm,
-                           nw, n, s.d_reads, nw, n);
+        const unsigned blocks = (unsigned)((n + 255) / 256);
+        hipLaunchKernelGGL(shouji::reads_to_word_major_kernel, dim3(blocks), dim3(256), 0, st, s.d_reads_in,
+                           s.d_woff, n, s.d_reads, nw, n);
         hipLaunchKernelGGL(shouji::pool_gather_kernel, dim3(blocks), dim3(256), 0, st, S->cfg.pool,
                            S->cfg.pool_bases, s.d_off, s.d_len, n, s.d_refs, nw, n);
         rc = hipGetLastError() == hipSuccess ? SHOUJI_OK : SHOUJI_ERR_DEVICE;
@@ -345,8 +402,15 @@ void scheduler_loop(shouji_server *S) {
         while (!S->queue.empty() && s->pairs < B) {
             Part &q = S->queue.front();
             const int64_t take = std::min(q.count, B - s->pairs);
-            s->parts.push_back(Part{q.r, q.first, take});
+            s->parts.push_back(Part{q.r, q.first, take, q.word_first});
             s->pairs += take;
+            if (take < q.count && (q.r->req.flags & SHOUJI_REQUEST_PACKED)) {
+                // the rest of a packed request begins after the words of these reads
+                const int32_t *len = q.r->req.lengths + q.first;
+                int64_t words = 0;
+                for (int64_t k = 0; k < take; k++) words += packed_words(len[k], S->cfg.max_len);
+                q.word_first += words;
+            }
             q.first += take;
             q.count -= take;
             if (q.count == 0) S->queue.pop_front();
@@ -428,6 +492,9 @@ extern "C" int shouji_server_create(const shouji_server_config *cfg, shouji_serv
     std::unique_ptr<shouji_server> S(new shouji_server());
     S->cfg = *cfg;
     S->nw = (cfg->max_len + shouji::kHalf - 1) / shouji::kHalf;
+    if (cfg->max_batch_pairs > INT32_MAX / S->nw)
+        return set_error(SHOUJI_ERR_RANGE, "shouji_server_create: max_batch_pairs %lld too large (read words of a "
+                         "batch are indexed in 32 bits)", (long long)cfg->max_batch_pairs);
     if (hipGetDevice(&S->device) != hipSuccess)
         return set_error(SHOUJI_ERR_DEVICE, "shouji_server_create: no current HIP device");
     const int64_t per = slot_device_bytes(cfg->max_batch_pairs, S->nw, cfg->max_len);
@@ -456,10 +523,12 @@ extern "C" int shouji_server_submit(shouji_server *S, const shouji_request *r, u
     if (!S || !r || !ticket)
         return set_error(SHOUJI_ERR_NULL, "shouji_server_submit: server, request and ticket are required");
     if (r->n_pairs < 0) return set_error(SHOUJI_ERR_ARG, "shouji_server_submit: n_pairs < 0");
+    if (r->flags & ~(SHOUJI_REQUEST_PINNED | SHOUJI_REQUEST_PACKED))
+        return set_error(SHOUJI_ERR_ARG, "shouji_server_submit: unknown flags 0x%x", r->flags);
     if (r->n_pairs > 0) {
         if (!r->reads || !r->ref_offsets || !r->lengths || !r->E || !r->out_accept)
             return set_error(SHOUJI_ERR_NULL, "shouji_server_submit: request buffer missing");
-        if (r->words_per_read <= 0)
+        if (!(r->flags & SHOUJI_REQUEST_PACKED) && r->words_per_read <= 0)
             return set_error(SHOUJI_ERR_ARG, "shouji_server_submit: words_per_read must be positive");
     }
     std::unique_ptr<Request> R(new Request());
@@ -477,7 +546,12 @@ extern "C" int shouji_server_submit(shouji_server *S, const shouji_request *r, u
     if (r->n_pairs > 0 && (!S->queue.empty() || std::all_of(S->slots.begin(), S->slots.end(),
                                                             [](const std::unique_ptr<Slot> &q) { return q->busy; })))
         S->requests_deferred++;
-    for (int64_t f = 0; f < r->n_pairs; f += B) S->queue.push_back(Part{R.get(), f, std::min(B, r->n_pairs - f)});
+    if (r->flags & SHOUJI_REQUEST_PACKED) {
+        // one part: the scheduler cuts it and follows the word offset of each cut
+        if (r->n_pairs > 0) S->queue.push_back(Part{R.get(), 0, r->n_pairs, 0});
+    } else {
+        for (int64_t f = 0; f < r->n_pairs; f += B) S->queue.push_back(Part{R.get(), f, std::min(B, r->n_pairs - f)});
+    }
     S->reqs[t] = std::move(R);
     *ticket = t;
     S->cv.notify_all();

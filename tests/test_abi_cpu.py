@@ -81,6 +81,8 @@ def test_server_argument_errors_are_reported_without_a_device():
     cfg = sj.ServerConfig(16, 1000, 100, 0, 1024, 0, 0)
     assert L.shouji_server_create(ctypes.byref(cfg), ctypes.byref(h)) == -2      # slots
     assert b"slots" in L.shouji_last_error()
+    cfg = sj.ServerConfig(16, 1000, 300, 2, 1 << 40, 0, 0)
+    assert L.shouji_server_create(ctypes.byref(cfg), ctypes.byref(h)) == -3      # batch words
     t = ctypes.c_uint64()
     assert L.shouji_server_submit(None, None, ctypes.byref(t)) == -1
     assert L.shouji_server_wait(None, 1, None) == -1
@@ -104,3 +106,19 @@ def test_pool_and_pair_packing_layout():
     for p in range(7):
         for j in range(45):
             assert (int(pp[p, j // 16]) >> (2 * (j % 16))) & 3 == c[p, j]
+
+
+def test_packed_read_layout():
+    # reads back to back, ceil(m/16) words each, none for a length outside
+    # [1, max_len]; read p is the first words of its row in the row layout
+    rng = np.random.default_rng(2)
+    c = rng.integers(0, 4, (9, 70), dtype=np.uint8)
+    lens = np.array([70, 1, 16, 17, 0, -3, 71, 33, 48], dtype=np.int32)
+    words, off = sj.pack_reads_packed(c, lens, 70)
+    k = [5, 1, 1, 2, 0, 0, 0, 3, 3]
+    assert list(np.diff(off)) == k and off[0] == 0 and words.size == sum(k)
+    assert words.dtype == np.uint32
+    rows = sj.pack_pairs(c, 70)
+    for p in range(9):
+        assert np.array_equal(words[off[p]:off[p + 1]], rows[p, :k[p]])
+    assert list(sj.packed_read_words(lens, 70)) == k

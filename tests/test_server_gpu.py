@@ -219,3 +219,56 @@ def test_pinned_and_pageable_requests_share_batches(sj, work):
             srv2.submit(work["reads"][:4], work["off"][:4], p.lengths[:4], p.E[:4], pinned=True)
         finally:
             srv2.close()
+
+
+def test_packed_reads_in_every_mix_of_formats(sj, work):
+    # packed requests (pinned and pageable) are cut across batches at any
+    # pair, and share batches with row requests (pinned and pageable)
+    p = work["p"]
+    words, wo = sj.pack_reads_packed(p.P, p.lengths, MAX_LEN)
+    cuts = _cuts(p.n, [2500, 1, 7000, 333, 4096, 5000, 64, 9000, 3, 4095])
+    keep = []
+    print("server: packed and row requests, %d requests, batch 4096" % len(cuts), flush=True)
+    with _server(sj, work, slots=2, max_batch_pairs=4096) as srv:
+        tickets = []
+        for i, (lo, hi) in enumerate(cuts):
+            kind = i % 4
+            if kind == 0:
+                t = srv.submit(words[wo[lo]:wo[hi]], work["off"][lo:hi], p.lengths[lo:hi], p.E[lo:hi],
+                               packed=True)
+            elif kind == 2:
+                t = _submit(srv, work, lo, hi)
+            else:
+                r = words[wo[lo]:wo[hi]] if kind == 1 else work["reads"][lo:hi]
+                bufs = [_pinned(a) for a in (r, work["off"][lo:hi], p.lengths[lo:hi], p.E[lo:hi],
+                                             np.zeros(hi - lo, np.uint8), np.zeros(hi - lo, np.int16))]
+                keep.append(bufs)
+                r, o, L, E, a, c = [v for _, v in bufs]
+                t = srv.submit(r, o, L, E, pinned=True, packed=kind == 1, out_accept=a, out_popcount=c)
+            tickets.append(t)
+        for (lo, hi), t in zip(cuts, tickets):
+            acc, pc, _ = srv.wait(t)
+            _expect(work, lo, hi, acc, pc)
+        st = srv.stats()
+    assert st["pairs_done"] == p.n and st["queued_pairs"] == 0
+
+
+def test_packed_reads_with_invalid_and_empty_lengths(sj, work):
+    # a length outside [1, max_len] takes no words of the packed reads; the
+    # pairs after it still find theirs
+    p = work["p"]
+    lo, hi = 0, 3000
+    lens = p.lengths[lo:hi].copy()
+    lens[3::47] = MAX_LEN + 1
+    lens[4::53] = -2
+    lens[5::59] = 0
+    words, _ = sj.pack_reads_packed(p.P[lo:hi], lens, MAX_LEN)
+    with _server(sj, work, slots=2, max_batch_pairs=1000) as srv:
+        acc, pc, _ = srv.wait(srv.submit(words, work["off"][lo:hi], lens, p.E[lo:hi], packed=True))
+        with pytest.raises(ValueError):
+            srv.submit(words[:-1], work["off"][lo:hi], lens, p.E[lo:hi], packed=True)
+    bad = (lens < 0) | (lens > MAX_LEN)
+    assert (acc[bad] == 0xFF).all() and (pc[bad] == -1).all()
+    good = ~bad
+    ea, ep = oracle.shouji_batch(p.P[lo:hi][good], p.T[lo:hi][good], lens[good], E_per_pair=p.E[lo:hi][good])
+    assert np.array_equal(acc[good], ea) and np.array_equal(pc[good], ep)
