@@ -733,18 +733,19 @@ def bench_serving(dev, total_pairs, batch_pairs, slots, distinct=1_000_000, load
                 "deferred_poisson": st2["requests_deferred"] - st1["requests_deferred"],
                 "mismatches_vs_batched": state["bad"]}
 
-    # host-link bytes per pair: the reads, the segment offset, length and E
+    # host-link bytes per pair: the reads, the segment offset, length, E and
+    # the read's word offset in the batch
     nw = sj.nwords(max_len)
     # a short untimed pass first, so that first-use costs of the process stay
     # out of the timed runs
     run("pinned", nreq=min(40, len(sizes)))
     rows_pinned = run("pinned")
     res = run("packed")
-    res["host_bytes_per_pair"] = 4 * pwords.size / distinct + 16
+    res["host_bytes_per_pair"] = 4 * pwords.size / distinct + 20
     res["rows_pinned"] = rows_pinned
-    res["rows_pinned"]["host_bytes_per_pair"] = 4 * nw + 16
+    res["rows_pinned"]["host_bytes_per_pair"] = 4 * nw + 20
     res["pageable"] = run("pageable")
-    res["pageable"]["host_bytes_per_pair"] = 4 * nw + 16
+    res["pageable"]["host_bytes_per_pair"] = 4 * nw + 20
     res.update({"workload": "Poisson stream of %d requests, %d pairs in all, request size "
                             "U{1..200000}, lengths uniform 64..300, E_p=floor(r*m) r~U[0,0.10], "
                             "2 GiB device-resident packed reference pool (8 Gi bases), seed %d; "
