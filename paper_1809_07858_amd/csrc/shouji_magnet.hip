@@ -68,8 +68,10 @@ __global__ __launch_bounds__(kMagnetBlock) void magnet_kernel(MagnetParams prm) 
     // carried run ends at the first mismatch; the runs strictly between the
     // first and the last mismatch are searched with doubling masks (r_k: a
     // run of at least k starts here) and a binary descent on the length; the
-    // matches after the last mismatch are carried on.
-    auto longest = [&](int d, int lo, int hi, int &start) -> int {
+    // matches after the last mismatch are carried on.  The result is exact
+    // when it is at least `need`; the walk stops as soon as no run of the
+    // rest of the range can reach `need` or exceed the longest found.
+    auto longest = [&](int d, int lo, int hi, int &start, int need) -> int {
         const int a = lo > d ? lo : d;                       // pattern index j-d >= 0
         const int b = hi < m - 1 + d ? hi : m - 1 + d;       // pattern index j-d < m
         int best = 0;
@@ -77,6 +79,8 @@ __global__ __launch_bounds__(kMagnetBlock) void magnet_kernel(MagnetParams prm) 
         if (a > b) return 0;
         int carry = 0, cs = (a >> 4) * 16;                  // run reaching the word's start
         for (int w = a >> 4; w <= (b >> 4); w++) {
+            const int rest = b - (a > 16 * w ? a : 16 * w) + 1;   // positions left in the range
+            if (carry + rest <= (best > need - 1 ? best : need - 1)) break;
             const uint32_t tw = T[(int64_t)w * ld];
             const int q0 = 16 * w - d;                       // read position of the word's field 0
             const int qw = q0 >> 4;                          // floor division
@@ -139,14 +143,27 @@ __global__ __launch_bounds__(kMagnetBlock) void magnet_kernel(MagnetParams prm) 
         sp--;
         const uint32_t e = stk[sp * kMagnetBlock];
         const int lo = (int)(e & 0xFFFFu), hi = (int)(e >> 16);
-        int len = 0, s = 0;
-        for (int r = 0; r < 2 * Ee + 1; r++) {
-            const int d = r == 2 * Ee ? 0 : ((r & 1) ? (r >> 1) + 1 : -((r >> 1) + 1));
+        // The main diagonal comes last in the order but is searched first:
+        // its run bounds what every other diagonal must reach.  A side
+        // diagonal precedes it, so it takes over from the main run on a tie,
+        // and from an earlier side run only when strictly longer.  A run of
+        // length 0 takes nothing, and in the first call a run shorter than
+        // thr stops the pair whichever diagonal holds it, so neither needs
+        // an exact length.
+        int s = 0;
+        int len = longest(0, lo, hi, s, first ? thr : 1);
+        bool main_kept = true;
+        for (int r = 0; r < 2 * Ee; r++) {
+            const int d = (r & 1) ? (r >> 1) + 1 : -((r >> 1) + 1);
+            int need = main_kept ? len : len + 1;
+            if (need < 1) need = 1;
+            if (first && need < thr) need = thr;
             int st;
-            const int l = longest(d, lo, hi, st);
-            if (l > len) {
+            const int l = longest(d, lo, hi, st, need);
+            if (l >= need) {
                 len = l;
                 s = st;
+                main_kept = false;
             }
         }
         if (first && len < thr) {                            // early termination: all ones
