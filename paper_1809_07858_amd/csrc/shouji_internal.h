@@ -179,12 +179,15 @@ struct TilesParams {
 // Pattern ring slots.  Iteration j reads pattern positions [16j-Ee, 16j+18+Ee]
 // (both lane halves).  After its searches the word that iteration j+1 first
 // needs, word j+1+H0 with H0 = (18+Ee)/16, is written; it must not overwrite
-// positions from 16j+16-Ee on.
+// positions from 16j+16-Ee on.  Rounded up to a multiple of 8, so that each
+// half of a word (8 positions starting at a multiple of 8) lands in 8
+// consecutive slots and is written without a wrap test.
 inline int ring_slots(int Ee) {
     const int H0 = (kBlock + kCols - 1 + Ee) / kHalf;
     const int a = 2 * Ee + kBlock + kCols;
     const int b = kHalf * (H0 + 1) + Ee;
-    return a > b ? a : b;
+    const int r = a > b ? a : b;
+    return (r + 7) / 8 * 8;
 }
 // LDS of one wavefront: the pattern ring (+ mirror); the per-position masks
 // of the iteration's positions lo .. lo+kBlock+kCols+Ee-1; the bit planes of

@@ -682,13 +682,21 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     auto pass_finish = [&](int pw, int limit, uint32_t (&raw)[32]) {
         transpose32(raw);
         if (half == 0 && pw < limit) {
-            int slot = (pw * kHalf) % R;
+            // R is a multiple of 8: each half word goes to 8 consecutive
+            // slots (paired writes), the slots below kMirror also past R
 #pragma unroll
-            for (int u = 0; u < kHalf; u++) {
-                const uint2 v = make_uint2(raw[2 * u], raw[2 * u + 1]);
-                ring[slot * kRingStride + pl] = v;
-                if (slot < kMirror) ring[(slot + R) * kRingStride + pl] = v;
-                slot = slot + 1 == R ? 0 : slot + 1;
+            for (int h = 0; h < 2; h++) {
+                const int s0 = (pw * kHalf + 8 * h) % R;
+                uint2 *dst = ring + s0 * kRingStride + pl;
+#pragma unroll
+                for (int u = 0; u < 8; u++)
+                    dst[u * kRingStride] = make_uint2(raw[2 * (8 * h + u)], raw[2 * (8 * h + u) + 1]);
+                if (s0 < kMirror) {
+#pragma unroll
+                    for (int u = 0; u < 8; u++)
+                        if (s0 + u < kMirror)
+                            dst[(R + u) * kRingStride] = make_uint2(raw[2 * (8 * h + u)], raw[2 * (8 * h + u) + 1]);
+                }
             }
         }
     };
