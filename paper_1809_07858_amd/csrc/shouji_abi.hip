@@ -60,6 +60,24 @@ int raise_lds_limit(const void *kernel, size_t &limit, size_t bytes) {
 
 extern "C" int shouji_version(void) { return 1 * 10000 + 0 * 100 + 0; }
 
+namespace {
+// Wavefronts a CU holds with workgroups of wpg wavefronts of wl LDS bytes
+// each (registers allow two per SIMD).
+int waves_per_cu(size_t wl, int wpg) {
+    const size_t w = shouji::kLdsPerCU / (wl * wpg) * wpg;
+    return w > 8 ? 8 : (int)w;
+}
+// Ring slots of a plain launch with workgroups of wpg wavefronts: 8-aligned
+// unless that lets a CU hold fewer wavefronts.
+int plain_ring(int Ee, int wpg) {
+    const int a = shouji::ring_slots_aligned(Ee), m = shouji::ring_slots(Ee);
+    return waves_per_cu(shouji::plain_lds_wave_bytes(Ee, a), wpg) >=
+                   waves_per_cu(shouji::plain_lds_wave_bytes(Ee, m), wpg)
+               ? a
+               : m;
+}
+}  // namespace
+
 extern "C" int shouji_filter(const uint32_t *reads, const uint32_t *refs, const int32_t *lengths,
                              int32_t E, uint8_t *out_accept, int16_t *out_popcount,
                              int64_t n_pairs, int32_t max_len, int64_t ld, void *stream) {
@@ -83,13 +101,13 @@ extern "C" int shouji_filter(const uint32_t *reads, const uint32_t *refs, const 
     prm.max_len = max_len;
     prm.E = E;
     prm.Ee = Ee;
-    prm.R = shouji::ring_slots(Ee);
     prm.out_accept = out_accept;
     prm.out_popcount = out_popcount;
     prm.n = n_pairs;
     // Workgroups of 4 wavefronts (1024 pairs each); LDS and registers let a CU
     // hold two of them, i.e. two wavefronts per SIMD.
-    const size_t wave_lds = shouji::plain_lds_wave_bytes(Ee);
+    prm.R = plain_ring(Ee, shouji::kWavesPerGroup);
+    const size_t wave_lds = shouji::plain_lds_wave_bytes(Ee, prm.R);
     const size_t lds = wave_lds * shouji::kWavesPerGroup;
     if (lds > shouji::kLdsPerCU) return fail(SHOUJI_ERR_RANGE, "E %d needs more LDS than one CU holds", E);
     const int64_t waves = (n_pairs + shouji::kPairsPerWave - 1) / shouji::kPairsPerWave;
@@ -133,7 +151,6 @@ extern "C" int shouji_filter_local(const uint32_t *reads, const uint32_t *refs, 
     prm.max_len = max_len;
     prm.E = E;
     prm.Ee = Ee;
-    prm.R = shouji::ring_slots(Ee);
     prm.mode = mode;
     prm.out_accept = out_accept;
     prm.out_popcount = out_popcount;
@@ -143,9 +160,16 @@ extern "C" int shouji_filter_local(const uint32_t *reads, const uint32_t *refs, 
     int len_bits = 1;
     while ((1 << len_bits) <= max_len) len_bits++;   // bits of max_len
     prm.len_bits = len_bits;
-    const size_t wave_lds = shouji::local_lds_wave_bytes(Ee, len_bits);
+    // the 8-aligned ring unless the minimal one lets a CU hold more wavefronts
+    auto local_wpg = [](size_t wl) { return 8 * wl <= shouji::kLdsPerCU ? shouji::kWavesPerGroup : 1; };
+    auto local_waves = [&](size_t wl) { return wl > shouji::kLdsPerCU ? 0 : waves_per_cu(wl, local_wpg(wl)); };
+    prm.R = shouji::ring_slots(Ee);
+    if (local_waves(shouji::local_lds_wave_bytes(Ee, len_bits, shouji::ring_slots_aligned(Ee))) >=
+        local_waves(shouji::local_lds_wave_bytes(Ee, len_bits, prm.R)))
+        prm.R = shouji::ring_slots_aligned(Ee);
+    const size_t wave_lds = shouji::local_lds_wave_bytes(Ee, len_bits, prm.R);
     if (wave_lds > shouji::kLdsPerCU) return fail(SHOUJI_ERR_RANGE, "E %d needs more LDS than one CU holds", E);
-    const int wpg = 8 * wave_lds <= shouji::kLdsPerCU ? shouji::kWavesPerGroup : 1;
+    const int wpg = local_wpg(wave_lds);
     const size_t lds = wave_lds * wpg;
     const int64_t waves = (n_pairs + shouji::kPairsPerWave - 1) / shouji::kPairsPerWave;
     const int64_t grid = (waves + wpg - 1) / wpg;
@@ -302,16 +326,28 @@ extern "C" int shouji_filter_batched(const uint32_t *reads, const uint32_t *refs
         tp.tiles = po.tiles[c];
         tp.ntiles = ntiles + c;
         tp.max_len = max_len;
-        tp.R = shouji::ring_slots(Ecls);
-        const size_t wave_lds = shouji::plain_lds_wave_bytes(Ecls);
         // the workgroup size (at most the configured one) that lets a CU hold
-        // the most wavefronts (two per SIMD at most)
-        int wpg = 0, best_waves = 0;
-        for (int g = cfg.waves_per_group; g >= 1; g >>= 1) {
-            int waves = (int)(shouji::kLdsPerCU / (wave_lds * g)) * g;
-            if (waves > 8) waves = 8;
-            if (waves > best_waves) { best_waves = waves; wpg = g; }
+        // the most wavefronts (two per SIMD at most), with the 8-aligned ring
+        // unless the minimal one lets it hold more
+        auto best_group = [&](size_t wl, int &best_waves) {
+            int wpg_ = 0;
+            best_waves = 0;
+            for (int g = cfg.waves_per_group; g >= 1; g >>= 1) {
+                int waves = (int)(shouji::kLdsPerCU / (wl * g)) * g;
+                if (waves > 8) waves = 8;
+                if (waves > best_waves) { best_waves = waves; wpg_ = g; }
+            }
+            return wpg_;
+        };
+        int best_waves = 0, best_min = 0;
+        int wpg = best_group(shouji::plain_lds_wave_bytes(Ecls, shouji::ring_slots_aligned(Ecls)), best_waves);
+        tp.R = shouji::ring_slots_aligned(Ecls);
+        const int wpg_min = best_group(shouji::plain_lds_wave_bytes(Ecls, shouji::ring_slots(Ecls)), best_min);
+        if (best_min > best_waves) {
+            wpg = wpg_min;
+            tp.R = shouji::ring_slots(Ecls);
         }
+        const size_t wave_lds = shouji::plain_lds_wave_bytes(Ecls, tp.R);
         if (wpg == 0) return fail(SHOUJI_ERR_RANGE, "LDS too small for E %d", Ecls);
         tp.lds_wave_bytes = (int32_t)wave_lds;
         tp.waves_per_group = wpg;

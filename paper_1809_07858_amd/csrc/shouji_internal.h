@@ -179,32 +179,35 @@ struct TilesParams {
 // Pattern ring slots.  Iteration j reads pattern positions [16j-Ee, 16j+18+Ee]
 // (both lane halves).  After its searches the word that iteration j+1 first
 // needs, word j+1+H0 with H0 = (18+Ee)/16, is written; it must not overwrite
-// positions from 16j+16-Ee on.  Rounded up to a multiple of 8, so that each
-// half of a word (8 positions starting at a multiple of 8) lands in 8
-// consecutive slots and is written without a wrap test.
+// positions from 16j+16-Ee on.
 inline int ring_slots(int Ee) {
     const int H0 = (kBlock + kCols - 1 + Ee) / kHalf;
     const int a = 2 * Ee + kBlock + kCols;
     const int b = kHalf * (H0 + 1) + Ee;
-    const int r = a > b ? a : b;
-    return (r + 7) / 8 * 8;
+    return a > b ? a : b;
 }
-// LDS of one wavefront: the pattern ring (+ mirror); the per-position masks
-// of the iteration's positions lo .. lo+kBlock+kCols+Ee-1; the bit planes of
-// the 32 lengths per lane (+ valid plane).  Lanes l and l+32 hold the same
-// pairs, so masks and length planes are stored once per pair lane.
+// The same rounded up to a multiple of 8: each half of a word (8 positions
+// starting at a multiple of 8) then lands in 8 consecutive slots and is
+// written in paired LDS stores without a wrap test.  A launch takes it when
+// its CUs still hold as many wavefronts (the kernel handles either size).
+inline int ring_slots_aligned(int Ee) { return (ring_slots(Ee) + 7) / 8 * 8; }
+// LDS of one wavefront with a ring of R slots: the ring (+ mirror); the
+// per-position masks of the iteration's positions lo .. lo+kBlock+kCols+Ee-1;
+// the bit planes of the 32 lengths per lane (+ valid plane).  Lanes l and
+// l+32 hold the same pairs, so masks and length planes are stored once per
+// pair lane.
 __host__ __device__ inline int mask_slots(int Ee) { return kBlock + kCols + Ee; }
 // two-length form: pattern-position masks cover lo - Ee .. lo + 18 + Ee
 __host__ __device__ inline int pattern_mask_slots(int Ee) { return kBlock + kCols + 2 * Ee; }
-inline size_t plain_lds_wave_bytes(int Ee) {
-    return (size_t)(ring_slots(Ee) + kMirror) * kRingStride * 8 + (size_t)mask_slots(Ee) * kPairLanes * 4 +
+inline size_t plain_lds_wave_bytes(int Ee, int R) {
+    return (size_t)(R + kMirror) * kRingStride * 8 + (size_t)mask_slots(Ee) * kPairLanes * 4 +
            (size_t)(kLenBits + 1) * kPairLanes * 4;
 }
 
 // LDS of one wavefront in the two-length form: ring, text masks of the 19
 // text columns, pattern masks, and len_bits bit planes of both lengths.
-inline size_t local_lds_wave_bytes(int Ee, int len_bits) {
-    return (size_t)(ring_slots(Ee) + kMirror) * kRingStride * 8 + (size_t)(kBlock + kCols) * kPairLanes * 4 +
+inline size_t local_lds_wave_bytes(int Ee, int len_bits, int R) {
+    return (size_t)(R + kMirror) * kRingStride * 8 + (size_t)(kBlock + kCols) * kPairLanes * 4 +
            (size_t)pattern_mask_slots(Ee) * kPairLanes * 4 + (size_t)(2 * len_bits) * kPairLanes * 4;
 }
 

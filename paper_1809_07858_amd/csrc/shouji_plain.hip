@@ -681,7 +681,16 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     };
     auto pass_finish = [&](int pw, int limit, uint32_t (&raw)[32]) {
         transpose32(raw);
-        if (half == 0 && pw < limit) {
+        if (half == 0 && pw < limit && (R & 7) != 0) {
+            int slot = (pw * kHalf) % R;
+#pragma unroll
+            for (int u = 0; u < kHalf; u++) {
+                const uint2 v = make_uint2(raw[2 * u], raw[2 * u + 1]);
+                ring[slot * kRingStride + pl] = v;
+                if (slot < kMirror) ring[(slot + R) * kRingStride + pl] = v;
+                slot = slot + 1 == R ? 0 : slot + 1;
+            }
+        } else if (half == 0 && pw < limit) {
             // R is a multiple of 8: each half word goes to 8 consecutive
             // slots (paired writes), the slots below kMirror also past R
 #pragma unroll
