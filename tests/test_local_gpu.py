@@ -57,8 +57,11 @@ def _run(sj, P, T, LP, LT, E, mode, max_len):
 
 
 @pytest.mark.parametrize("mode", [0, 1, 2, 3])
-@pytest.mark.parametrize("E", [0, 3, 8])
+@pytest.mark.parametrize("E", [0, 3, 5, 8])
 def test_modes_vs_oracle(sj, mode, E):
+    # E = 5 with 8 length bits (max_len 200) keeps the minimal pattern ring
+    # (its slots not a multiple of 8: words written slot by slot), the other
+    # cases the 8-aligned one
     max_len = 200
     P, T, LP, LT, _ = _embedded(6000, 60, 160, max_len, seed=500 + E)
     print("local form mode=%d E=%d n=%d" % (mode, E, len(LP)), flush=True)
