@@ -239,9 +239,13 @@ void run_copies(const std::vector<CopyJob> &jobs, int threads) {
 
 // A part whose request buffers are pinned and whose reads are packed or in
 // rows of the server's width moves by DMA straight between the request and
-// the device.
-bool direct_part(const shouji_request &r, int nw) {
-    return (r.flags & SHOUJI_REQUEST_PINNED) && ((r.flags & SHOUJI_REQUEST_PACKED) || r.words_per_read == nw);
+// the device, unless it is small: each direct part costs its own copies (four
+// in, two out), while consecutive staged parts share theirs.
+constexpr int64_t kDirectMinPairs = 2048;
+bool direct_part(const Part &pt, int nw) {
+    const shouji_request &r = pt.r->req;
+    return pt.count >= kDirectMinPairs && (r.flags & SHOUJI_REQUEST_PINNED) &&
+           ((r.flags & SHOUJI_REQUEST_PACKED) || r.words_per_read == nw);
 }
 
 // Enqueue one batch on the slot's stream: parts in pageable memory are first
@@ -284,7 +288,7 @@ int enqueue_batch(shouji_server *S, Slot &s) {
         const Part &pt = s.parts[i];
         const shouji_request &r = pt.r->req;
         const int64_t c = pt.count, f = pt.first;
-        if (!direct_part(r, nw)) {
+        if (!direct_part(pt, nw)) {
             uint32_t *dst = s.h_reads + wpos[i];
             if (r.flags & SHOUJI_REQUEST_PACKED) {
                 jobs.push_back(CopyJob{dst, r.reads + pt.word_first, (size_t)(wpos[i + 1] - wpos[i]) * 4});
@@ -328,7 +332,7 @@ int enqueue_batch(shouji_server *S, Slot &s) {
         const Part &pt = s.parts[i];
         const shouji_request &r = pt.r->req;
         const int64_t c = pt.count, f = pt.first;
-        if (direct_part(r, nw)) {
+        if (direct_part(pt, nw)) {
             flush_in(at, wpos[i]);
             const uint32_t *src = (r.flags & SHOUJI_REQUEST_PACKED) ? r.reads + pt.word_first : r.reads + f * nw;
             copy(s.d_reads_in + wpos[i], src, (size_t)(wpos[i + 1] - wpos[i]) * 4, hipMemcpyHostToDevice);
@@ -367,7 +371,7 @@ int enqueue_batch(shouji_server *S, Slot &s) {
         for (const Part &pt : s.parts) {
             const shouji_request &r = pt.r->req;
             const int64_t c = pt.count, f = pt.first;
-            if (direct_part(r, nw)) {
+            if (direct_part(pt, nw)) {
                 flush_out(at);
                 copy(r.out_accept + f, s.d_acc + at, (size_t)c, hipMemcpyDeviceToHost);
                 if (r.out_popcount) copy(r.out_popcount + f, s.d_pc + at, (size_t)c * 2, hipMemcpyDeviceToHost);
@@ -440,7 +444,7 @@ void reaper_loop(shouji_server *S) {
         int64_t at = 0;
         for (const Part &pt : s.parts) {
             shouji_request &r = pt.r->req;
-            if (!direct_part(r, S->nw)) {
+            if (!direct_part(pt, S->nw)) {
                 memcpy(r.out_accept + pt.first, s.h_acc + at, (size_t)pt.count);
                 if (r.out_popcount) memcpy(r.out_popcount + pt.first, s.h_pc + at, (size_t)pt.count * 2);
             }

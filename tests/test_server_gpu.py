@@ -272,3 +272,35 @@ def test_packed_reads_with_invalid_and_empty_lengths(sj, work):
     good = ~bad
     ea, ep = oracle.shouji_batch(p.P[lo:hi][good], p.T[lo:hi][good], lens[good], E_per_pair=p.E[lo:hi][good])
     assert np.array_equal(acc[good], ea) and np.array_equal(pc[good], ep)
+
+
+def test_many_tiny_requests_of_every_format(sj, work):
+    # hundreds of 1..40-pair requests per batch, in every request format:
+    # small pinned parts are staged like pageable ones, large ones go by DMA
+    p = work["p"]
+    words, wo = sj.pack_reads_packed(p.P, p.lengths, MAX_LEN)
+    rng = np.random.default_rng(4100)
+    sizes = [int(s) for s in rng.integers(1, 41, 600)] + [2048, 5000]
+    cuts = _cuts(p.n, sizes)[:len(sizes)]
+    keep = []
+    print("server: %d tiny requests, batch 4096" % len(cuts), flush=True)
+    with _server(sj, work, slots=3, max_batch_pairs=4096) as srv:
+        tickets = []
+        for i, (lo, hi) in enumerate(cuts):
+            kind = i % 4
+            if kind == 0:
+                t = srv.submit(words[wo[lo]:wo[hi]], work["off"][lo:hi], p.lengths[lo:hi], p.E[lo:hi],
+                               packed=True)
+            elif kind == 2:
+                t = _submit(srv, work, lo, hi)
+            else:
+                r = words[wo[lo]:wo[hi]] if kind == 1 else work["reads"][lo:hi]
+                bufs = [_pinned(a) for a in (r, work["off"][lo:hi], p.lengths[lo:hi], p.E[lo:hi],
+                                             np.zeros(hi - lo, np.uint8), np.zeros(hi - lo, np.int16))]
+                keep.append(bufs)
+                r, o, L, E, a, c = [v for _, v in bufs]
+                t = srv.submit(r, o, L, E, pinned=True, packed=kind == 1, out_accept=a, out_popcount=c)
+            tickets.append(t)
+        for (lo, hi), t in zip(cuts, tickets):
+            acc, pc, _ = srv.wait(t)
+            _expect(work, lo, hi, acc, pc)
