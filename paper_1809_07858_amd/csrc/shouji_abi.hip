@@ -105,19 +105,38 @@ extern "C" int shouji_filter(const uint32_t *reads, const uint32_t *refs, const 
     prm.out_popcount = out_popcount;
     prm.n = n_pairs;
     // Workgroups of 4 wavefronts (1024 pairs each); LDS and registers let a CU
-    // hold two of them, i.e. two wavefronts per SIMD.
-    prm.R = plain_ring(Ee, shouji::kWavesPerGroup);
-    const size_t wave_lds = shouji::plain_lds_wave_bytes(Ee, prm.R);
+    // hold two of them, i.e. two wavefronts per SIMD.  Without a length array
+    // every pair has max_len bases: the boundary masks follow from the
+    // positions, and a wavefront's LDS holds the pattern ring only (two
+    // wavefronts per SIMD up to E = 22 instead of 13).
+    prm.ring_only = lengths == nullptr ? 1 : 0;
+    if (prm.ring_only) {
+        const int a = shouji::ring_slots_aligned(Ee), m = shouji::ring_slots(Ee);
+        prm.R = waves_per_cu(shouji::ring_lds_wave_bytes(a), shouji::kWavesPerGroup) >=
+                        waves_per_cu(shouji::ring_lds_wave_bytes(m), shouji::kWavesPerGroup)
+                    ? a
+                    : m;
+    } else {
+        prm.R = plain_ring(Ee, shouji::kWavesPerGroup);
+    }
+    const size_t wave_lds =
+        prm.ring_only ? shouji::ring_lds_wave_bytes(prm.R) : shouji::plain_lds_wave_bytes(Ee, prm.R);
     const size_t lds = wave_lds * shouji::kWavesPerGroup;
     if (lds > shouji::kLdsPerCU) return fail(SHOUJI_ERR_RANGE, "E %d needs more LDS than one CU holds", E);
     const int64_t waves = (n_pairs + shouji::kPairsPerWave - 1) / shouji::kPairsPerWave;
     const int64_t grid = (waves + shouji::kWavesPerGroup - 1) / shouji::kWavesPerGroup;
     if (grid > 0x7fffffff) return fail(SHOUJI_ERR_ARG, "n_pairs too large");
     prm.lds_wave_bytes = (int32_t)wave_lds;
-    static size_t lds_limit = 0;
-    if (int rc = raise_lds_limit((const void *)shouji::shouji_plain_kernel, lds_limit, lds)) return rc;
-    hipLaunchKernelGGL(shouji::shouji_plain_kernel, dim3((unsigned)grid),
-                       dim3(shouji::kWave * shouji::kWavesPerGroup), lds, (hipStream_t)stream, prm);
+    static size_t lds_limit = 0, lds_limit_ring = 0;
+    const void *kernel = prm.ring_only ? (const void *)shouji::shouji_plain_ring_kernel
+                                       : (const void *)shouji::shouji_plain_kernel;
+    if (int rc = raise_lds_limit(kernel, prm.ring_only ? lds_limit_ring : lds_limit, lds)) return rc;
+    if (prm.ring_only)
+        hipLaunchKernelGGL(shouji::shouji_plain_ring_kernel, dim3((unsigned)grid),
+                           dim3(shouji::kWave * shouji::kWavesPerGroup), lds, (hipStream_t)stream, prm);
+    else
+        hipLaunchKernelGGL(shouji::shouji_plain_kernel, dim3((unsigned)grid),
+                           dim3(shouji::kWave * shouji::kWavesPerGroup), lds, (hipStream_t)stream, prm);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(SHOUJI_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return ok();

@@ -30,6 +30,7 @@ struct PlainParams {
     int16_t *out_popcount;
     int64_t n;
     int32_t lds_wave_bytes;  // LDS bytes owned by one wavefront
+    int32_t ring_only;       // no length array: LDS holds the pattern ring only
 };
 
 // Two-length form: reads and references of different lengths, with a
@@ -199,6 +200,8 @@ inline int ring_slots_aligned(int Ee) { return (ring_slots(Ee) + 7) / 8 * 8; }
 __host__ __device__ inline int mask_slots(int Ee) { return kBlock + kCols + Ee; }
 // two-length form: pattern-position masks cover lo - Ee .. lo + 18 + Ee
 __host__ __device__ inline int pattern_mask_slots(int Ee) { return kBlock + kCols + 2 * Ee; }
+// LDS of one wavefront of a plain launch without lengths: the ring only.
+inline size_t ring_lds_wave_bytes(int R) { return (size_t)(R + kMirror) * kRingStride * 8; }
 inline size_t plain_lds_wave_bytes(int Ee, int R) {
     return (size_t)(R + kMirror) * kRingStride * 8 + (size_t)mask_slots(Ee) * kPairLanes * 4 +
            (size_t)(kLenBits + 1) * kPairLanes * 4;
@@ -212,6 +215,7 @@ inline size_t local_lds_wave_bytes(int Ee, int len_bits, int R) {
 }
 
 __global__ void shouji_plain_kernel(PlainParams prm);
+__global__ void shouji_plain_ring_kernel(PlainParams prm);
 __global__ void shouji_local_kernel(LocalParams prm);
 __global__ void shouji_tiles_kernel(TilesParams prm);
 __global__ void fill_i32_kernel(int32_t *p, int64_t n, int32_t v);

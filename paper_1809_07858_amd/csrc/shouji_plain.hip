@@ -151,12 +151,15 @@ struct Winner {
 // positions are kRingStride entries apart (all entries are loaded before the
 // first use).  `masked` (uniform): some cell may lie outside the map.  With
 // one length per pair, nv[s] masks position i0+s; with two (TWO), nv[s]
-// masks text position i0+s and nvp[s] pattern position i0-Ee+s.
-template <bool FIRST, int NB, bool TWO>
+// masks text position i0+s and nvp[s] pattern position i0-Ee+s.  REGM: every
+// pair has length reg_mlen, and the masks are computed from the positions
+// instead of read from nv.
+template <bool FIRST, int NB, bool TWO, bool REGM>
 __device__ __forceinline__ void candidate(Winner<NB> &W, const uint2 (&pv)[NB + 3],
                                           const uint32_t *__restrict__ nv, const uint32_t *__restrict__ nvp,
                                           int Ee, int i0, int d, bool masked,
-                                          const uint32_t (&tl)[NB + 3], const uint32_t (&th)[NB + 3]) {
+                                          const uint32_t (&tl)[NB + 3], const uint32_t (&th)[NB + 3],
+                                          int reg_mlen) {
     constexpr int C = NB + 3;
     uint32_t cell[C];
 #pragma unroll
@@ -170,6 +173,14 @@ __device__ __forceinline__ void candidate(Winner<NB> &W, const uint2 (&pv)[NB + 
         const uint32_t *np = nvp + (Ee - d) * kPairLanes;
 #pragma unroll
         for (int t = 0; t < C; t++) cell[t] |= nv[t * kPairLanes] | np[t * kPairLanes];
+    } else if (REGM && masked) {
+        // d < 0: the pattern index i0+t-d runs out first; d >= 0: the text
+        // column i0+t, and pattern indices below 0
+        const int first = d < 0 ? i0 - d : i0;
+#pragma unroll
+        for (int t = 0; t < C; t++) {
+            if (first + t >= reg_mlen || i0 + t - d < 0) cell[t] = ~0u;
+        }
     } else if (masked) {
         if (d < 0) {
             // pattern index j - d > j: the pattern side runs out first
@@ -243,13 +254,13 @@ __device__ __forceinline__ void ring_load(const uint2 *__restrict__ rb, int slot
 
 // Window search of one block of NB windows at i0 (sb = ring slot of i0): the
 // winner of every window over all 2E+1 diagonals.
-template <int NB, bool TWO, bool MASKS = true>
+template <int NB, bool TWO, bool MASKS = true, bool REGM = false>
 __device__ __forceinline__ void block_winners(Winner<NB> &W, const uint2 *__restrict__ ring,
                                               const uint32_t *__restrict__ nv,
                                               const uint32_t *__restrict__ nvp, int pl, int i0,
                                               int sb, int Ee, int R, int lo, int hi_col, int m_min,
                                               const uint32_t (&tl)[NB + 3],
-                                              const uint32_t (&th)[NB + 3]) {
+                                              const uint32_t (&th)[NB + 3], int reg_mlen = -1) {
     // evaluation order (Algorithm 1): d = +1, -1, +2, -2, ..., +E, -E, then
     // the main diagonal (d > 0: text index exceeds pattern index by d, the
     // diagonal Algorithm 1 calls lower j, drawn as upper in Fig. 6); diagonal
@@ -263,29 +274,29 @@ __device__ __forceinline__ void block_winners(Winner<NB> &W, const uint2 *__rest
     auto mk = [&](int d) { return MASKS && needs_mask(d, lo, hi_col, m_min); };
     if (Ee == 0) {
         ring_load<C>(rb, sb, A);
-        candidate<true, NB, TWO>(W, A, nv, nvp, Ee, i0, 0, mk(0), tl, th);
+        candidate<true, NB, TWO, REGM>(W, A, nv, nvp, Ee, i0, 0, mk(0), tl, th, reg_mlen);
         return;
     }
     int sP = sb == 0 ? R - 1 : sb - 1;   // slot of d = +k
     int sN = sb + 1 == R ? 0 : sb + 1;   // slot of d = -k
     ring_load<C>(rb, sP, A);
     ring_load<C>(rb, sN, B);
-    candidate<true, NB, TWO>(W, A, nv, nvp, Ee, i0, 1, mk(1), tl, th);
+    candidate<true, NB, TWO, REGM>(W, A, nv, nvp, Ee, i0, 1, mk(1), tl, th, reg_mlen);
     // A <- the next d > 0 (or the main diagonal when E = 1)
     sP = sP == 0 ? R - 1 : sP - 1;
     ring_load<C>(rb, Ee >= 2 ? sP : sb, A);
-    candidate<false, NB, TWO>(W, B, nv, nvp, Ee, i0, -1, mk(-1), tl, th);
+    candidate<false, NB, TWO, REGM>(W, B, nv, nvp, Ee, i0, -1, mk(-1), tl, th, reg_mlen);
     for (int k = 2; k <= Ee; k++) {
         // A holds d = +k; B <- d = -k
         sN = sN + 1 == R ? 0 : sN + 1;
         ring_load<C>(rb, sN, B);
-        candidate<false, NB, TWO>(W, A, nv, nvp, Ee, i0, k, mk(k), tl, th);
+        candidate<false, NB, TWO, REGM>(W, A, nv, nvp, Ee, i0, k, mk(k), tl, th, reg_mlen);
         // A <- d = +(k+1), or the main diagonal after the last k
         sP = sP == 0 ? R - 1 : sP - 1;
         ring_load<C>(rb, k < Ee ? sP : sb, A);
-        candidate<false, NB, TWO>(W, B, nv, nvp, Ee, i0, -k, mk(-k), tl, th);
+        candidate<false, NB, TWO, REGM>(W, B, nv, nvp, Ee, i0, -k, mk(-k), tl, th, reg_mlen);
     }
-    candidate<false, NB, TWO>(W, A, nv, nvp, Ee, i0, 0, mk(0), tl, th);
+    candidate<false, NB, TWO, REGM>(W, A, nv, nvp, Ee, i0, 0, mk(0), tl, th, reg_mlen);
 }
 
 // Where the zeros of the final bit-vector lie, for the local and glocal
@@ -454,7 +465,7 @@ __device__ __forceinline__ uint32_t from_half1(uint32_t v) {
 // has the reference's columns, cells outside the read are mismatches, and
 // the ones before the first / after the last zero of the bit-vector can be
 // left out of the count (Sec. 2.2.3).
-template <bool TWO>
+template <bool TWO, bool RO = false>
 __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, int R, int lane) {
     const int half = lane >> 5;
     const int pl = lane & (kPairLanes - 1);
@@ -583,6 +594,10 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     const int m_min = lmax < 0 ? 0 : (TWO ? min(lmin, rmin) : lmin);
     const int m_words = lmax < 0 ? 0 : (TWO ? max(lmax, rmax) : lmax);
     const bool uniform = !TWO && (m_min == m_max);
+    // RO: the wavefront's LDS holds the ring only (every pair has max_len
+    // bases, so the lengths are uniform): masks from the positions
+    static_assert(!(TWO && RO), "the two-length form keeps its masks in LDS");
+    const int reg_mlen = RO ? m_max : -1;
     if (!uniform) {
         // bit planes of the lengths, kept in LDS (read by the boundary masks
         // and the output only); with one length for all valid pairs none are
@@ -773,13 +788,15 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
             if ((Ee > lo) || (hi_col + Ee >= m_min)) {
                 if constexpr (TWO)
                     fill_masks2(i0, nvh, nvph, kCols);
-                else
+                else if (!RO)
                     fill_masks(i0, nvh, kCols + Ee);
-                block_winners<kBlock, TWO>(W, ring, nvh, nvph, pl, i0, sb, Ee, R, lo, hi_col, m_min, tl, th);
+                block_winners<kBlock, TWO, true, RO>(W, ring, nvh, nvph, pl, i0, sb, Ee, R, lo, hi_col, m_min,
+                                                     tl, th, reg_mlen);
             } else {
                 // interior: every pattern index i0+t-d lies in [0, m_min) and every
                 // text column below m_min, so no candidate needs a mask
-                block_winners<kBlock, TWO, false>(W, ring, nvh, nvph, pl, i0, sb, Ee, R, lo, hi_col, m_min, tl, th);
+                block_winners<kBlock, TWO, false, RO>(W, ring, nvh, nvph, pl, i0, sb, Ee, R, lo, hi_col, m_min,
+                                                      tl, th);
             }
         }
         // serial bit-vector update: block 2j on the low half, 2j+1 on the
@@ -819,10 +836,11 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
         uint32_t *nvps = nvp + NB * half * kPairLanes + pl;
         if constexpr (TWO)
             fill_masks2(i0, nvs, nvps, C);
-        else
+        else if (!RO)
             fill_masks(i0, nvs, C + Ee);
         Winner<NB> W;
-        block_winners<NB, TWO>(W, ring, nvs, nvps, pl, i0, i0 % R, Ee, R, lo, lo + NB + C - 1, m_min, tl, th);
+        block_winners<NB, TWO, true, RO>(W, ring, nvs, nvps, pl, i0, i0 % R, Ee, R, lo, lo + NB + C - 1, m_min,
+                                         tl, th, reg_mlen);
         uint32_t o[NB];
         if (half == 0) block_fsm<NB>(F, W, o);
         F.s0 = from_half0(F.s0); F.s1 = from_half0(F.s1); F.s2 = from_half0(F.s2);
@@ -956,8 +974,8 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     }
 }
 
-__global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_plain_kernel(PlainParams prm) {
-    extern __shared__ uint32_t lds_all[];
+template <bool RO>
+__device__ __forceinline__ void plain_wave(const PlainParams &prm, uint32_t *lds_all) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
     GroupJob J;
@@ -978,7 +996,20 @@ __global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_plain_kernel
     J.base = ((int64_t)blockIdx.x * kWavesPerGroup + wave) * kPairsPerWave;
     J.n = prm.n;
     if (J.base >= J.n) return;
-    filter_group<false>(J, lds_all + (size_t)wave * (prm.lds_wave_bytes / 4), prm.R, lane);
+    filter_group<false, RO>(J, lds_all + (size_t)wave * (prm.lds_wave_bytes / 4), prm.R, lane);
+}
+
+__global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_plain_kernel(PlainParams prm) {
+    extern __shared__ uint32_t lds_all[];
+    plain_wave<false>(prm, lds_all);
+}
+
+// The same without a length array (every pair has max_len bases): the
+// boundary masks follow from the positions and the wavefront's LDS holds the
+// pattern ring only.
+__global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_plain_ring_kernel(PlainParams prm) {
+    extern __shared__ uint32_t lds_all[];
+    plain_wave<true>(prm, lds_all);
 }
 
 // Two-length form: reads and references of different lengths, local /

@@ -95,6 +95,25 @@ def test_no_lengths_and_padded_ld(sj):
     assert np.array_equal(ga, ea) and np.array_equal(gp, ep)
 
 
+@pytest.mark.parametrize("m,E", [(250, 13), (250, 14), (250, 15), (250, 20), (250, 22), (250, 23), (250, 25),
+                                 (100, 0), (100, 5), (100, 10), (37, 31)])
+def test_no_lengths_every_threshold(sj, m, E):
+    # without a length array the kernel keeps only the pattern ring in LDS
+    # and computes the boundary masks from the positions (two wavefronts per
+    # SIMD up to E = 22); ragged pair counts leave a partial last wavefront
+    p = syninput.generate(2_500 + 3 * E + m, m, E=min(max(E, 1), 25), seed=9000 + 31 * m + E,
+                          p_repeat=0.3 if m == 250 else 0.0)
+    print("case no lengths n=%d m=%d E=%d" % (p.n, m, E), flush=True)
+    ga, gp = _run(sj, p, E, m, with_lengths=False)
+    ea, ep = oracle.shouji_batch(p.P, p.T, p.lengths, E=E)
+    bad = np.nonzero((ga != ea) | (gp != ep))[0]
+    assert bad.size == 0, "mismatches at %s (gpu %s/%s oracle %s/%s)" % (
+        bad[:8], ga[bad[:8]], gp[bad[:8]], ea[bad[:8]], ep[bad[:8]])
+    # the same pairs with their (all equal) lengths passed: the other kernel
+    la, lp = _run(sj, p, E, m, with_lengths=True)
+    assert np.array_equal(la, ga) and np.array_equal(lp, gp)
+
+
 def test_E_clamped_and_large(sj):
     p = syninput.generate(2_100, 20, E=3, seed=4)
     _check(sj, p, 19, 20)
