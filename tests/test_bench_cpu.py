@@ -1,0 +1,66 @@
+"""CPU checks of bench.py's measurement model: the algorithmic work and bytes
+per pair it divides by, the peak it compares against, the source hash that
+ties counter summaries to the kernel, and the one-GPU rule."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_gate_count_model():
+    # m=100, E=5: 100*11*8 + 100*10*11 + 100*12.25 = 20,025 gates per 32
+    # pairs, plus two sequences of 7 words at 256 ops per 32 pairs
+    assert bench.algorithmic_lane_ops_per_pair(100, 5) == pytest.approx((8800 + 11000 + 1225 + 2 * 7 * 256) / 32)
+    assert bench.algorithmic_lane_ops_per_pair(100, 5) == pytest.approx(769.03125)
+    # E=0: one candidate, no comparisons
+    assert bench.algorithmic_lane_ops_per_pair(100, 0) == pytest.approx((800 + 1225 + 3584) / 32)
+    # grows linearly in E
+    d1 = bench.algorithmic_lane_ops_per_pair(250, 11) - bench.algorithmic_lane_ops_per_pair(250, 10)
+    d2 = bench.algorithmic_lane_ops_per_pair(250, 21) - bench.algorithmic_lane_ops_per_pair(250, 20)
+    assert d1 == pytest.approx(d2) == pytest.approx(250 * (16 + 22) / 32)
+
+
+def test_bytes_and_peak():
+    assert bench.algorithmic_bytes_per_pair(100) == 57
+    assert bench.VALU_PEAK_TOPS == pytest.approx(78.6432)
+    assert bench.HBM_PEAK_GBS == 8000.0
+
+
+def test_source_hash_ignores_comments_and_layout():
+    a = "int f(int x) { // one\n  return x + 1; /* two */ }\n"
+    b = "int f(int x) {\n\n return x + 1;   }"
+    assert bench.strip_comments(a) == bench.strip_comments(b)
+    assert bench.strip_comments("a /* x */ b") != bench.strip_comments("ab")
+    h = bench.kernel_source_hash()
+    assert len(h) == 16 and h == bench.kernel_source_hash()
+
+
+def test_committed_traffic_matches_its_summary():
+    # reported only for the source the counters were taken on, and then
+    # exactly the summary's figure
+    path = os.path.join(ROOT, "profiles", "shouji_plain_m100_E5_n2000000_hbm_traffic.md")
+    assert os.path.exists(path)
+    t = bench.committed_traffic("m100_E5_n2000000")
+    vals = {}
+    for line in open(path):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals["kernel_source_sha256"] == bench.kernel_source_hash():
+        assert t == float(vals["hbm_bytes_per_launch"])
+    else:
+        assert t is None
+    assert bench.committed_traffic("no_such_workload") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
