@@ -71,7 +71,9 @@ typedef enum {
  *   Step 3: popcount = ones of S over [0, m); accept = popcount <= E.
  *
  *   reads, refs   word-major packed sequences (see above), ld words apart.
- *   lengths       n_pairs lengths m_p, or NULL: every pair has max_len bases.
+ *   lengths       n_pairs lengths m_p, or NULL: every pair has max_len bases
+ *                 (the faster call for equal lengths: its kernel keeps only the
+ *                 pattern ring in LDS, two wavefronts per SIMD up to E = 22).
  *   E             edit threshold, >= 0.  Internally clamped to max_len - 1
  *                 (diagonals beyond the map are all ones); after clamping it
  *                 must be <= SHOUJI_MAX_E, else SHOUJI_ERR_RANGE.

@@ -40,7 +40,9 @@
 //
 // Cells outside the m x m map (pattern or text index outside [0, m)) are
 // mismatches, in the interior blocks no such cell exists and no mask is
-// applied; the boundary blocks OR in per-pair masks kept in LDS.
+// applied; the boundary blocks OR in per-pair masks kept in LDS, or, when
+// every pair has the same length (a call without a length array), masks
+// computed from the positions, so that LDS holds the pattern ring only.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
