@@ -506,6 +506,14 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     // no per-pair lane mask stays live into the window loop.  All loads are
     // issued first: the lengths, then text / pattern word 0 (which does not
     // depend on them).
+    const int nwords = (J.max_len + kHalf - 1) / kHalf;
+    uint32_t raw0[32];
+    if (nwords > 0) {
+        load_word(seq + base, full, left, pl, raw0);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 32; k++) raw0[k] = 0u;
+    }
     const int32_t *lp = J.lengths ? J.lengths + base : nullptr;
     const int32_t *tp = TWO ? J.ref_lengths + base : nullptr;
     int mv[32], mtv[TWO ? 32 : 1];
@@ -523,14 +531,9 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
             if constexpr (TWO) mtv[k] = tp[qi];
         }
     }
-    const int nwords = (J.max_len + kHalf - 1) / kHalf;
-    uint32_t raw0[32];
-    if (nwords > 0) {
-        load_word(seq + base, full, left, pl, raw0);
-    } else {
-#pragma unroll
-        for (int k = 0; k < 32; k++) raw0[k] = 0u;
-    }
+    // word 0 transposed while the lengths are still arriving (its loads are
+    // issued first and complete first)
+    transpose32(raw0);
     // Fast path (one length per pair, a full wavefront, every length in
     // range -- the usual case): the lengths are the planes' source as they
     // are, every pair is valid, and min / max come from the raw values.
@@ -696,8 +699,7 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
         const uint32_t *row = seq + (int64_t)w * J.ld + base;
         load_word(row, full, left, pl, raw);
     };
-    auto pass_finish = [&](int pw, int limit, uint32_t (&raw)[32]) {
-        transpose32(raw);
+    auto ring_write = [&](int pw, int limit, uint32_t (&raw)[32]) {
         if (half == 0 && pw < limit && (R & 7) != 0) {
             int slot = (pw * kHalf) % R;
 #pragma unroll
@@ -725,6 +727,10 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
                 }
             }
         }
+    };
+    auto pass_finish = [&](int pw, int limit, uint32_t (&raw)[32]) {
+        transpose32(raw);
+        ring_write(pw, limit, raw);
     };
     auto pass = [&](int pw, int tw, uint32_t (&raw)[32]) {
         pass_load(pw, tw, nhalves, raw);
@@ -762,7 +768,7 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     if (nblocks > 0) {
         // pattern words 0..H0 into the ring; text words 0 and 1
         uint32_t raw1[32];
-        pass_finish(0, nhalves, raw0);
+        ring_write(0, nhalves, raw0);
         start_text(TA, raw0);
         if (nhalves > 1) {       // else word 1 holds no position of any pair
             pass(1, 1, raw1);
