@@ -18,7 +18,10 @@
 //
 // One pair per lane: the recursion is a stack of pending parts in LDS (the
 // right part pushed last, so that its whole subtree is solved before the
-// left part).  A diagonal's run search walks 16 text positions per step: the
+// left part), E+1 entries per lane: every run taken pops one part and pushes
+// at most two, and nothing is pushed after the (E+1)-th run, so at most E+1
+// parts are ever pending; sized per launch, it leaves LDS for more
+// wavefronts at small E.  A diagonal's run search walks 16 text positions per step: the
 // reference word, the read's two words around the diagonal's offset joined
 // with v_alignbit, one XOR and a fold give the 16 match bits, and the
 // longest run of matches in the word is found with doubling masks and a
@@ -43,7 +46,7 @@ __device__ __forceinline__ uint32_t field_mask(int n) {
 }  // namespace
 
 __global__ __launch_bounds__(kMagnetBlock) void magnet_kernel(MagnetParams prm) {
-    __shared__ uint32_t stack[kMagnetStack * kMagnetBlock];
+    extern __shared__ uint32_t stack[];                       // (E+1) entries per lane
     const int tid = threadIdx.x;
     const int64_t p = (int64_t)blockIdx.x * kMagnetBlock + tid;
     if (p >= prm.n) return;
@@ -175,8 +178,8 @@ __global__ __launch_bounds__(kMagnetBlock) void magnet_kernel(MagnetParams prm) 
         zeros += len;
         if (++taken == E + 1) break;                         // E+1 runs taken
         // left part [lo, s-2], then right part [s+len+1, hi] on top
-        if (lo <= s - 2 && sp < kMagnetStack) stk[(sp++) * kMagnetBlock] = (uint32_t)lo | ((uint32_t)(s - 2) << 16);
-        if (s + len + 1 <= hi && sp < kMagnetStack)
+        if (lo <= s - 2 && sp <= E) stk[(sp++) * kMagnetBlock] = (uint32_t)lo | ((uint32_t)(s - 2) << 16);
+        if (s + len + 1 <= hi && sp <= E)
             stk[(sp++) * kMagnetBlock] = (uint32_t)(s + len + 1) | ((uint32_t)hi << 16);
     }
     const int ones = m - zeros;
@@ -218,7 +221,10 @@ extern "C" int shouji_filter_magnet(const uint32_t *reads, const uint32_t *refs,
     prm.out_popcount = out_popcount;
     prm.n = n_pairs;
     const unsigned grid = (unsigned)((n_pairs + shouji::kMagnetBlock - 1) / shouji::kMagnetBlock);
-    hipLaunchKernelGGL(shouji::magnet_kernel, dim3(grid), dim3(shouji::kMagnetBlock), 0, (hipStream_t)stream, prm);
+    // a pair holds at most E+1 pending parts (each run taken pops one and
+    // pushes at most two; after E+1 runs nothing is pushed)
+    const size_t lds = (size_t)(prm.E + 1) * shouji::kMagnetBlock * 4;
+    hipLaunchKernelGGL(shouji::magnet_kernel, dim3(grid), dim3(shouji::kMagnetBlock), lds, (hipStream_t)stream, prm);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return set_error(SHOUJI_ERR_DEVICE, "shouji_filter_magnet: launch failed: %s", hipGetErrorString(e));

@@ -24,7 +24,6 @@ struct WindowParams {
 
 // MAGNET filter (one pair per lane, LDS stack of pending subproblems).
 constexpr int kMagnetBlock = 256;
-constexpr int kMagnetStack = 32;     // entries per lane; at most min(E+1, 17) are ever live
 struct MagnetParams {
     const uint32_t *reads;
     const uint32_t *refs;
