@@ -48,6 +48,14 @@ def test_mixed_lengths_per_pair_E(sj):
     _check(sj, p, 300)
 
 
+def test_longest_lengths_and_largest_thresholds(sj):
+    # lengths 500..1024 (up to 64 words) with E_p up to 31: every bin of the
+    # E > 13 class and the largest length buckets
+    p = syninput.generate(3_000, 500, 1024, E=None, r_max=0.031, seed=3100)
+    assert p.E.max() >= 25 and p.lengths.max() > 1000
+    _check(sj, p, 1024)
+
+
 @pytest.mark.parametrize("config", [(4, 2), (8, 4), (16, 1), (32, 4)])
 def test_every_config_exact(sj, config):
     p = syninput.generate(20_000, 30, 200, E=None, r_max=0.15, seed=31)

@@ -96,12 +96,13 @@ def test_no_lengths_and_padded_ld(sj):
 
 
 @pytest.mark.parametrize("m,E", [(250, 13), (250, 14), (250, 15), (250, 20), (250, 22), (250, 23), (250, 25),
-                                 (100, 0), (100, 5), (100, 10), (37, 31)])
+                                 (100, 0), (100, 5), (100, 10), (37, 31), (1024, 12)])
 def test_no_lengths_every_threshold(sj, m, E):
     # without a length array the kernel keeps only the pattern ring in LDS
     # and computes the boundary masks from the positions (two wavefronts per
     # SIMD up to E = 22); ragged pair counts leave a partial last wavefront
-    p = syninput.generate(2_500 + 3 * E + m, m, E=min(max(E, 1), 25), seed=9000 + 31 * m + E,
+    n = 2_500 + 3 * E + m if m < 1024 else 1_100
+    p = syninput.generate(n, m, E=min(max(E, 1), 25), seed=9000 + 31 * m + E,
                           p_repeat=0.3 if m == 250 else 0.0)
     print("case no lengths n=%d m=%d E=%d" % (p.n, m, E), flush=True)
     ga, gp = _run(sj, p, E, m, with_lengths=False)
