@@ -304,3 +304,21 @@ def test_many_tiny_requests_of_every_format(sj, work):
         for (lo, hi), t in zip(cuts, tickets):
             acc, pc, _ = srv.wait(t)
             _expect(work, lo, hi, acc, pc)
+
+
+def test_longest_reads(sj):
+    # max_len 1024 (64-word rows), lengths 500..1024, E_p up to 31, packed and
+    # row requests in the same batches
+    p = syninput.generate(2_000, 500, 1024, E=None, r_max=0.031, seed=4200)
+    codes, off = syninput.reference_pool(p, seed=4201, base_len=1000)
+    pool = torch.from_numpy(sj.pack_pool(codes).view(np.int32)).to("cuda:0")
+    rows = sj.pack_pairs(p.P, 1024)
+    words, wo = sj.pack_reads_packed(p.P, p.lengths, 1024)
+    ea, ep = oracle.shouji_batch(p.P, p.T, p.lengths, E_per_pair=p.E)
+    with sj.Server(pool, codes.size, 1024, slots=2, max_batch_pairs=700) as srv:
+        t0 = srv.submit(words[wo[0]:wo[1000]], off[:1000], p.lengths[:1000], p.E[:1000], packed=True)
+        t1 = srv.submit(rows[1000:], off[1000:], p.lengths[1000:], p.E[1000:])
+        a0, c0, _ = srv.wait(t0)
+        a1, c1, _ = srv.wait(t1)
+    acc, pc = np.concatenate([a0, a1]), np.concatenate([c0, c1])
+    assert np.array_equal(acc, ea) and np.array_equal(pc, ep)
