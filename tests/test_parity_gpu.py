@@ -160,6 +160,26 @@ def test_config1_full_size(sj, E):
     _check(sj, p, E, 100)
 
 
+@pytest.mark.parametrize("m,E", [(100, 0), (100, 5), (100, 10), (250, 15), (250, 22)])
+def test_no_lengths_full_size_equals_lengths(sj, m, E):
+    # 2M pairs: the ring-only kernel (no length array) against the kernel with
+    # lengths, whose full-size outputs are checked against the oracle above
+    p = syninput.generate(2_000_000, m, E=E, seed=9500 + E, p_repeat=0.3 if m == 250 else 0.0)
+    print("case full size no lengths m=%d E=%d" % (m, E), flush=True)
+    d = torch.device("cuda:0")
+    reads = sj.pack_words_device(p.P, m)
+    refs = sj.pack_words_device(p.T, m)
+    lens = torch.from_numpy(p.lengths).to(d)
+    a1, p1 = sj.shouji_filter(reads, refs, lens, E, max_len=m)
+    a0, p0 = sj.shouji_filter(reads, refs, None, E, max_len=m)
+    torch.cuda.synchronize()
+    assert torch.equal(a0, a1) and torch.equal(p0, p1)
+    # and the oracle on a strided sample
+    idx = np.arange(0, p.n, 997)
+    ea, ep = oracle.shouji_batch(p.P[idx], p.T[idx], p.lengths[idx], E=E)
+    assert np.array_equal(a0.cpu().numpy()[idx], ea) and np.array_equal(p0.cpu().numpy()[idx], ep)
+
+
 @pytest.mark.parametrize("E", [0, 5, 10, 15, 20, 25])
 def test_config2_full_size_sampled(sj, E):
     # m=250, 2M pairs with tandem repeats, in one launch: a strided sample of
