@@ -504,8 +504,8 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     // Loads are never predicated (a missing pair reads the last one and is
     // then replaced by -1), and each length is materialised at once, so that
     // no per-pair lane mask stays live into the window loop.  All loads are
-    // issued first: the lengths, then text / pattern word 0 (which does not
-    // depend on them).
+    // issued first: text / pattern word 0 (which does not depend on the
+    // lengths), then the lengths.
     const int nwords = (J.max_len + kHalf - 1) / kHalf;
     uint32_t raw0[32];
     if (nwords > 0) {
@@ -699,6 +699,9 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
         const uint32_t *row = seq + (int64_t)w * J.ld + base;
         load_word(row, full, left, pl, raw);
     };
+    // The ring entries of pattern word pw (low half): slot by slot with the
+    // wrap test when R is the minimal size, or as two runs of 8 consecutive
+    // slots when R is a multiple of 8.
     auto ring_write = [&](int pw, int limit, uint32_t (&raw)[32]) {
         if (half == 0 && pw < limit && (R & 7) != 0) {
             int slot = (pw * kHalf) % R;
