@@ -282,10 +282,14 @@ extern "C" int shouji_filter_batched(const uint32_t *reads, const uint32_t *refs
     hipLaunchKernelGGL(shouji::fill_i32_kernel, dim3((L.nbins + 255) / 256), dim3(256), 0, st, counts,
                        (int64_t)L.nbins, 0);
     {
-        const int64_t blocks = (n_pairs + 255) / 256;
-        hipLaunchKernelGGL(shouji::bin_count_kernel, dim3((unsigned)(blocks < 2048 ? blocks : 2048)),
-                           dim3(256), (size_t)L.nbins * 4, st, lengths, E_per_pair, n_pairs, max_len,
-                           cfg.bin_width, L.nbins, counts);
+        const int64_t per = (int64_t)shouji::kCountThreads * 4;
+        const int64_t blocks = (n_pairs + per - 1) / per;
+        const int fit = (int)(shouji::kCountLds / ((size_t)L.nbins * 4));
+        const int copies = fit < 1 ? 1 : (fit > shouji::kCountThreads / shouji::kWave ? shouji::kCountThreads / shouji::kWave : fit);
+        hipLaunchKernelGGL(shouji::bin_count_kernel,
+                           dim3((unsigned)(blocks < shouji::kCountGroups ? blocks : shouji::kCountGroups)),
+                           dim3(shouji::kCountThreads), (size_t)L.nbins * 4 * copies, st, lengths, E_per_pair,
+                           n_pairs, max_len, cfg.bin_width, L.nbins, copies, counts);
     }
     // 2. bin offsets and tile lists
     shouji::PlanOut po;

@@ -40,22 +40,40 @@ __global__ void fill_i32_kernel(int32_t *p, int64_t n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
-__global__ __launch_bounds__(256) void bin_count_kernel(const int32_t *__restrict__ lengths,
+// Histogram of the pair keys.  Each wavefront counts into its own LDS copy
+// (copy w % ncopies) so that lanes of different wavefronts do not contend,
+// and each thread loads four pairs before it counts them.  Workgroups are
+// few and large: the closing global adds of all workgroups land on the few
+// cache lines of counts[], and their number is what bounds this kernel.
+__global__ __launch_bounds__(kCountThreads) void bin_count_kernel(const int32_t *__restrict__ lengths,
                                                         const int32_t *__restrict__ Ep, int64_t n,
-                                                        int max_len, int bw, int nbins,
+                                                        int max_len, int bw, int nbins, int ncopies,
                                                         int32_t *__restrict__ counts) {
     extern __shared__ int32_t hist[];
-    for (int b = threadIdx.x; b < nbins; b += blockDim.x) hist[b] = 0;
+    for (int b = threadIdx.x; b < nbins * ncopies; b += blockDim.x) hist[b] = 0;
     __syncthreads();
+    int32_t *mine = hist + (int)((threadIdx.x / kWave) % ncopies) * nbins;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
-        const int m = lengths ? lengths[p] : max_len;
-        int bin, Ee;
-        if (pair_key(m, Ep[p], max_len, bw, bin, Ee)) atomicAdd(&hist[bin], 1);
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += 4 * stride) {
+        int m[4], e[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int64_t q = p + k * stride;
+            m[k] = q < n ? (lengths ? lengths[q] : max_len) : -1;
+            e[k] = q < n ? Ep[q] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            int bin, Ee;
+            if (pair_key(m[k], e[k], max_len, bw, bin, Ee)) atomicAdd(&mine[bin], 1);
+        }
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < nbins; b += blockDim.x)
-        if (hist[b]) atomicAdd(&counts[b], hist[b]);
+    for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
+        int32_t c = 0;
+        for (int k = 0; k < ncopies; k++) c += hist[k * nbins + b];
+        if (c) atomicAdd(&counts[b], c);
+    }
 }
 
 // One workgroup of kPlanThreads threads.

@@ -71,6 +71,9 @@ struct VerifyParams {
 constexpr int kMaxE = 31;                     // largest E (after clamping to m-1)
 constexpr int kBinE = kMaxE + 1;              // E values per length bucket
 constexpr int kPlanThreads = 1024;
+constexpr int kCountThreads = 1024;           // histogram workgroup
+constexpr int kCountGroups = 512;             // histogram workgroups at most
+constexpr int kCountLds = 64 * 1024;          // LDS of the histogram copies at most
 constexpr int kCostBuckets = 16;
 // Tiles are launched per E class, each with the LDS its largest E needs:
 // Ee <= 13 fits two wavefronts per SIMD, Ee <= 31 one.
@@ -220,7 +223,7 @@ __global__ void shouji_local_kernel(LocalParams prm);
 __global__ void shouji_tiles_kernel(TilesParams prm);
 __global__ void fill_i32_kernel(int32_t *p, int64_t n, int32_t v);
 __global__ void bin_count_kernel(const int32_t *lengths, const int32_t *Ep, int64_t n, int max_len,
-                                 int bw, int nbins, int32_t *counts);
+                                 int bw, int nbins, int ncopies, int32_t *counts);
 __global__ void bin_plan_kernel(const int32_t *counts, int nbins, int nbucket_len, PlanOut out);
 __global__ void bin_scatter_kernel(ScatterParams prm);
 __global__ void bin_scatter_lds_kernel(ScatterParams prm);
