@@ -132,8 +132,13 @@ __global__ __launch_bounds__(kPlanThreads) void bin_plan_kernel(
         out.ntiles[tid] = acc;
     }
     __syncthreads();
+    // the bin's first slot is carried in a register: reading it back from
+    // offsets[] after each tile store would wait on memory once per tile
+    int64_t first = part[tid] - s;
     for (int b = lo; b < hi; b++) {
         const int c = counts[b];
+        const int64_t ob = first;
+        first += c;
         if (!c) continue;
         const int Ee = b % kBinE, mb = b / kBinE;
         const int cls = e_class(Ee);
@@ -144,7 +149,7 @@ __global__ __launch_bounds__(kPlanThreads) void bin_plan_kernel(
         int4 *tl = out.tiles[cls];
         for (int i = 0; i < nt; i++) {
             const int cnt = min(kPairsPerWave, c - i * kPairsPerWave);
-            tl[t0 + i] = make_int4((int)(out.offsets[b] + (int64_t)i * kPairsPerWave), cnt, Ee, 0);
+            tl[t0 + i] = make_int4((int)(ob + (int64_t)i * kPairsPerWave), cnt, Ee, 0);
         }
     }
     (void)nbucket_len;
