@@ -10,6 +10,7 @@
 #include <utility>
 
 #include "../../include/shouji.h"
+#include "shouji_binning.h"
 #include "shouji_internal.h"
 
 namespace {

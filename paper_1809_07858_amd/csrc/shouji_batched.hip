@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "shouji_binning.h"
 #include "shouji_internal.h"
 
 namespace shouji {

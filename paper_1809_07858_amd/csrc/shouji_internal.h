@@ -67,82 +67,6 @@ struct VerifyParams {
     int16_t *out;
 };
 
-// ---- batched form
-constexpr int kMaxE = 31;                     // largest E (after clamping to m-1)
-constexpr int kBinE = kMaxE + 1;              // E values per length bucket
-constexpr int kPlanThreads = 1024;
-constexpr int kCountThreads = 1024;           // histogram workgroup
-constexpr int kCountGroups = 512;             // histogram workgroups at most
-constexpr int kCountLds = 64 * 1024;          // LDS of the histogram copies at most
-constexpr int kCostBuckets = 16;
-// Tiles are launched per E class, each with the LDS its largest E needs:
-// Ee <= 13 fits two wavefronts per SIMD, Ee <= 31 one.
-constexpr int kEClasses = 2;
-__host__ __device__ inline int e_class(int Ee) { return Ee <= 13 ? 0 : 1; }
-__host__ __device__ inline int e_class_bound(int c) { return c == 0 ? 13 : 31; }
-constexpr int kMinBinWidth = 4;
-constexpr int kScatterChunk = 8192;           // pairs per workgroup of the staged scatter
-constexpr int kScatterThreads = 1024;
-constexpr int kScatterMaxBins = 4128;         // LDS tables of the staged scatter
-inline size_t scatter_lds_bytes(int nbins) {
-    return (size_t)nbins * 4 * 2 + 8 + (size_t)nbins * 8 + (size_t)kScatterChunk * (2 + 2 + 4);
-}
-
-struct PlanOut {
-    int64_t *offsets;
-    int64_t *cursors;
-    int4 *tiles[kEClasses];
-    int32_t *ntiles;          // kEClasses counts
-};
-
-struct ScatterParams {
-    const uint32_t *reads;
-    const uint32_t *refs;
-    int64_t ld;
-    const int32_t *lengths;
-    const int32_t *Ep;
-    int64_t n;
-    int32_t max_len;
-    int32_t bw;
-    int64_t *cursors;
-    int64_t *bperm;
-    int32_t *blens;
-    int32_t *bE;
-    uint32_t *breads;
-    uint32_t *brefs;
-    int64_t bld;
-    uint8_t *out_accept;
-    int16_t *out_popcount;
-    int32_t nbins;
-};
-
-// Byte offsets of the batched workspace regions (each 256-byte aligned).
-struct BatchedLayout {
-    size_t breads, brefs, blens, bE, bperm, counts, offsets, cursors, tiles[kEClasses], ntiles, total;
-    int nbins, nw;
-    int64_t max_tiles;
-};
-inline BatchedLayout batched_layout(int64_t n, int max_len, int bw) {
-    BatchedLayout L;
-    L.nw = (max_len + kHalf - 1) / kHalf;
-    L.nbins = ((max_len + bw - 1) / bw + 1) * kBinE;
-    L.max_tiles = L.nbins + (n + kPairsPerWave - 1) / kPairsPerWave;
-    size_t off = 0;
-    auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; };
-    L.breads = take((size_t)L.nw * n * 4);
-    L.brefs = take((size_t)L.nw * n * 4);
-    L.blens = take((size_t)n * 4);
-    L.bE = take((size_t)n * 4);
-    L.bperm = take((size_t)n * 8);
-    L.counts = take((size_t)L.nbins * 4);
-    L.offsets = take((size_t)L.nbins * 8);
-    L.cursors = take((size_t)L.nbins * 8);
-    for (int c = 0; c < kEClasses; c++) L.tiles[c] = take((size_t)L.max_tiles * 16);
-    L.ntiles = take(kEClasses * 4);
-    L.total = off;
-    return L;
-}
-
 // One group of up to 1024 pairs [base, min(base+1024, n)) for filter_group.
 struct GroupJob {
     const uint32_t *reads;
@@ -221,12 +145,6 @@ __global__ void shouji_plain_kernel(PlainParams prm);
 __global__ void shouji_plain_ring_kernel(PlainParams prm);
 __global__ void shouji_local_kernel(LocalParams prm);
 __global__ void shouji_tiles_kernel(TilesParams prm);
-__global__ void fill_i32_kernel(int32_t *p, int64_t n, int32_t v);
-__global__ void bin_count_kernel(const int32_t *lengths, const int32_t *Ep, int64_t n, int max_len,
-                                 int bw, int nbins, int ncopies, int32_t *counts);
-__global__ void bin_plan_kernel(const int32_t *counts, int nbins, int nbucket_len, PlanOut out);
-__global__ void bin_scatter_kernel(ScatterParams prm);
-__global__ void bin_scatter_lds_kernel(ScatterParams prm);
 
 // Thread-local error text behind shouji_last_error (printf-style format).
 int set_error(int code, const char *fmt, ...);
