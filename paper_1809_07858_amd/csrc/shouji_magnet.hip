@@ -21,7 +21,12 @@
 // left part), E+1 entries per lane: every run taken pops one part and pushes
 // at most two, and nothing is pushed after the (E+1)-th run, so at most E+1
 // parts are ever pending; sized per launch, it leaves LDS for more
-// wavefronts at small E.  A diagonal's run search walks 16 text positions per step: the
+// wavefronts at small E.  For max_len <= 256, where the LDS it takes leaves a
+// CU at least half its workgroups, each lane first copies its pair's words
+// into a column of LDS of its own (no barrier: no lane reads another's
+// column), so the many re-reads of the same words by the run searches of
+// every diagonal and part wait on LDS, not on the caches; otherwise they are
+// read from global memory.  A diagonal's run search walks 16 text positions per step: the
 // reference word, the read's two words around the diagonal's offset joined
 // with v_alignbit, one XOR and a fold give the 16 match bits, and the
 // longest run of matches in the word is found with doubling masks and a
@@ -45,8 +50,11 @@ __device__ __forceinline__ uint32_t field_mask(int n) {
 
 }  // namespace
 
+template <bool STAGED>
 __global__ __launch_bounds__(kMagnetBlock) void magnet_kernel(MagnetParams prm) {
-    extern __shared__ uint32_t stack[];                       // (E+1) entries per lane
+    // (E+1) stack entries per lane, then (STAGED) the lane's read words and
+    // reference words, ceil(max_len/16) entries each
+    extern __shared__ uint32_t stack[];
     const int tid = threadIdx.x;
     const int64_t p = (int64_t)blockIdx.x * kMagnetBlock + tid;
     if (p >= prm.n) return;
@@ -62,6 +70,16 @@ __global__ __launch_bounds__(kMagnetBlock) void magnet_kernel(MagnetParams prm) 
     const uint32_t *T = prm.refs + p;
     const int64_t ld = prm.ld;
     const int nw = (m + 15) >> 4;                       // words holding the pair's bases
+    uint32_t *sP = stack + (prm.E + 1) * kMagnetBlock + tid;
+    uint32_t *sT = sP + ((prm.max_len + 15) >> 4) * kMagnetBlock;
+    if (STAGED) {
+        for (int k = 0; k < nw; k++) {
+            sP[k * kMagnetBlock] = P[(int64_t)k * ld];
+            sT[k * kMagnetBlock] = T[(int64_t)k * ld];
+        }
+    }
+    auto read_word = [&](int k) -> uint32_t { return STAGED ? sP[k * kMagnetBlock] : P[(int64_t)k * ld]; };
+    auto ref_word = [&](int k) -> uint32_t { return STAGED ? sT[k * kMagnetBlock] : T[(int64_t)k * ld]; };
     const int thr = m > E ? (m - E + (E + 1) - 1) / (E + 1) : 0;   // ceil((m-E)/(E+1))
 
     // longest run of zeros of diagonal d inside text positions [lo, hi]
@@ -84,12 +102,12 @@ __global__ __launch_bounds__(kMagnetBlock) void magnet_kernel(MagnetParams prm) 
         for (int w = a >> 4; w <= (b >> 4); w++) {
             const int rest = b - (a > 16 * w ? a : 16 * w) + 1;   // positions left in the range
             if (carry + rest <= (best > need - 1 ? best : need - 1)) break;
-            const uint32_t tw = T[(int64_t)w * ld];
+            const uint32_t tw = ref_word(w);
             const int q0 = 16 * w - d;                       // read position of the word's field 0
             const int qw = q0 >> 4;                          // floor division
             const int ob = (q0 & 15) * 2;
-            const uint32_t lo_w = (qw >= 0 && qw < nw) ? P[(int64_t)qw * ld] : 0u;
-            const uint32_t hi_w = (qw + 1 >= 0 && qw + 1 < nw) ? P[(int64_t)(qw + 1) * ld] : 0u;
+            const uint32_t lo_w = (qw >= 0 && qw < nw) ? read_word(qw) : 0u;
+            const uint32_t hi_w = (qw + 1 >= 0 && qw + 1 < nw) ? read_word(qw + 1) : 0u;
             const uint32_t pv = __builtin_amdgcn_alignbit(hi_w, lo_w, ob);
             const uint32_t xr = tw ^ pv;
             const int klo = a - 16 * w > 0 ? a - 16 * w : 0;
@@ -224,7 +242,24 @@ extern "C" int shouji_filter_magnet(const uint32_t *reads, const uint32_t *refs,
     // a pair holds at most E+1 pending parts (each run taken pops one and
     // pushes at most two; after E+1 runs nothing is pushed)
     const size_t lds = (size_t)(prm.E + 1) * shouji::kMagnetBlock * 4;
-    hipLaunchKernelGGL(shouji::magnet_kernel, dim3(grid), dim3(shouji::kMagnetBlock), lds, (hipStream_t)stream, prm);
+    // staged: at most 32 stack entries (E <= 31 once max_len > 32) and 2 x 16
+    // words per lane, 64 KiB per workgroup.  Staging pays while a CU still
+    // holds at least half the workgroups it holds without it (measured: 8-9%
+    // faster at m=100, E=2..10 and 4% at m=250, E=5; at m=250, E=15 and 25,
+    // 3 and 2 workgroups instead of 8 and 6, 4% and 28% slower).
+    const size_t staged = (size_t)2 * ((max_len + 15) / 16) * shouji::kMagnetBlock * 4;
+    auto groups_per_cu = [](size_t bytes) {
+        const size_t k = shouji::kLdsPerCU / bytes;
+        const size_t cap = 32 / (shouji::kMagnetBlock / shouji::kWave);   // 8 wavefronts per SIMD
+        return k < cap ? k : cap;
+    };
+    if ((max_len + 15) / 16 <= shouji::kMagnetStageWords && lds + staged <= 65536 &&
+        2 * groups_per_cu(lds + staged) >= groups_per_cu(lds))
+        hipLaunchKernelGGL(shouji::magnet_kernel<true>, dim3(grid), dim3(shouji::kMagnetBlock), lds + staged,
+                           (hipStream_t)stream, prm);
+    else
+        hipLaunchKernelGGL(shouji::magnet_kernel<false>, dim3(grid), dim3(shouji::kMagnetBlock), lds,
+                           (hipStream_t)stream, prm);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return set_error(SHOUJI_ERR_DEVICE, "shouji_filter_magnet: launch failed: %s", hipGetErrorString(e));

@@ -24,6 +24,7 @@ struct WindowParams {
 
 // MAGNET filter (one pair per lane, LDS stack of pending subproblems).
 constexpr int kMagnetBlock = 256;
+constexpr int kMagnetStageWords = 16;  // most words per sequence staged in LDS (max_len <= 256)
 struct MagnetParams {
     const uint32_t *reads;
     const uint32_t *refs;

@@ -48,12 +48,15 @@ def test_mixed_lengths_per_pair_E(sj):
     _check(sj, p, 300)
 
 
-def test_longest_lengths_and_largest_thresholds(sj):
+@pytest.mark.parametrize("config", [None, (4, 2)])
+def test_longest_lengths_and_largest_thresholds(sj, config):
     # lengths 500..1024 (up to 64 words) with E_p up to 31: every bin of the
-    # E > 13 class and the largest length buckets
+    # E > 13 class and the largest length buckets.  Bin width 4 gives the
+    # most bins (8,224): one histogram copy per workgroup, and more bins than
+    # the LDS-staged scatter holds, so the direct scatter runs
     p = syninput.generate(3_000, 500, 1024, E=None, r_max=0.031, seed=3100)
     assert p.E.max() >= 25 and p.lengths.max() > 1000
-    _check(sj, p, 1024)
+    _check(sj, p, 1024, config=config)
 
 
 @pytest.mark.parametrize("config", [(4, 2), (8, 4), (16, 1), (32, 4)])
