@@ -589,8 +589,10 @@ def bench_serving(dev, total_pairs, batch_pairs, slots, distinct=1_000_000, load
     bases: random bases around a region holding the generated reference
     segments); a request's pairs are a contiguous run of `distinct` generated
     pairs.  First the whole stream is submitted at once (peak pairs/s), then it
-    is replayed with Poisson arrivals at `load` x that peak; latency = submit to
-    results in the caller's host buffers.  This runs three times: with the reads
+    is replayed with Poisson arrivals at `load` x that peak (one seeded sequence
+    of exponential gaps, scaled to each run's rate); latency = submit to
+    results in the caller's host buffers.  The packed stream is also replayed
+    at half its peak.  This runs three times: with the reads
     packed back to back (ceil(m/16) words each) in pinned host memory, and with
     reads in rows of ceil(300/16) = 19 words in pinned memory (both moved by DMA
     in place) and in pageable memory (staged by the server).  Every served
@@ -666,7 +668,11 @@ def bench_serving(dev, total_pairs, batch_pairs, slots, distinct=1_000_000, load
     out_base = np.cumsum([0] + sizes)
     pin_out = [pinned(np.zeros(total_pairs, np.uint8)), pinned(np.zeros(total_pairs, np.int16))]
 
-    def run(mode, nreq=None):
+    # one sequence of unit-mean exponential gaps for every run, scaled to each
+    # run's own arrival rate, so that the runs differ only in what they measure
+    unit_gaps = np.random.default_rng(seed + 5).exponential(1.0, len(sizes))
+
+    def run(mode, nreq=None, load=load):
         N = len(sizes) if nreq is None else nreq     # the first N requests of the stream
         tot = int(sum(sizes[:N]))
         srv = sj.Server(pool, pool_words * 16, max_len, slots=slots, max_batch_pairs=batch_pairs,
@@ -707,7 +713,7 @@ def bench_serving(dev, total_pairs, batch_pairs, slots, distinct=1_000_000, load
             # Poisson arrivals at load x peak
             mean_size = tot / N
             rate = load * peak / mean_size             # requests per second
-            arrivals = np.cumsum(rng.exponential(1.0 / rate, N))
+            arrivals = np.cumsum(unit_gaps[:N] / rate)
             lat = [None] * N
             sub_t = [None] * N
             tq = []
@@ -765,6 +771,10 @@ def bench_serving(dev, total_pairs, batch_pairs, slots, distinct=1_000_000, load
     res["rows_pinned"]["host_bytes_per_pair"] = 4 * nw + 20
     res["pageable"] = run("pageable")
     res["pageable"]["host_bytes_per_pair"] = 4 * nw + 20
+    # latency away from saturation: the packed stream at half its burst peak
+    half = run("packed", load=0.5)
+    res["packed_load_0.5"] = {k: half[k] for k in ("value", "p50_ms", "p99_ms", "mean_ms", "max_ms",
+                                                   "offered_pairs_per_s", "load", "peak_pairs_per_s")}
     res.update({"workload": "Poisson stream of %d requests, %d pairs in all, request size "
                             "U{1..200000}, lengths uniform 64..300, E_p=floor(r*m) r~U[0,0.10], "
                             "2 GiB device-resident packed reference pool (8 Gi bases), seed %d; "
