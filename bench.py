@@ -124,6 +124,8 @@ def main():
     ap.add_argument("--serving-pairs", type=int, default=40_000_000)
     ap.add_argument("--serving-batch", type=int, default=1 << 19)
     ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--serving-fill-wait-us", type=int, default=0,
+                    help="server batch fill wait (microseconds; 0: a free slot takes what is queued)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -281,7 +283,8 @@ def main():
         out["local"] = bench_local(dev, args.n, args.E, ms_per_step, with_oracle=not args.no_cpu)
     if not args.no_serving:
         out["serving"] = bench_serving(dev, args.serving_pairs, args.serving_batch,
-                                       args.serving_slots, with_oracle=not args.no_cpu)
+                                       args.serving_slots, with_oracle=not args.no_cpu,
+                                       fill_wait_us=args.serving_fill_wait_us)
     print(json.dumps(out), flush=True)
 
 
@@ -580,7 +583,7 @@ def bench_local(dev, n, E, plain_ms, m=100, max_len=128, steps=50, with_oracle=T
 
 
 def bench_serving(dev, total_pairs, batch_pairs, slots, distinct=1_000_000, load=0.8,
-                  with_oracle=True, seed=4000):
+                  with_oracle=True, seed=4000, fill_wait_us=0):
     """Serving form: a Poisson stream of requests through the request server.
 
     Requests hold U{1..200000} pairs (about total_pairs in all), lengths uniform
@@ -676,7 +679,7 @@ def bench_serving(dev, total_pairs, batch_pairs, slots, distinct=1_000_000, load
         N = len(sizes) if nreq is None else nreq     # the first N requests of the stream
         tot = int(sum(sizes[:N]))
         srv = sj.Server(pool, pool_words * 16, max_len, slots=slots, max_batch_pairs=batch_pairs,
-                        memory_budget=16 << 30)
+                        memory_budget=16 << 30, fill_wait_us=fill_wait_us)
         state = {"bad": 0}
         try:
             def submit(i):
@@ -782,7 +785,8 @@ def bench_serving(dev, total_pairs, batch_pairs, slots, distinct=1_000_000, load
                             "reads in rows of 19 words, pinned and pageable, are nested)"
                             % (len(sizes), total_pairs, seed),
                 "requests": len(sizes), "pairs": total_pairs, "distinct_pairs": distinct,
-                "batch_pairs": batch_pairs, "batched_vs_oracle_sample_mismatches": oracle_bad,
+                "batch_pairs": batch_pairs, "fill_wait_us": fill_wait_us,
+                "batched_vs_oracle_sample_mismatches": oracle_bad,
                 "pool_bytes": pool_words * 4, "setup_s": setup_s})
     return res
 

@@ -280,6 +280,13 @@ typedef struct {
                                 slots are made when `slots` would not fit, and
                                 SHOUJI_ERR_NOMEM is returned when not even one does   */
     int32_t host_threads;    /* threads staging a batch into pinned memory (0: 8)     */
+    int32_t fill_wait_us;    /* batch fill wait, 0..1000000 microseconds (0: none):
+                                while another batch is in flight and fewer than
+                                max_batch_pairs pairs are queued, a free slot waits
+                                until this long after the oldest queued request was
+                                submitted before it takes them, so that batches under
+                                a steady stream run fuller; with no batch in flight a
+                                slot never waits                                      */
 } shouji_server_config;
 
 typedef struct {

@@ -31,7 +31,8 @@ class ShoujiError(RuntimeError):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("pool", ctypes.c_void_p), ("pool_bases", ctypes.c_int64), ("max_len", ctypes.c_int32),
                 ("slots", ctypes.c_int32), ("max_batch_pairs", ctypes.c_int64),
-                ("memory_budget", ctypes.c_int64), ("host_threads", ctypes.c_int32)]
+                ("memory_budget", ctypes.c_int64), ("host_threads", ctypes.c_int32),
+                ("fill_wait_us", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -488,7 +489,7 @@ class Server:
     """
 
     def __init__(self, pool, pool_bases, max_len, slots=3, max_batch_pairs=1 << 20,
-                 memory_budget=0, host_threads=0):
+                 memory_budget=0, host_threads=0, fill_wait_us=0):
         import torch
         if not pool.is_cuda or pool.dtype != torch.int32 or not pool.is_contiguous():
             raise ValueError("pool must be a contiguous int32 CUDA tensor")
@@ -498,7 +499,8 @@ class Server:
         self.max_len = int(max_len)
         self.nw = nwords(max_len)
         cfg = ServerConfig(pool.data_ptr(), int(pool_bases), int(max_len), int(slots),
-                           int(max_batch_pairs), int(memory_budget), int(host_threads))
+                           int(max_batch_pairs), int(memory_budget), int(host_threads),
+                           int(fill_wait_us))
         h = ctypes.c_void_p()
         _check(lib().shouji_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

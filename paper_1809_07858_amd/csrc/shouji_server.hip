@@ -400,6 +400,18 @@ void scheduler_loop(shouji_server *S) {
             S->cv.wait(lk);
             continue;
         }
+        // with a batch in flight the device is busy anyway: a part-filled batch
+        // may wait for more requests, until the oldest queued one is due
+        if (S->cfg.fill_wait_us > 0 && !S->inflight.empty()) {
+            int64_t queued = 0;
+            for (const Part &q : S->queue)
+                if ((queued += q.count) >= B) break;
+            const clk::time_point due = S->queue.front().r->submitted + std::chrono::microseconds(S->cfg.fill_wait_us);
+            if (queued < B && clk::now() < due) {
+                S->cv.wait_until(lk, due);
+                continue;
+            }
+        }
         // fill the slot with queued parts in arrival order
         s->parts.clear();
         s->pairs = 0;
@@ -493,6 +505,9 @@ extern "C" int shouji_server_create(const shouji_server_config *cfg, shouji_serv
                          SHOUJI_MAX_LEN);
     if (cfg->max_batch_pairs <= 0 || cfg->slots <= 0 || cfg->memory_budget < 0)
         return set_error(SHOUJI_ERR_ARG, "shouji_server_create: max_batch_pairs and slots must be positive");
+    if (cfg->fill_wait_us < 0 || cfg->fill_wait_us > 1000000)
+        return set_error(SHOUJI_ERR_RANGE, "shouji_server_create: fill_wait_us %d outside 0..1000000",
+                         cfg->fill_wait_us);
     std::unique_ptr<shouji_server> S(new shouji_server());
     S->cfg = *cfg;
     S->nw = (cfg->max_len + shouji::kHalf - 1) / shouji::kHalf;

@@ -83,6 +83,11 @@ def test_server_argument_errors_are_reported_without_a_device():
     assert b"slots" in L.shouji_last_error()
     cfg = sj.ServerConfig(16, 1000, 300, 2, 1 << 40, 0, 0)
     assert L.shouji_server_create(ctypes.byref(cfg), ctypes.byref(h)) == -3      # batch words
+    for wait in (-1, 1000001):
+        cfg = sj.ServerConfig(16, 1000, 100, 2, 1024, 0, 0, wait)
+        assert L.shouji_server_create(ctypes.byref(cfg), ctypes.byref(h)) == -3  # fill wait
+        assert b"fill_wait_us" in L.shouji_last_error()
+    assert ctypes.sizeof(sj.ServerConfig) == 48
     t = ctypes.c_uint64()
     assert L.shouji_server_submit(None, None, ctypes.byref(t)) == -1
     assert L.shouji_server_wait(None, 1, None) == -1

@@ -322,3 +322,28 @@ def test_longest_reads(sj):
         a1, c1, _ = srv.wait(t1)
     acc, pc = np.concatenate([a0, a1]), np.concatenate([c0, c1])
     assert np.array_equal(acc, ea) and np.array_equal(pc, ep)
+
+
+def test_fill_wait_trickled_stream(sj, work):
+    # requests trickle in while batches are in flight: with a fill wait a free
+    # slot holds a part-filled batch for more requests (never with nothing in
+    # flight); every result is the same.  The batch counts depend on host
+    # timing and are printed, not compared
+    import time
+    cuts = _cuts(12_000, [150] * 80)
+    batches = {}
+    for wait in (0, 3000):
+        print("server: %d trickled requests, fill_wait_us %d" % (len(cuts), wait), flush=True)
+        with _server(sj, work, slots=2, max_batch_pairs=4096, fill_wait_us=wait) as srv:
+            tickets = []
+            for lo, hi in cuts:
+                tickets.append(_submit(srv, work, lo, hi))
+                time.sleep(0.0002)
+            for (lo, hi), t in zip(cuts, tickets):
+                acc, pc, ms = srv.wait(t)
+                assert ms >= 0.0
+                _expect(work, lo, hi, acc, pc)
+            st = srv.stats()
+        assert st["pairs_done"] == 12_000 and st["queued_pairs"] == 0
+        batches[wait] = st["batches"]
+    print("batches:", batches, flush=True)
