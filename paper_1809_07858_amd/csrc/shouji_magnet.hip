@@ -22,11 +22,11 @@
 // at most two, and nothing is pushed after the (E+1)-th run, so at most E+1
 // parts are ever pending; sized per launch, it leaves LDS for more
 // wavefronts at small E.  For max_len <= 256, where the LDS it takes leaves a
-// CU at least half its workgroups, each lane first copies its pair's words
-// into a column of LDS of its own (no barrier: no lane reads another's
-// column), so the many re-reads of the same words by the run searches of
-// every diagonal and part wait on LDS, not on the caches; otherwise they are
-// read from global memory.  A diagonal's run search walks 16 text positions per step: the
+// CU enough of its workgroups, each lane first copies its pair's words (both
+// sequences', or the read's alone) into a column of LDS of its own (no
+// barrier: no lane reads another's column), so the many re-reads of the same
+// words by the run searches of every diagonal and part wait on LDS, not on
+// the caches; the words not copied are read from global memory.  A diagonal's run search walks 16 text positions per step: the
 // reference word, the read's two words around the diagonal's offset joined
 // with v_alignbit, one XOR and a fold give the 16 match bits, and the
 // longest run of matches in the word is found with doubling masks and a
@@ -50,7 +50,7 @@ __device__ __forceinline__ uint32_t field_mask(int n) {
 
 }  // namespace
 
-template <bool STAGED>
+template <int STAGED>
 __global__ __launch_bounds__(kMagnetBlock) void magnet_kernel(MagnetParams prm) {
     // (E+1) stack entries per lane, then (STAGED) the lane's read words and
     // reference words, ceil(max_len/16) entries each
@@ -75,11 +75,11 @@ __global__ __launch_bounds__(kMagnetBlock) void magnet_kernel(MagnetParams prm) 
     if (STAGED) {
         for (int k = 0; k < nw; k++) {
             sP[k * kMagnetBlock] = P[(int64_t)k * ld];
-            sT[k * kMagnetBlock] = T[(int64_t)k * ld];
+            if (STAGED == 2) sT[k * kMagnetBlock] = T[(int64_t)k * ld];
         }
     }
     auto read_word = [&](int k) -> uint32_t { return STAGED ? sP[k * kMagnetBlock] : P[(int64_t)k * ld]; };
-    auto ref_word = [&](int k) -> uint32_t { return STAGED ? sT[k * kMagnetBlock] : T[(int64_t)k * ld]; };
+    auto ref_word = [&](int k) -> uint32_t { return STAGED == 2 ? sT[k * kMagnetBlock] : T[(int64_t)k * ld]; };
     const int thr = m > E ? (m - E + (E + 1) - 1) / (E + 1) : 0;   // ceil((m-E)/(E+1))
 
     // longest run of zeros of diagonal d inside text positions [lo, hi]
@@ -243,22 +243,27 @@ extern "C" int shouji_filter_magnet(const uint32_t *reads, const uint32_t *refs,
     // pushes at most two; after E+1 runs nothing is pushed)
     const size_t lds = (size_t)(prm.E + 1) * shouji::kMagnetBlock * 4;
     // staged: at most 32 stack entries (E <= 31 once max_len > 32) and 2 x 16
-    // words per lane, 64 KiB per workgroup.  Staging pays while a CU still
-    // holds at least half the workgroups it holds without it (measured: 8-9%
-    // faster at m=100, E=2..10 and 4% at m=250, E=5; at m=250, E=15 and 25,
-    // 3 and 2 workgroups instead of 8 and 6, 4% and 28% slower).
+    // words per lane, 64 KiB per workgroup.  Staging both sequences pays while
+    // a CU still holds at least half the workgroups it holds without it
+    // (measured: 8-9% faster at m=100, E=2..10 and 4% at m=250, E=5; at m=250,
+    // E=15 and 25, 3 and 2 workgroups instead of 8 and 6, 4% and 28% slower).
+    // Else the read's words alone, when that keeps more than half (m=250,
+    // E=15: 5 of 8, 5% faster; E=25: 3 of 6, 2% slower, so not there).
     const size_t staged = (size_t)2 * ((max_len + 15) / 16) * shouji::kMagnetBlock * 4;
     auto groups_per_cu = [](size_t bytes) {
         const size_t k = shouji::kLdsPerCU / bytes;
         const size_t cap = 32 / (shouji::kMagnetBlock / shouji::kWave);   // 8 wavefronts per SIMD
         return k < cap ? k : cap;
     };
-    if ((max_len + 15) / 16 <= shouji::kMagnetStageWords && lds + staged <= 65536 &&
-        2 * groups_per_cu(lds + staged) >= groups_per_cu(lds))
-        hipLaunchKernelGGL(shouji::magnet_kernel<true>, dim3(grid), dim3(shouji::kMagnetBlock), lds + staged,
+    const bool fits = (max_len + 15) / 16 <= shouji::kMagnetStageWords && lds + staged <= 65536;
+    if (fits && 2 * groups_per_cu(lds + staged) >= groups_per_cu(lds))
+        hipLaunchKernelGGL(shouji::magnet_kernel<2>, dim3(grid), dim3(shouji::kMagnetBlock), lds + staged,
+                           (hipStream_t)stream, prm);
+    else if (fits && 2 * groups_per_cu(lds + staged / 2) > groups_per_cu(lds))
+        hipLaunchKernelGGL(shouji::magnet_kernel<1>, dim3(grid), dim3(shouji::kMagnetBlock), lds + staged / 2,
                            (hipStream_t)stream, prm);
     else
-        hipLaunchKernelGGL(shouji::magnet_kernel<false>, dim3(grid), dim3(shouji::kMagnetBlock), lds,
+        hipLaunchKernelGGL(shouji::magnet_kernel<0>, dim3(grid), dim3(shouji::kMagnetBlock), lds,
                            (hipStream_t)stream, prm);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess)

@@ -49,6 +49,15 @@ def test_m100_vs_oracle(sj, E):
     assert (acc == 1).any() and (acc == 0).any()
 
 
+@pytest.mark.parametrize("E", [5, 15, 25])
+def test_m250_vs_oracle(sj, E):
+    # max_len 250: both sequences' words in LDS at E = 5, the read's only at
+    # E = 15 and 25 (the stack takes the rest)
+    p = syninput.generate(4_000, 250, E=E, seed=1150 + E)
+    acc, pc = _compare(sj, p.P, p.T, p.lengths, E, 250, "m250")
+    assert (acc == 1).any() and (acc == 0).any()
+
+
 @pytest.mark.parametrize("E", [0, 4, 13, 20, 31])
 def test_mixed_lengths_vs_oracle(sj, E):
     p = syninput.generate(6000, 40, 300, E=min(max(E, 1), 25), seed=1200 + E)
