@@ -227,3 +227,14 @@ def test_lengths_around_word_and_block_edges(sj):
         p = syninput.generate(2_100, m, E=min(3, max(m - 1, 0)), seed=900 + m)
         for E in (0, 1, 5):
             _check(sj, p, E, m)
+
+
+def test_no_lengths_around_word_and_block_edges(sj):
+    # the kernel without a length array computes its boundary masks from the
+    # positions: the same word, block and iteration edges as above, at
+    # thresholds that clamp to m-1 for the shortest pairs
+    for m in (1, 2, 3, 4, 5, 8, 9, 15, 16, 17, 18, 20, 24, 31, 32, 33, 34, 36, 40, 47, 48, 49, 97, 98, 99, 100,
+              101, 104, 112, 113):
+        p = syninput.generate(1_500, m, E=min(3, max(m - 1, 0)), seed=1900 + m)
+        for E in (0, 1, 5, 20):
+            _check(sj, p, E, m, with_lengths=False)
