@@ -156,3 +156,19 @@ def test_full_size_sampled(sj):
     ea, ep = oracle.shouji_batch(p.P[idx], p.T[idx], p.lengths[idx], E_per_pair=p.E[idx])
     bad = np.nonzero((ga[idx] != ea) | (gp[idx] != ep))[0]
     assert bad.size == 0, "mismatches at %s" % idx[bad[:8]]
+
+
+def test_no_lengths_per_pair_E(sj):
+    # lengths = NULL: every pair has max_len bases; per-pair thresholds across
+    # both E classes and a ragged pair count
+    p = syninput.generate(5_003, 150, E=None, r_max=0.2, seed=3200)
+    assert (p.lengths == 150).all() and p.E.max() > 13
+    d = torch.device("cuda:0")
+    r = torch.from_numpy(sj.pack_words(p.P, 150)).to(d)
+    t = torch.from_numpy(sj.pack_words(p.T, 150)).to(d)
+    E = torch.from_numpy(p.E).to(d)
+    print("batched no lengths n=%d" % p.n, flush=True)
+    acc, pc = sj.shouji_filter_batched(r, t, None, E, max_len=150)
+    torch.cuda.synchronize()
+    ea, ep = oracle.shouji_batch(p.P, p.T, p.lengths, E_per_pair=p.E)
+    assert np.array_equal(acc.cpu().numpy(), ea) and np.array_equal(pc.cpu().numpy(), ep)
