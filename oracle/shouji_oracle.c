@@ -69,6 +69,55 @@ static int count_zeros(const uint8_t *v, int len) {
 }
 
 /*
+ * Steps 1 and 2 of the filter (Sec. 2.2.1-2.2.2; Algorithm 1) for a pattern
+ * P of length mP and a text T of length mT with windows of W columns (W = 4
+ * in Shouji; other widths only for the window-width study of Suppl. Sec.
+ * 6.1).  Every other form of the filter in this file calls this one
+ * function, so the worked examples that pin any of them pin all of them.
+ * On return S[0 .. mT+W-2] holds the Shouji bit-vector (positions >= mT
+ * stay 1).  reading: 0 = B (the adopted reading), 1 = A (sensitivity study
+ * only).
+ */
+static void shouji_steps(const uint8_t *P, int mP, const uint8_t *T, int mT, int E, int W, int reading,
+                         uint8_t *S) {
+    /* Step 1 (Sec. 2.2.1): the 2E+1 diagonals, stored as rows over text
+     * columns 0 .. mT+W-2 so that every window i in [0, mT) reads W cells. */
+    int nd = 2 * E + 1, w = mT + W - 1;
+    uint8_t *N = (uint8_t *)malloc((size_t)nd * (size_t)w + 1);
+    for (int d = -E; d <= E; d++)
+        for (int j = 0; j < w; j++)
+            N[(size_t)(d + E) * w + j] = (uint8_t)map_cell2(P, mP, T, mT, d, j);
+    /* Step 2 (Sec. 2.2.2): the Shouji bit-vector starts as all ones; one
+     * window per text column. */
+    for (int j = 0; j < w; j++) S[j] = 1;
+    for (int i = 0; i < mT; i++) {
+        const uint8_t *Z = NULL;
+        int best_key = -1;
+        /* off-diagonal candidates in evaluation order d = +1, -1, ..., +E, -E;
+         * key = 2 * zeros + leading zero, the earliest keeps full ties */
+        for (int k = 1; k <= E; k++) {
+            for (int s = 0; s < 2; s++) {
+                int d = s == 0 ? k : -k;
+                const uint8_t *seg = N + (size_t)(d + E) * w + i;
+                int key = 2 * count_zeros(seg, W) + (seg[0] == 0 ? 1 : 0);
+                if (key > best_key) { best_key = key; Z = seg; }
+            }
+        }
+        const uint8_t *M = N + (size_t)E * w + i;     /* main diagonal, last */
+        if (reading == 0) {
+            int key = 2 * count_zeros(M, W) + (M[0] == 0 ? 1 : 0);
+            if (key > best_key) { best_key = key; Z = M; }
+        } else {
+            if (Z == NULL || count_zeros(M, W) > count_zeros(Z, W)) Z = M;
+        }
+        /* update S[i..i+W-1] only with strictly more zeros */
+        if (count_zeros(Z, W) > count_zeros(S + i, W))
+            for (int t = 0; t < W; t++) S[i + t] = Z[t];
+    }
+    free(N);
+}
+
+/*
  * Filter one pair.  P, T: base codes, length m (>= 0).  reading: 0 = B (the
  * adopted reading), 1 = A (sensitivity study only).  If S_out is not NULL it
  * receives the final Shouji bit-vector S[0..m).  Returns the number of ones.
@@ -76,44 +125,13 @@ static int count_zeros(const uint8_t *v, int len) {
 int oracle_shouji_pair(const uint8_t *P, const uint8_t *T, int32_t m, int32_t E,
                        int32_t reading, uint8_t *S_out) {
     if (m < 0 || E < 0) return -1;
-    /* Step 1 (Sec. 2.2.1): the 2E+1 diagonals, stored as rows over text
-     * columns 0..m+2 so that every window i in [0, m) reads 4 cells. */
-    int nd = 2 * E + 1, w = m + 3;
-    uint8_t *N = (uint8_t *)malloc((size_t)nd * (size_t)w + 1);
-    uint8_t *S = (uint8_t *)malloc((size_t)w + 1);
-    for (int d = -E; d <= E; d++)
-        for (int j = 0; j < w; j++)
-            N[(size_t)(d + E) * w + j] = (uint8_t)map_cell(P, T, m, d, j);
-    /* Step 2 (Sec. 2.2.2): Shouji bit-vector starts as all ones. */
-    for (int j = 0; j < w; j++) S[j] = 1;
-    for (int i = 0; i < m; i++) {
-        const uint8_t *Z = NULL;
-        int best_key = -1;
-        /* off-diagonal candidates in evaluation order d = +1, -1, ..., +E, -E */
-        for (int k = 1; k <= E; k++) {
-            for (int s = 0; s < 2; s++) {
-                int d = s == 0 ? k : -k;
-                const uint8_t *seg = N + (size_t)(d + E) * w + i;
-                int key = 2 * count_zeros(seg, 4) + (seg[0] == 0 ? 1 : 0);
-                if (key > best_key) { best_key = key; Z = seg; }
-            }
-        }
-        const uint8_t *M = N + (size_t)E * w + i;     /* main diagonal */
-        if (reading == 0) {
-            int key = 2 * count_zeros(M, 4) + (M[0] == 0 ? 1 : 0);
-            if (key > best_key) { best_key = key; Z = M; }
-        } else {
-            if (Z == NULL || count_zeros(M, 4) > count_zeros(Z, 4)) Z = M;
-        }
-        /* update S[i..i+3] only with strictly more zeros */
-        if (count_zeros(Z, 4) > count_zeros(S + i, 4))
-            for (int t = 0; t < 4; t++) S[i + t] = Z[t];
-    }
+    uint8_t *S = (uint8_t *)malloc((size_t)m + 4);
+    shouji_steps(P, m, T, m, E, 4, reading, S);
     /* Step 3 (Sec. 2.2.3): count the ones over the m positions. */
     int ones = 0;
     for (int j = 0; j < m; j++) ones += S[j];
     if (S_out) memcpy(S_out, S, (size_t)m);
-    free(N); free(S);
+    free(S);
     return ones;
 }
 
@@ -128,34 +146,12 @@ int oracle_shouji_pair(const uint8_t *P, const uint8_t *T, int32_t m, int32_t E,
 int oracle_shouji_pair_w(const uint8_t *P, const uint8_t *T, int32_t m, int32_t E, int32_t W,
                          uint8_t *S_out) {
     if (m < 0 || E < 0 || W < 1) return -1;
-    int nd = 2 * E + 1, w = m + W - 1;
-    uint8_t *N = (uint8_t *)malloc((size_t)nd * (size_t)w + 1);
-    uint8_t *S = (uint8_t *)malloc((size_t)w + 1);
-    for (int d = -E; d <= E; d++)
-        for (int j = 0; j < w; j++)
-            N[(size_t)(d + E) * w + j] = (uint8_t)map_cell(P, T, m, d, j);
-    for (int j = 0; j < w; j++) S[j] = 1;
-    for (int i = 0; i < m; i++) {
-        const uint8_t *Z = NULL;
-        int best_key = -1;
-        for (int k = 1; k <= E; k++) {
-            for (int s2 = 0; s2 < 2; s2++) {
-                int d = s2 == 0 ? k : -k;
-                const uint8_t *seg = N + (size_t)(d + E) * w + i;
-                int key = 2 * count_zeros(seg, W) + (seg[0] == 0 ? 1 : 0);
-                if (key > best_key) { best_key = key; Z = seg; }
-            }
-        }
-        const uint8_t *M = N + (size_t)E * w + i;
-        int key = 2 * count_zeros(M, W) + (M[0] == 0 ? 1 : 0);
-        if (key > best_key) { best_key = key; Z = M; }
-        if (count_zeros(Z, W) > count_zeros(S + i, W))
-            for (int t = 0; t < W; t++) S[i + t] = Z[t];
-    }
+    uint8_t *S = (uint8_t *)malloc((size_t)m + (size_t)W);
+    shouji_steps(P, m, T, m, E, W, 0, S);
     int ones = 0;
     for (int j = 0; j < m; j++) ones += S[j];
     if (S_out) memcpy(S_out, S, (size_t)m);
-    free(N); free(S);
+    free(S);
     return ones;
 }
 
@@ -198,34 +194,8 @@ enum { ORACLE_GLOBAL = 0, ORACLE_LOCAL = 1, ORACLE_GLOCAL_START = 2, ORACLE_GLOC
 int oracle_shouji_pair2(const uint8_t *P, int32_t mP, const uint8_t *T, int32_t mT, int32_t E,
                         int32_t mode, int32_t reading, uint8_t *S_out) {
     if (mP < 0 || mT < 0 || E < 0 || mode < 0 || mode > 3) return -1;
-    int nd = 2 * E + 1, w = mT + 3;
-    uint8_t *N = (uint8_t *)malloc((size_t)nd * (size_t)w + 1);
-    uint8_t *S = (uint8_t *)malloc((size_t)w + 1);
-    for (int d = -E; d <= E; d++)
-        for (int j = 0; j < w; j++)
-            N[(size_t)(d + E) * w + j] = (uint8_t)map_cell2(P, mP, T, mT, d, j);
-    for (int j = 0; j < w; j++) S[j] = 1;
-    for (int i = 0; i < mT; i++) {
-        const uint8_t *Z = NULL;
-        int best_key = -1;
-        for (int k = 1; k <= E; k++) {
-            for (int s = 0; s < 2; s++) {
-                int d = s == 0 ? k : -k;
-                const uint8_t *seg = N + (size_t)(d + E) * w + i;
-                int key = 2 * count_zeros(seg, 4) + (seg[0] == 0 ? 1 : 0);
-                if (key > best_key) { best_key = key; Z = seg; }
-            }
-        }
-        const uint8_t *M = N + (size_t)E * w + i;
-        if (reading == 0) {
-            int key = 2 * count_zeros(M, 4) + (M[0] == 0 ? 1 : 0);
-            if (key > best_key) { best_key = key; Z = M; }
-        } else {
-            if (Z == NULL || count_zeros(M, 4) > count_zeros(Z, 4)) Z = M;
-        }
-        if (count_zeros(Z, 4) > count_zeros(S + i, 4))
-            for (int t = 0; t < 4; t++) S[i + t] = Z[t];
-    }
+    uint8_t *S = (uint8_t *)malloc((size_t)mT + 4);
+    shouji_steps(P, mP, T, mT, E, 4, reading, S);
     /* Step 3 with the counting mode: the range of positions whose ones count */
     int first = -1, last = -1;
     for (int j = 0; j < mT; j++)
@@ -238,7 +208,7 @@ int oracle_shouji_pair2(const uint8_t *P, int32_t mP, const uint8_t *T, int32_t 
     int ones = 0;
     for (int j = lo; j < hi; j++) ones += S[j];
     if (S_out) memcpy(S_out, S, (size_t)mT);
-    free(N); free(S);
+    free(S);
     return ones;
 }
 

@@ -55,6 +55,12 @@ def test_modes_remove_exactly_the_end_runs():
 
 
 def test_equal_lengths_global_is_the_plain_filter():
+    # Fig. 6(c) pins the diagonal order, the tie rule and the strict update of
+    # the two-length form (its stated local count of 2 comes out only with
+    # them).  With equal lengths and global counting the plain filter must be
+    # the same function, so that pin holds for the plain filter too: compare
+    # every vector, on pairs built to reach order-sensitive ties (a two-letter
+    # alphabet, tandem repeats, insertions and deletions).
     rng = np.random.default_rng(6)
     for m in (1, 4, 17, 100):
         for E in (0, 2, 5):
@@ -62,6 +68,32 @@ def test_equal_lengths_global_is_the_plain_filter():
             T = P.copy()
             T[rng.integers(0, m, 3)] = rng.integers(0, 4, 3)
             assert oracle.shouji_pair2(P, T, E, GLOBAL) == oracle.shouji_pair(P, T, E)
+    n, m = 4000, 60
+    P = np.zeros((n, m), np.uint8)
+    T = np.zeros((n, m), np.uint8)
+    for k in range(n):
+        alpha = 2 if k % 2 else 4
+        unit = rng.integers(0, alpha, int(rng.integers(1, 4)))
+        a = np.resize(unit, m) if k % 3 == 0 else rng.integers(0, alpha, m)
+        b = list(a)
+        for _ in range(int(rng.integers(0, 6))):
+            op, pos = int(rng.integers(0, 3)), int(rng.integers(0, len(b) + 1))
+            if op == 0 and pos < len(b):
+                b[pos] = int(rng.integers(0, alpha))
+            elif op == 1:
+                b.insert(pos, int(rng.integers(0, alpha)))
+            elif pos < len(b):
+                del b[pos]
+        b = (b + list(rng.integers(0, alpha, m)))[:m]
+        P[k], T[k] = a, b
+    L = np.full(n, m, np.int32)
+    for E in (1, 2, 3, 5, 8):
+        acc, pc = oracle.shouji_batch(P, T, L, E=E)
+        acc2, pc2 = oracle.shouji_batch2(P, T, L, L, E=E, mode=GLOBAL)
+        assert np.array_equal(pc, pc2) and np.array_equal(acc, acc2)
+    for k in range(0, n, 40):
+        for E in (2, 5):
+            assert oracle.shouji_pair2(P[k], T[k], E, GLOBAL) == oracle.shouji_pair(P[k], T[k], E)
 
 
 def test_read_embedded_in_reference_closed_form():
