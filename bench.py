@@ -54,6 +54,28 @@ def algorithmic_lane_ops_per_pair(m, E):
     return (per32 + unpack) / 32.0
 
 
+def planning_lane_ops_per_pair(m, E):
+    """The bit-sliced planning model of the method's work per pair: 26 lane-ops
+    per (window, candidate diagonal) and 15 per window for the bit-vector
+    update and count, per 32 pairs, plus 1.9 per pair-position to unpack (two
+    32x32 bit transposes per 16 positions): m*((2E+1)*26 + 15)/32 + 1.9*m.
+    m=100, E=5: 1130.6 lane-ops per pair."""
+    return m * ((2 * E + 1) * 26 + 15) / 32.0 + 1.9 * m
+
+
+def cpu_model():
+    """The host CPU's model name (first 'model name' of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def algorithmic_bytes_per_pair(m):
     """HBM bytes the method must move per pair: two 2-bit packed sequences,
     the length, the accept byte and the int16 popcount."""
@@ -214,7 +236,9 @@ def main():
     del acc2, pc2
 
     ops_pair = algorithmic_lane_ops_per_pair(m, E)
-    achieved_tops = ops_pair * n / (ms_per_step / 1e3) / 1e12
+    gate_tops = ops_pair * n / (ms_per_step / 1e3) / 1e12
+    plan_pair = planning_lane_ops_per_pair(m, E)
+    achieved_tops = plan_pair * n / (ms_per_step / 1e3) / 1e12
     workload_tag = "m%d_E%d_n%d" % (m, E, n)
     traffic = committed_traffic(workload_tag)
 
@@ -241,6 +265,10 @@ def main():
                      "ms_per_launch": ms_per_step,
                      "ms_per_launch_isolated": launch_ms,
                      "traffic": traffic,
+                     "model": "planning model m*((2E+1)*26+15)/32 + 1.9*m lane-ops per pair",
+                     "lane_ops_per_pair": plan_pair,
+                     "frac_gate_model": gate_tops / VALU_PEAK_TOPS,
+                     "achieved_gate_model": gate_tops,
                      "algorithmic_lane_ops_per_pair": ops_pair,
                      "hbm_algorithmic_GBs": algorithmic_bytes_per_pair(m) * value / 1e9,
                      "hbm_frac": algorithmic_bytes_per_pair(m) * value / 1e9 / HBM_PEAK_GBS,
@@ -265,10 +293,20 @@ def main():
         cpu_s = time.perf_counter() - tc
         ga = acc[:ns].cpu().numpy()
         gp = pc[:ns].cpu().numpy()
+        # one thread, on a tenth of that sample (about cpu_seconds / 10 * threads)
+        n1 = max(1000, min(ns, int(ns / cpu_s * args.cpu_seconds / 10 / max(threads, 1))))
+        tc = time.perf_counter()
+        oracle.shouji_batch(pairs.P[:n1], pairs.T[:n1], pairs.lengths[:n1], E=E, nthreads=1)
+        one_s = time.perf_counter() - tc
         out["cpu_baseline"] = {"value": ns / cpu_s, "unit": "pairs/s", "cores": threads,
                                "kind": "oracle",
                                "sample": "first %d pairs of the same batch (%.1f s on %d threads)"
-                                         % (ns, cpu_s, threads)}
+                                         % (ns, cpu_s, threads),
+                               "value_1thread": n1 / one_s,
+                               "sample_1thread": "first %d pairs (%.1f s on 1 thread)" % (n1, one_s),
+                               "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+                               "compiler": oracle.compiler(),
+                               "timed": "filter loop only (no generation, no I/O), one run"}
         out["parity_mismatches"] = int(((ga != ea) | (gp != ep)).sum())
         out["parity_sample"] = ns
     if not args.no_batched:
@@ -292,9 +330,11 @@ def bench_batched(n, dev, steps=20, with_oracle=True):
     """Batched form on a mixed workload: n pairs, lengths uniform in 64..300,
     per-pair E_p = floor(r*m) with r uniform in [0, 0.10] (seed 3000), unsorted.
     One step = one shouji_filter_batched call (binning, scatter, filter), inputs
-    resident.  Compared with plain launches, one per (length, E) group of the
-    same pairs (pre-grouped outside the timed region, all launches replayed from
-    one captured graph), which must give identical outputs."""
+    resident; timed as eager calls and as replays of one captured graph.
+    Compared with the plain form on the same pairs: one plain launch per
+    threshold E (lengths passed, max_len 300; the pairs pre-grouped by E outside
+    the timed region, the launches replayed from one captured graph), which must
+    give identical outputs.  With the oracle: every pair compared."""
     import numpy as np
     import torch
     import paper_1809_07858_amd as sj
@@ -321,64 +361,115 @@ def bench_batched(n, dev, steps=20, with_oracle=True):
                                  stream=stream)
     e1.record(stream)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
+    eager_ms = e0.elapsed_time(e1) / steps
+    eager_acc, eager_pc = acc.clone(), pc.clone()
 
-    # plain launches, one per (length, E) group
-    key = pairs.lengths.astype(np.int64) * 64 + pairs.E
-    order = np.argsort(key, kind="stable")
-    ks, starts = np.unique(key[order], return_index=True)
+    # one call captured in a graph, replayed
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        sj.shouji_filter_batched(reads, refs, lens, Ep, acc, pc, max_len=max_len, workspace=ws,
+                                 stream=side)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        sj.shouji_filter_batched(reads, refs, lens, Ep, acc, pc, max_len=max_len, workspace=ws,
+                                 stream=torch.cuda.current_stream())
+    acc.fill_(0xEE)
+    pc.fill_(-7)
+    g.replay()
+    torch.cuda.synchronize()
+    graph_same = bool(torch.equal(acc, eager_acc) and torch.equal(pc, eager_pc))
+    e0.record(stream)
+    for _ in range(steps):
+        g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    graph_same = graph_same and bool(torch.equal(acc, eager_acc) and torch.equal(pc, eager_pc))
+    del g
+
+    # the plain form, one launch per threshold E with the lengths passed
+    order = np.argsort(pairs.E, kind="stable")
+    es, starts = np.unique(pairs.E[order], return_index=True)
     bounds = list(starts) + [n]
     order_t = torch.from_numpy(order).to(dev)
     g_reads = reads[:, order_t].contiguous()
     g_refs = refs[:, order_t].contiguous()
+    g_lens = lens[order_t].contiguous()
     g_acc = torch.empty(n, dtype=torch.uint8, device=dev)
     g_pc = torch.empty(n, dtype=torch.int16, device=dev)
-    groups = []
-    for gi, kv in enumerate(ks):
+    views = []
+    for gi, e in enumerate(es):
         lo, hi = int(bounds[gi]), int(bounds[gi + 1])
-        m, e = int(kv // 64), int(kv % 64)
-        groups.append((lo, hi, m, e))
-    views = [(g_reads[:, lo:hi].contiguous(), g_refs[:, lo:hi].contiguous(), lo, hi, m, e)
-             for lo, hi, m, e in groups]
+        views.append((g_reads[:, lo:hi].contiguous(), g_refs[:, lo:hi].contiguous(),
+                      g_lens[lo:hi].contiguous(), lo, hi, int(e)))
+    del g_reads, g_refs
+
+    # the launches go round-robin to four streams (largest E first), so that
+    # launches of different E run side by side and fill the chip
+    views.sort(key=lambda v: -v[5])
+    subs = [torch.cuda.Stream() for _ in range(4)]
 
     def plain_all(st):
-        for r_, t_, lo, hi, m, e in views:
-            sj.shouji_filter(r_, t_, None, e, g_acc[lo:hi], g_pc[lo:hi], n_pairs=hi - lo,
-                             max_len=m, stream=st)
+        for q in subs:
+            q.wait_stream(st)
+        for i, (r_, t_, l_, lo, hi, e) in enumerate(views):
+            q = subs[i % len(subs)]
+            with torch.cuda.stream(q):
+                sj.shouji_filter(r_, t_, l_, e, g_acc[lo:hi], g_pc[lo:hi], n_pairs=hi - lo,
+                                 max_len=max_len, stream=q)
+        for q in subs:
+            st.wait_stream(q)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
         plain_all(side)
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
+    pg = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(pg):
         plain_all(torch.cuda.current_stream())
-    graph.replay()
+    pg.replay()
     torch.cuda.synchronize()
+    reps = 10
     e0.record(stream)
-    reps = 3
     for _ in range(reps):
-        graph.replay()
+        pg.replay()
     e1.record(stream)
     torch.cuda.synchronize()
     plain_ms = e0.elapsed_time(e1) / reps
     same = int((acc[order_t] != g_acc).sum().item() + (pc[order_t] != g_pc).sum().item())
+    del pg, views
+    # planning-model lane-ops of every pair (its own m and E)
+    ops = float(planning_lane_ops_per_pair(pairs.lengths.astype(np.float64),
+                                           pairs.E.astype(np.float64)).sum())
+    tops = ops / (ms / 1e3) / 1e12
     out = {"workload": "%d pairs, lengths uniform 64..300, E_p=floor(r*m) r~U[0,0.10], "
                        "unsorted, seed 3000" % n,
-           "value": n / (ms / 1e3), "unit": "pairs/s", "ms_per_step": ms,
+           "value": n / (ms / 1e3), "unit": "pairs/s", "ms_per_step": ms, "timed": "graph replay",
+           "eager_ms_per_step": eager_ms, "graph_equals_eager": graph_same,
            "tuned_config": {"bin_width": bw, "waves_per_group": wpg}, "tune_ms": tune_ms,
-           "plain_per_group_value": n / (plain_ms / 1e3), "plain_groups": len(groups),
-           "plain_ms": plain_ms, "vs_plain": plain_ms / ms, "mismatches_vs_plain": same,
+           "roofline": {"bound": "alu", "achieved": tops, "peak": VALU_PEAK_TOPS,
+                        "unit": "Tlane-op/s (32-bit integer VALU)", "frac": tops / VALU_PEAK_TOPS,
+                        "model": "planning model per pair at its own m and E_p",
+                        "lane_ops_per_pair_mean": ops / n},
+           "plain_per_E_value": n / (plain_ms / 1e3), "plain_launches": len(es),
+           "plain_per_E_ms": plain_ms, "vs_plain": plain_ms / ms, "mismatches_vs_plain": same,
+           "plain_baseline": "one plain launch per E (lengths passed, max_len 300) on the same "
+                             "pairs grouped by E, spread over four streams, replayed from one "
+                             "captured graph",
            "accept_rate": float(acc.float().mean().item())}
     if with_oracle:
-        # the full-size batch against the oracle on a strided sample
+        # the full-size batch against the oracle, every pair
         import oracle
-        idx = np.arange(0, n, 151)
-        ea, ep = oracle.shouji_batch(pairs.P[idx], pairs.T[idx], pairs.lengths[idx], E_per_pair=pairs.E[idx])
-        ga, gp = acc.cpu().numpy()[idx], pc.cpu().numpy()[idx]
-        out["mismatches_vs_oracle_sample"] = int(((ga != ea) | (gp != ep)).sum())
-        out["oracle_sample"] = "every 151st pair (%d)" % idx.size
+        tc = time.perf_counter()
+        ea, ep = oracle.shouji_batch(pairs.P, pairs.T, pairs.lengths, E_per_pair=pairs.E)
+        out["oracle_s"] = time.perf_counter() - tc
+        ga, gp = acc.cpu().numpy(), pc.cpu().numpy()
+        out["mismatches_vs_oracle"] = int(((ga != ea) | (gp != ep)).sum())
+        out["oracle_compared"] = n
     return out
 
 
@@ -778,6 +869,25 @@ def bench_serving(dev, total_pairs, batch_pairs, slots, distinct=1_000_000, load
     half = run("packed", load=0.5)
     res["packed_load_0.5"] = {k: half[k] for k in ("value", "p50_ms", "p99_ms", "mean_ms", "max_ms",
                                                    "offered_pairs_per_s", "load", "peak_pairs_per_s")}
+    # what the host link gives: a 512 MiB pinned host-to-device copy
+    hsrc = torch.empty(1 << 27, dtype=torch.int32, pin_memory=True)
+    ddst = torch.empty(1 << 27, dtype=torch.int32, device=dev)
+    ddst.copy_(hsrc, non_blocking=True)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(5):
+        ddst.copy_(hsrc, non_blocking=True)
+    c1.record()
+    torch.cuda.synchronize()
+    h2d_peak = 5 * hsrc.numel() * 4 / (c0.elapsed_time(c1) / 1e3) / 1e9
+    del hsrc, ddst
+    res["load_basis"] = ("load = offered rate / this server's own burst peak in the same run (the "
+                         "whole stream submitted at once); the burst peak is bound by the host "
+                         "link, not by the batched kernels")
+    res["h2d_GBs_peak_burst"] = res["peak_pairs_per_s"] * res["host_bytes_per_pair"] / 1e9
+    res["h2d_GBs_poisson"] = res["value"] * res["host_bytes_per_pair"] / 1e9
+    res["h2d_GBs_pinned_copy"] = h2d_peak
     res.update({"workload": "Poisson stream of %d requests, %d pairs in all, request size "
                             "U{1..200000}, lengths uniform 64..300, E_p=floor(r*m) r~U[0,0.10], "
                             "2 GiB device-resident packed reference pool (8 Gi bases), seed %d; "

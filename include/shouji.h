@@ -154,7 +154,10 @@ typedef struct {
 } shouji_batched_config;
 
 /* Workspace bytes shouji_filter_batched needs for n_pairs pairs of at most
- * max_len bases (any config); negative status on bad arguments. */
+ * max_len bases (any config); negative status on bad arguments.  The binning
+ * indexes pairs in 32 bits: n_pairs above SHOUJI_MAX_BATCHED_PAIRS is
+ * SHOUJI_ERR_RANGE here and in shouji_filter_batched. */
+#define SHOUJI_MAX_BATCHED_PAIRS 2147483647LL
 int64_t shouji_batched_workspace_bytes(int64_t n_pairs, int32_t max_len);
 
 int shouji_filter_batched(const uint32_t *reads, const uint32_t *refs, const int32_t *lengths,
@@ -305,6 +308,9 @@ typedef struct {
                                    an invalid pair                                     */
     int64_t n_pairs;            /* >= 0                                                */
     uint32_t flags;             /* SHOUJI_REQUEST_* bits                               */
+    int64_t read_words;         /* SHOUJI_REQUEST_PACKED: words the `reads` buffer
+                                   holds; submit checks it against the lengths (see
+                                   there).  Ignored for reads in rows.                */
 } shouji_request;
 
 /* The request's buffers are pinned host memory (hipHostMalloc): when its read
@@ -317,8 +323,9 @@ typedef struct {
  * ceil(m_p/16) words, none when m_p lies outside [1, max_len], and begins
  * where read p-1 ends, so `reads` holds the sum of these counts.  The server
  * moves only these words to the device (a read of m bases costs ceil(m/16)
- * words on the host link instead of ceil(max_len/16)).  The server trusts the
- * count: a shorter buffer is read past its end. */
+ * words on the host link instead of ceil(max_len/16)).  The request states the
+ * buffer's size in read_words; submit sums the counts from the lengths and
+ * returns SHOUJI_ERR_ARG, queueing nothing, when read_words is smaller. */
 #define SHOUJI_REQUEST_PACKED 2u
 
 typedef struct {
@@ -341,7 +348,8 @@ int shouji_server_create(const shouji_server_config *config, shouji_server **out
 
 /* Queue a request and return its ticket.  The request's buffers are read and
  * written by the server until shouji_server_wait returns for this ticket; the
- * caller keeps them alive and untouched until then.  A pair whose length lies
+ * caller keeps them alive and untouched until then.  Submit reads the lengths
+ * once (a packed request's word count is checked against them).  A pair whose length lies
  * outside [0, max_len], whose segment is not inside the pool, whose E is
  * negative or, after clamping to m-1, above SHOUJI_MAX_E gets the sentinels. */
 int shouji_server_submit(shouji_server *server, const shouji_request *request, uint64_t *ticket);

@@ -30,15 +30,29 @@ GLOCAL_START = 2    # without the run of ones before the first zero
 GLOCAL_END = 3      # without the run of ones after the last zero
 
 
+CC = "gcc"
+CFLAGS = ["-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11"]
+
+
 def build():
     """Compile the oracle's C sources into _build/liboracle.so (gcc -O2, OpenMP)."""
     os.makedirs(os.path.dirname(_SO), exist_ok=True)
     tmp = _SO + ".tmp%d" % os.getpid()
-    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-                           os.path.join(_HERE, "shouji_oracle.c"),
+    subprocess.check_call([CC] + CFLAGS +
+                          [os.path.join(_HERE, "shouji_oracle.c"),
                            os.path.join(_HERE, "levenshtein.c"),
                            os.path.join(_HERE, "magnet_oracle.c"), "-o", tmp])
     os.replace(tmp, _SO)
+
+
+def compiler():
+    """The compiler and flags the oracle library is built with, e.g. for a
+    benchmark record: 'gcc (Ubuntu 11.4.0-1ubuntu1~22.04) 11.4.0 -O2 -fopenmp ...'."""
+    try:
+        ver = subprocess.run([CC, "--version"], capture_output=True, text=True).stdout.splitlines()[0]
+    except (OSError, IndexError):
+        ver = CC
+    return "%s %s" % (ver, " ".join(CFLAGS))
 
 
 def _load():

@@ -39,7 +39,7 @@ class Request(ctypes.Structure):
     _fields_ = [("reads", ctypes.c_void_p), ("words_per_read", ctypes.c_int32),
                 ("ref_offsets", ctypes.c_void_p), ("lengths", ctypes.c_void_p), ("E", ctypes.c_void_p),
                 ("out_accept", ctypes.c_void_p), ("out_popcount", ctypes.c_void_p),
-                ("n_pairs", ctypes.c_int64), ("flags", ctypes.c_uint32)]
+                ("n_pairs", ctypes.c_int64), ("flags", ctypes.c_uint32), ("read_words", ctypes.c_int64)]
 
 
 REQUEST_PINNED = 1
@@ -546,7 +546,8 @@ class Server:
         req = Request(reads.ctypes.data, 1 if packed else max(1, reads.shape[1]), offs.ctypes.data,
                       lens.ctypes.data, Ep.ctypes.data, acc.ctypes.data,
                       None if pc is None else pc.ctypes.data, n,
-                      (REQUEST_PINNED if pinned else 0) | (REQUEST_PACKED if packed else 0))
+                      (REQUEST_PINNED if pinned else 0) | (REQUEST_PACKED if packed else 0),
+                      reads.size if packed else 0)
         t = ctypes.c_uint64()
         _check(lib().shouji_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
         return Ticket(t.value, (reads, offs, lens, Ep), acc, pc)

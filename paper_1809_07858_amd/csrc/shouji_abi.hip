@@ -246,6 +246,9 @@ shouji_batched_config resolve_config(const shouji_batched_config *cfg, int64_t n
 
 extern "C" int64_t shouji_batched_workspace_bytes(int64_t n_pairs, int32_t max_len) {
     if (n_pairs < 0) return fail(SHOUJI_ERR_ARG, "n_pairs < 0");
+    if (n_pairs > SHOUJI_MAX_BATCHED_PAIRS)
+        return fail(SHOUJI_ERR_RANGE, "n_pairs %lld above the batched form's limit %lld", (long long)n_pairs,
+                    (long long)SHOUJI_MAX_BATCHED_PAIRS);
     if (max_len < 0 || max_len > SHOUJI_MAX_LEN)
         return fail(SHOUJI_ERR_RANGE, "max_len %d outside [0, %d]", max_len, SHOUJI_MAX_LEN);
     ok();
@@ -261,6 +264,10 @@ extern "C" int shouji_filter_batched(const uint32_t *reads, const uint32_t *refs
     if (n_pairs < 0) return fail(SHOUJI_ERR_ARG, "n_pairs < 0 (%lld)", (long long)n_pairs);
     if (max_len < 0 || max_len > SHOUJI_MAX_LEN)
         return fail(SHOUJI_ERR_RANGE, "max_len %d outside [0, %d]", max_len, SHOUJI_MAX_LEN);
+    // bin counts, cursors within a bin and tile starts are 32-bit
+    if (n_pairs > SHOUJI_MAX_BATCHED_PAIRS)
+        return fail(SHOUJI_ERR_RANGE, "n_pairs %lld above the batched form's limit %lld", (long long)n_pairs,
+                    (long long)SHOUJI_MAX_BATCHED_PAIRS);
     if (n_pairs == 0) return ok();
     if (!reads || !refs || !E_per_pair || !out_accept || !workspace)
         return fail(SHOUJI_ERR_NULL, "reads, refs, E_per_pair, out_accept and workspace are required");

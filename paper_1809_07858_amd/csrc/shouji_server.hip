@@ -549,6 +549,19 @@ extern "C" int shouji_server_submit(shouji_server *S, const shouji_request *r, u
             return set_error(SHOUJI_ERR_NULL, "shouji_server_submit: request buffer missing");
         if (!(r->flags & SHOUJI_REQUEST_PACKED) && r->words_per_read <= 0)
             return set_error(SHOUJI_ERR_ARG, "shouji_server_submit: words_per_read must be positive");
+        if (r->flags & SHOUJI_REQUEST_PACKED) {
+            // the words the lengths say the buffer holds, before anything is queued
+            const int ml = S->cfg.max_len;
+            int64_t need = 0;
+            for (int64_t p = 0; p < r->n_pairs; p++) {
+                const int32_t m = r->lengths[p];
+                if (m >= 1 && m <= ml) need += (m + SHOUJI_BASES_PER_WORD - 1) / SHOUJI_BASES_PER_WORD;
+            }
+            if (r->read_words < need)
+                return set_error(SHOUJI_ERR_ARG,
+                                 "shouji_server_submit: packed reads hold %lld words, the lengths need %lld",
+                                 (long long)r->read_words, (long long)need);
+        }
     }
     std::unique_ptr<Request> R(new Request());
     R->req = *r;

@@ -127,3 +127,23 @@ def test_packed_read_layout():
     for p in range(9):
         assert np.array_equal(words[off[p]:off[p + 1]], rows[p, :k[p]])
     assert list(sj.packed_read_words(lens, 70)) == k
+
+
+def test_batched_pair_count_limit():
+    # the binning indexes pairs in 32 bits: above 2^31 - 1 pairs the batched
+    # form refuses the call before anything is enqueued
+    L = sj.lib()
+    big = 1 << 31
+    assert L.shouji_batched_workspace_bytes(big, 300) == -3
+    assert b"limit" in L.shouji_last_error()
+    assert L.shouji_batched_workspace_bytes(big - 1, 16) > 0
+    vp = ctypes.c_void_p(16)
+    rc = L.shouji_filter_batched(vp, vp, None, vp, vp, None, big, 300, big, vp, 1 << 40, None, None)
+    assert rc == -3
+
+
+def test_request_struct_carries_the_packed_word_count():
+    # read_words sits after flags (8-byte aligned): the struct is 80 bytes
+    assert sj.Request.flags.offset == 64
+    assert sj.Request.read_words.offset == 72
+    assert ctypes.sizeof(sj.Request) == 80

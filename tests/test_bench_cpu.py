@@ -64,3 +64,19 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_planning_model():
+    # m*((2E+1)*26 + 15)/32 + 1.9*m lane-ops per pair: m=100, E=5 -> 1130.625
+    assert bench.planning_lane_ops_per_pair(100, 5) == pytest.approx(100 * 301 / 32 + 190)
+    assert bench.planning_lane_ops_per_pair(100, 5) == pytest.approx(1130.625)
+    # E=0 and m=250, E=25
+    assert bench.planning_lane_ops_per_pair(100, 0) == pytest.approx(100 * 41 / 32 + 190)
+    assert bench.planning_lane_ops_per_pair(250, 25) == pytest.approx(250 * (51 * 26 + 15) / 32 + 475)
+    # the 57 us per 2M pairs that a half of the peak means at the headline
+    t = bench.planning_lane_ops_per_pair(100, 5) * 2_000_000 / (0.5 * bench.VALU_PEAK_TOPS * 1e12)
+    assert t == pytest.approx(57.5e-6, rel=1e-2)
+
+
+def test_cpu_model_is_reported():
+    assert isinstance(bench.cpu_model(), str) and bench.cpu_model()

@@ -267,6 +267,18 @@ def test_packed_reads_with_invalid_and_empty_lengths(sj, work):
         acc, pc, _ = srv.wait(srv.submit(words, work["off"][lo:hi], lens, p.E[lo:hi], packed=True))
         with pytest.raises(ValueError):
             srv.submit(words[:-1], work["off"][lo:hi], lens, p.E[lo:hi], packed=True)
+        # the library's own check, past the binding's: a word count short of
+        # what the lengths need is refused and nothing is queued
+        import ctypes
+        offs = np.ascontiguousarray(work["off"][lo:hi], dtype=np.int64)
+        Ep = np.ascontiguousarray(p.E[lo:hi], dtype=np.int32)
+        oa = np.empty(hi - lo, np.uint8)
+        req = sj.Request(words.ctypes.data, 1, offs.ctypes.data, lens.ctypes.data, Ep.ctypes.data,
+                         oa.ctypes.data, None, hi - lo, sj.REQUEST_PACKED, words.size - 1)
+        t = ctypes.c_uint64()
+        assert sj.lib().shouji_server_submit(srv._h, ctypes.byref(req), ctypes.byref(t)) == -2
+        assert b"packed reads hold" in sj.lib().shouji_last_error()
+        assert srv.stats()["queued_pairs"] == 0
     bad = (lens < 0) | (lens > MAX_LEN)
     assert (acc[bad] == 0xFF).all() and (pc[bad] == -1).all()
     good = ~bad
