@@ -180,6 +180,35 @@ int shouji_tune_batched(const uint32_t *reads, const uint32_t *refs, const int32
                         float *best_ms);
 
 /*
+ * Batched form that allocates nothing and takes no workspace.
+ *
+ * For callers that cannot allocate device memory: code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Filter, arguments,
+ * results, sentinels and errors as for shouji_filter_batched; the binned copy
+ * of the pairs lives in a device array owned by the library, of
+ * SHOUJI_NOALLOC_SCRATCH_BYTES bytes, one per GPU the library runs on, held
+ * until the process ends.  The call allocates nothing (no hipMalloc, no
+ * allocating library routine).
+ *
+ *   n_pairs, max_len  the binned copy must fit the array:
+ *                 shouji_batched_workspace_bytes(n_pairs, max_len) <=
+ *                 SHOUJI_NOALLOC_SCRATCH_BYTES (about 780,000 pairs at
+ *                 max_len 300, 1.8 million at max_len 100), else
+ *                 SHOUJI_ERR_RANGE before anything is enqueued.
+ *   Concurrency   every call on one GPU shares that GPU's array, which keeps
+ *                 the last call's contents: calls that overlap on one GPU
+ *                 (other streams, other threads) race and must be ordered by
+ *                 the caller.  Counters the binning needs are cleared by its
+ *                 own kernels in every call.
+ */
+#define SHOUJI_NOALLOC_SCRATCH_BYTES (128LL << 20)
+
+int shouji_filter_batched_noalloc(const uint32_t *reads, const uint32_t *refs, const int32_t *lengths,
+                                  const int32_t *E_per_pair, uint8_t *out_accept, int16_t *out_popcount,
+                                  int64_t n_pairs, int32_t max_len, int64_t ld,
+                                  const shouji_batched_config *config, void *stream);
+
+/*
  * Window-width variant: W-column search windows instead of 4.
  *
  * Suppl. Sec. 6.1 and Fig. 4 compare the accuracy of window widths (4 is the

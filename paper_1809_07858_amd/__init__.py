@@ -77,6 +77,8 @@ def lib():
         L.shouji_batched_workspace_bytes.argtypes = [i64, i32]
         L.shouji_filter_batched.restype = ctypes.c_int
         L.shouji_filter_batched.argtypes = [vp, vp, vp, vp, vp, vp, i64, i32, i64, vp, i64, vp, vp]
+        L.shouji_filter_batched_noalloc.restype = ctypes.c_int
+        L.shouji_filter_batched_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, i64, i32, i64, vp, vp]
         L.shouji_tune_batched.restype = ctypes.c_int
         L.shouji_tune_batched.argtypes = [vp, vp, vp, vp, vp, vp, i64, i32, i64, vp, i64, vp, vp, vp]
         L.shouji_server_slot_bytes.restype = ctypes.c_int64
@@ -352,7 +354,7 @@ def batched_workspace_bytes(n_pairs, max_len):
 
 
 def _batched_args(reads, refs, lengths, E_per_pair, out_accept, out_popcount, n_pairs, max_len,
-                  workspace, want_popcount):
+                  workspace, want_popcount, with_workspace=True):
     import torch
     if reads.dim() != 2 or refs.shape != reads.shape:
         raise ValueError("reads/refs must be [nwords, ld] tensors of the same shape")
@@ -376,17 +378,19 @@ def _batched_args(reads, refs, lengths, E_per_pair, out_accept, out_popcount, n_
         out_accept = torch.empty(n_pairs, dtype=torch.uint8, device=dev)
     if out_popcount is None and want_popcount:
         out_popcount = torch.empty(n_pairs, dtype=torch.int16, device=dev)
+    args = [ctypes.c_void_p(reads.data_ptr()), ctypes.c_void_p(refs.data_ptr()),
+            None if lengths is None else ctypes.c_void_p(lengths.data_ptr()),
+            ctypes.c_void_p(E_per_pair.data_ptr()), ctypes.c_void_p(out_accept.data_ptr()),
+            None if out_popcount is None else ctypes.c_void_p(out_popcount.data_ptr()),
+            int(n_pairs), int(max_len), int(ld)]
+    if not with_workspace:
+        return args, out_accept, out_popcount, None
     need = batched_workspace_bytes(n_pairs, max_len)
     if workspace is None:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
     if workspace.numel() * workspace.element_size() < need:
         raise ValueError("workspace too small: %d bytes needed" % need)
-    args = [ctypes.c_void_p(reads.data_ptr()), ctypes.c_void_p(refs.data_ptr()),
-            None if lengths is None else ctypes.c_void_p(lengths.data_ptr()),
-            ctypes.c_void_p(E_per_pair.data_ptr()), ctypes.c_void_p(out_accept.data_ptr()),
-            None if out_popcount is None else ctypes.c_void_p(out_popcount.data_ptr()),
-            int(n_pairs), int(max_len), int(ld), ctypes.c_void_p(workspace.data_ptr()),
-            int(workspace.numel() * workspace.element_size())]
+    args += [ctypes.c_void_p(workspace.data_ptr()), int(workspace.numel() * workspace.element_size())]
     return args, out_accept, out_popcount, workspace
 
 
@@ -401,6 +405,25 @@ def shouji_filter_batched(reads, refs, lengths, E_per_pair, out_accept=None, out
     if config is not None:
         cfg = ctypes.byref(BatchedConfig(int(config[0]), int(config[1])))
     _check(lib().shouji_filter_batched(*args, cfg, _stream_handle(stream)))
+    return out_accept, out_popcount
+
+
+NOALLOC_SCRATCH_BYTES = 128 << 20   # SHOUJI_NOALLOC_SCRATCH_BYTES
+
+
+def shouji_filter_batched_noalloc(reads, refs, lengths, E_per_pair, out_accept=None, out_popcount=None,
+                                  n_pairs=None, max_len=None, config=None, stream=None,
+                                  want_popcount=True):
+    """Batched form without a workspace: the library's own scratch array holds the
+    binned copy (at most NOALLOC_SCRATCH_BYTES; see include/shouji.h).  With the
+    outputs passed in, nothing is allocated on the way to the library."""
+    args, out_accept, out_popcount, _ = _batched_args(
+        reads, refs, lengths, E_per_pair, out_accept, out_popcount, n_pairs, max_len, None,
+        want_popcount, with_workspace=False)
+    cfg = None
+    if config is not None:
+        cfg = ctypes.byref(BatchedConfig(int(config[0]), int(config[1])))
+    _check(lib().shouji_filter_batched_noalloc(*args, cfg, _stream_handle(stream)))
     return out_accept, out_popcount
 
 

@@ -438,3 +438,63 @@ extern "C" int shouji_tune_batched(const uint32_t *reads, const uint32_t *refs, 
     if (best_ms) *best_ms = top_ms;
     return ok();
 }
+
+// ------------------------------------------- batched form without allocation
+
+namespace {
+
+// The binned copy of shouji_filter_batched_noalloc: a device array owned by
+// the library (each GPU the library runs on holds its own copy until the
+// process ends).  In host code `noalloc_scratch` names a host-side stand-in,
+// never the device memory: the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+__device__ __align__(256) unsigned char noalloc_scratch[SHOUJI_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;   // device ordinal -> address of its copy
+
+int scratch_address(void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return fail(SHOUJI_ERR_DEVICE, "no current HIP device: %s", hipGetErrorString(hipGetLastError()));
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+        if (e != hipSuccess || p == nullptr)
+            return fail(SHOUJI_ERR_DEVICE, "cannot locate the scratch array on device %d: %s", dev,
+                        hipGetErrorString(e));
+        it = g_scratch_ptr.emplace(dev, p).first;
+    }
+    *out = it->second;
+    return SHOUJI_OK;
+}
+
+}  // namespace
+
+extern "C" int shouji_filter_batched_noalloc(const uint32_t *reads, const uint32_t *refs,
+                                             const int32_t *lengths, const int32_t *E_per_pair,
+                                             uint8_t *out_accept, int16_t *out_popcount, int64_t n_pairs,
+                                             int32_t max_len, int64_t ld,
+                                             const shouji_batched_config *config, void *stream) {
+    // sizes first: nothing here touches the device before they are accepted
+    if (n_pairs < 0) return fail(SHOUJI_ERR_ARG, "n_pairs < 0 (%lld)", (long long)n_pairs);
+    if (max_len < 0 || max_len > SHOUJI_MAX_LEN)
+        return fail(SHOUJI_ERR_RANGE, "max_len %d outside [0, %d]", max_len, SHOUJI_MAX_LEN);
+    if (n_pairs > SHOUJI_MAX_BATCHED_PAIRS)
+        return fail(SHOUJI_ERR_RANGE, "n_pairs %lld above the batched form's limit %lld", (long long)n_pairs,
+                    (long long)SHOUJI_MAX_BATCHED_PAIRS);
+    if (n_pairs == 0) return ok();
+    const int64_t need = (int64_t)shouji::batched_layout(n_pairs, max_len, shouji::kMinBinWidth).total;
+    if (need > SHOUJI_NOALLOC_SCRATCH_BYTES)
+        return fail(SHOUJI_ERR_RANGE,
+                    "%lld pairs of up to %d bases need %lld bytes of scratch, the library holds %lld: "
+                    "call shouji_filter_batched with a workspace instead",
+                    (long long)n_pairs, max_len, (long long)need, (long long)SHOUJI_NOALLOC_SCRATCH_BYTES);
+    void *ws = nullptr;
+    if (int rc = scratch_address(&ws)) return rc;
+    // the same binning, scatter and tile kernels as the call with a workspace
+    return shouji_filter_batched(reads, refs, lengths, E_per_pair, out_accept, out_popcount, n_pairs, max_len,
+                                 ld, ws, SHOUJI_NOALLOC_SCRATCH_BYTES, config, stream);
+}

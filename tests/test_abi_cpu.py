@@ -147,3 +147,17 @@ def test_request_struct_carries_the_packed_word_count():
     assert sj.Request.flags.offset == 64
     assert sj.Request.read_words.offset == 72
     assert ctypes.sizeof(sj.Request) == 80
+
+
+def test_noalloc_batched_refuses_sizes_beyond_its_scratch():
+    # sizes are checked before the device is touched: more pairs than the
+    # library's scratch array holds is SHOUJI_ERR_RANGE, naming the limit
+    L = sj.lib()
+    vp = ctypes.c_void_p(16)
+    n = 2_000_000
+    assert sj.batched_workspace_bytes(n, 300) > sj.NOALLOC_SCRATCH_BYTES
+    assert L.shouji_filter_batched_noalloc(vp, vp, None, vp, vp, None, n, 300, n, None, None) == -3
+    assert b"scratch" in L.shouji_last_error()
+    assert L.shouji_filter_batched_noalloc(vp, vp, None, vp, vp, None, -1, 300, 0, None, None) == -2
+    assert L.shouji_filter_batched_noalloc(vp, vp, None, vp, vp, None, 10, 5000, 10, None, None) == -3
+    assert L.shouji_filter_batched_noalloc(None, None, None, None, None, None, 0, 300, 0, None, None) == 0
