@@ -259,8 +259,10 @@ int shouji_filter_magnet(const uint32_t *reads, const uint32_t *refs, const int3
  * the filter in front of aligners).  This computes, on the GPU, the
  * unit-cost global edit distance of read and reference (equal lengths) for
  * the pairs with filter_accept[p] == 1 (every pair when filter_accept is
- * NULL), by the textbook recurrence restricted to the band |i - j| <= K,
- * K >= E (exact for the test "distance <= E").
+ * NULL), on the band |i - j| <= E (exact for the test "distance <= E": a path
+ * that leaves the band has more than E indels), with the bit-vector
+ * recurrence of Myers (1999) over a diagonal band of 32 rows (E <= 15) or 64
+ * rows (E <= 31) per pair.
  *
  *   reads, refs, lengths, ld, max_len, n_pairs, stream: as for shouji_filter.
  *   E             threshold, 0..SHOUJI_MAX_E (else SHOUJI_ERR_ARG / _RANGE).

@@ -271,10 +271,12 @@ __global__ __launch_bounds__(kScatterThreads) void bin_scatter_lds_kernel(Scatte
     int rows[PER];
 #pragma unroll
     for (int i = 0; i < PER; i++) rows[i] = bin[i] >= 0 ? ((bin[i] / kBinE) * prm.bw + kHalf - 1) / kHalf : 0;
-    // rows of both sequences in turn; the loads of the next row are issued
-    // before the current one goes through LDS, so their latency overlaps it
+    // rows of both sequences in turn; the loads of the next three rows are in
+    // flight while the current one goes through LDS, so that the latency of
+    // HBM under load is covered (one row ahead left each workgroup waiting on
+    // its loads for most of every row)
     const int nrows = 2 * nw;
-    uint32_t cur[PER], nxt[PER];
+    uint32_t cur[PER], n1[PER], n2[PER], n3[PER];
     auto load_row = [&](int r, uint32_t (&v)[PER]) {
         const int w = r < nw ? r : r - nw;
         const uint32_t *in = r < nw ? prm.reads : prm.refs;
@@ -283,10 +285,12 @@ __global__ __launch_bounds__(kScatterThreads) void bin_scatter_lds_kernel(Scatte
             v[i] = w < rows[i] ? in[(int64_t)w * prm.ld + c0 + tid + (int64_t)i * kScatterThreads] : 0u;
     };
     if (nrows > 0) load_row(0, cur);
+    if (nrows > 1) load_row(1, n1);
+    if (nrows > 2) load_row(2, n2);
     for (int r = 0; r < nrows; r++) {
         const int w = r < nw ? r : r - nw;
         uint32_t *outp = r < nw ? prm.breads : prm.brefs;
-        if (r + 1 < nrows) load_row(r + 1, nxt);
+        if (r + 3 < nrows) load_row(r + 3, n3);
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < PER; i++)
@@ -298,7 +302,11 @@ __global__ __launch_bounds__(kScatterThreads) void bin_scatter_lds_kernel(Scatte
                 outp[(int64_t)w * prm.bld + gbase[b] + (q - loff[b])] = buf[q];
         }
 #pragma unroll
-        for (int i = 0; i < PER; i++) cur[i] = nxt[i];
+        for (int i = 0; i < PER; i++) {
+            cur[i] = n1[i];
+            n1[i] = n2[i];
+            n2[i] = n3[i];
+        }
     }
 }
 

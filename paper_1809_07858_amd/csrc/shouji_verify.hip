@@ -3,32 +3,45 @@
 //
 // The filter's purpose (Sec. 1, Sec. 3.3, Table 3) is to spare the aligner
 // the pairs it rejects; this is that aligner's threshold test on the GPU.
-// For each pair to verify, the unit-cost global edit distance between read
-// and reference is computed with the textbook recurrence restricted to the
-// band |i - j| <= K around the main diagonal (Ukkonen), K >= E chosen from a
-// few compiled band widths: a path leaving the band has more than K >= E
-// indels, so the band decides "distance <= E" exactly, and the distance
-// itself when it is <= E.
+// For each pair to verify, the unit-cost global edit distance D[m][m] of read
+// P and reference T is computed on a diagonal band |i - j| <= K, K = E
+// (Ukkonen): a path leaving the band has more than K indels, so the band
+// decides "distance <= E" exactly, and gives the distance when it is <= E.
 //
-// Layout: one pair per lane.  Pairs to verify are first collected into a
-// list (an atomic counter in the caller's workspace; the order does not
-// matter, results go to each pair's own index), so that a wavefront holds
-// only pairs that need work.  Per lane the band's cells of one row live in
-// registers, and the reference window T[i-K-1 .. i+K-1] is a shift register
-// of 2-bit codes, from which one XOR and a fold give the match bits of all
-// cells of the row.
+// The band is computed column by column (one reference base per step) with
+// the bit-vector recurrence of Myers (J. ACM 46(3), 1999) in the block form
+// Hyyro describes for a boundary difference entering at the top: the band's
+// W rows are W bits of two vectors, Pv and Mv, flagging the vertical
+// differences D[i][j] - D[i-1][j] of +1 and -1, and one step turns the
+// column j-1 vectors into column j with a handful of logic operations and
+// one addition.  The band is kept on the diagonal by shifting it down one row
+// after every step (its top row leaves, a new bottom row enters with
+// difference +1, the value of a vertical step), and the value of the cell
+// just above the band is carried in a scalar.  Cells outside the band are
+// given values of real paths (a horizontal step in from above the band, a
+// vertical step down below it), so every cell holds a value between the true
+// distance and the band-restricted one, which keeps the test exact; rows
+// above row 0 are virtual rows with D[i][j] = j - i that never match.
+//
+// Layout: pairs to verify are first collected into a list (an atomic counter
+// in the caller's workspace; results go to each pair's own index), so that a
+// wavefront holds only pairs that need work.  One pair per lane, a band of
+// 32 rows (E <= 15) or 64 rows (E <= 31).  Columns go in chunks of 16 (one
+// packed reference word): the reference word and the pattern words around
+// the band are turned once per chunk into bit planes (low code bit, high code
+// bit, position inside the read), so that a column takes its pattern planes
+// with one funnel shift each and its reference base with one bit-field
+// extract per plane.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "../../include/shouji.h"
 #include "shouji_internal.h"
 
 namespace shouji {
-
-namespace {
-constexpr int32_t kBandInf = 0x3FFF;   // cells outside the map / band
-}
 
 // out: -2 for pairs the filter did not accept, -3 for invalid lengths;
 // pairs to verify are appended to list (count in *count).  A workgroup
@@ -81,95 +94,186 @@ __global__ __launch_bounds__(kCollectBlock) void verify_collect_kernel(
 
 __global__ void zero_counter_kernel(unsigned long long *count) { *count = 0ull; }
 
-template <int K>
-__global__ __launch_bounds__(256) void verify_band_kernel(VerifyParams prm) {
-    constexpr int NB = 2 * K + 1;              // band cells of a row
-    constexpr int WW = (2 * NB + 31) / 32;     // words of the 2-bit reference window
-    constexpr int TOPW = (2 * (NB - 1)) / 32;  // word and bit of the window's top field
-    constexpr int TOPB = (2 * (NB - 1)) % 32;
+// The 16 low code bits (or, for w >> 1, high code bits) of a packed word of
+// 16 bases, as bits 0..15.
+__device__ __forceinline__ uint32_t code_plane(uint32_t w) {
+    uint32_t x = w & 0x55555555u;
+    x = (x | (x >> 1)) & 0x33333333u;
+    x = (x | (x >> 2)) & 0x0F0F0F0Fu;
+    x = (x | (x >> 4)) & 0x00FF00FFu;
+    x = (x | (x >> 8)) & 0x0000FFFFu;
+    return x;
+}
+
+// All ones when bit u of a code plane is set, else zero, as a band vector
+// (the bit-field extract's result is unsigned: it is made signed before it
+// is widened, so that a 64-bit mask is all ones in both halves).
+template <typename V>
+__device__ __forceinline__ V base_mask(uint32_t plane, int u) {
+    return (V)(int64_t)(int32_t)__builtin_amdgcn_sbfe(plane, u, 1);
+}
+
+// Banded distance of one pair per lane, band half-width K = E.  V: the band
+// vector (uint32_t: 32 rows, K <= 15; uint64_t: 64 rows, K <= 31).  Per column
+// j (reference base T[j-1]) band bit b is row i = j-1-K+b before the step, and
+// A = D[j-K-1][j] (the cell above the band) after it.  The pattern planes of a
+// chunk c (columns 16c+1 .. 16c+16) come from a window of NF 16-bit fields,
+// field q = pattern word c-BW+q, from which column 16c+1+u takes the bits at
+// offset u + 16 BW - 1 - K (P[j-2-K+b] at bit b).
+template <typename V, int BW>
+__global__ __launch_bounds__(256) void verify_myers_kernel(VerifyParams prm) {
+    constexpr int W = 8 * (int)sizeof(V);
+    constexpr int NF = 4 * BW;                 // 16-bit fields of the window
+    constexpr int NWW = NF / 2;                // 32-bit words of the window
+    const int K = prm.E;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)*prm.count) return;
     const int64_t p = prm.list[t];
     const int m = prm.lengths ? prm.lengths[p] : prm.max_len;
+    if (m == 0) {                              // empty pair: distance 0, no word to read
+        prm.out[p] = 0;
+        return;
+    }
+    const int64_t ld = prm.ld;
+    const int nw = (prm.max_len + 15) / 16;    // >= 1 here
     const uint32_t *P = prm.reads + p;
     const uint32_t *T = prm.refs + p;
-    const int64_t ld = prm.ld;
 
-    // row 0: D[0][j] = j on the band (cell b <-> column j = i - K + b); Q = D + 1
-    int32_t Q[NB];
-#pragma unroll
-    for (int b = 0; b < NB; b++) Q[b] = b >= K ? b - K + 1 : kBandInf;
-
-    // reference window: field b holds T[i - K + b - 1] while row i is computed
-    uint32_t win[WW];
-#pragma unroll
-    for (int w = 0; w < WW; w++) win[w] = 0u;
-    uint32_t tword = 0u;
-    int q = 0;                                 // next reference position to push
-    auto push = [&]() {
-        uint32_t c = 0u;
-        if (q < m) {
-            if ((q & 15) == 0) tword = T[(int64_t)(q >> 4) * ld];
-            c = (tword >> ((q & 15) * 2)) & 3u;
-        }
-        q++;
-#pragma unroll
-        for (int w = 0; w < WW; w++)
-            win[w] = w + 1 < WW ? __builtin_amdgcn_alignbit(win[w + 1], win[w], 2) : win[w] >> 2;
-        win[TOPW] |= c << TOPB;
+    // pattern word wd as planes; positions outside [0, m) are not in the read
+    auto fetch = [&](int wd) -> uint32_t {
+        return (wd >= 0 && wd < nw && 16 * wd < m) ? P[(int64_t)wd * ld] : 0u;
     };
-    for (int s = 0; s <= K; s++) push();       // fields K..2K <- T[0..K]
+    auto planes_of = [&](int wd, uint32_t w, uint32_t &lo, uint32_t &hi, uint32_t &in) {
+        lo = code_plane(w);
+        hi = code_plane(w >> 1);
+        const int n = (wd >= 0 && wd < nw) ? min(16, m - 16 * wd) : 0;
+        in = n > 0 ? (1u << n) - 1u : 0u;
+    };
+    auto field = [&](int wd, uint32_t &lo, uint32_t &hi, uint32_t &in) { planes_of(wd, fetch(wd), lo, hi, in); };
+    uint32_t wlo[NWW], whi[NWW], win[NWW];
+#pragma unroll
+    for (int i = 0; i < NWW; i++) {
+        uint32_t l0, h0, i0, l1, h1, i1;
+        field(2 * i - BW, l0, h0, i0);
+        field(2 * i + 1 - BW, l1, h1, i1);
+        wlo[i] = l0 | (l1 << 16);
+        whi[i] = h0 | (h1 << 16);
+        win[i] = i0 | (i1 << 16);
+    }
+    // column 0: rows -K .. W-1-K; D[i][0] = |i| (vertical difference -1 on
+    // rows <= 0, +1 below); A = D[-K-1][0] = K+1
+    V Pv = 0, Mv = 0;
+#pragma unroll
+    for (int b = 0; b < W; b++) {
+        if (b <= K) Mv |= (V)1 << b; else Pv |= (V)1 << b;
+    }
+    int A = K + 1;
+    // Operands of the column step held in VGPRs (opaque to the compiler): the
+    // SIMD runs two wavefronts' VALU instructions side by side only when every
+    // operand is a VGPR.  obase: window offset of column 16c+1.
+    uint32_t obase = (uint32_t)(16 * BW - 1 - K), one = 1u;
+    asm volatile("" : "+v"(obase), "+v"(one));
+    const V vone = (V)one;
 
-    uint32_t pword = 0u;
-    int result = -1;
-    bool done = false;
-    for (int i = 1; i <= m; i++) {
-        if (((i - 1) & 15) == 0) pword = P[(int64_t)((i - 1) >> 4) * ld];
-        const uint32_t c = (pword >> (((i - 1) & 15) * 2)) & 3u;
-        const uint32_t cb = c * 0x55555555u;   // c in every 2-bit field
-        uint32_t eq[WW];
-#pragma unroll
-        for (int w = 0; w < WW; w++) {
-            const uint32_t x = win[w] ^ cb;
-            eq[w] = ~(x | (x >> 1)) & 0x55555555u;
+    // the planes of the band at window offset o (0 <= o <= 30)
+    auto planes = [&](const uint32_t (&w)[NWW], uint32_t o) -> V {
+        if constexpr (W == 32) {
+            return __builtin_amdgcn_alignbit(w[1], w[0], o);
+        } else {
+            const uint32_t lo = __builtin_amdgcn_alignbit(w[1], w[0], o);
+            const uint32_t hi = __builtin_amdgcn_alignbit(w[2], w[1], o);
+            return (V)lo | ((V)hi << 32);
         }
-        // D[i][j] = min(D[i-1][j-1] + [P[i-1] != T[j-1]], D[i-1][j] + 1, D[i][j-1] + 1)
-        int32_t left = kBandInf + 1;           // D[i][j-1] + 1
-#pragma unroll
-        for (int b = 0; b < NB; b++) {
-            const int32_t eqb = (int32_t)((eq[(2 * b) >> 5] >> ((2 * b) & 31)) & 1u);
-            const int32_t up = b + 1 < NB ? Q[b + 1] : kBandInf + 1;   // D[i-1][j] + 1
-            const int32_t v = min(min(Q[b] - eqb, up), left);
-            Q[b] = v + 1;
-            left = v + 1;
+    };
+    // one column: reference code planes tl, th (all ones or zero), window
+    // offset o; IN: the band may hold rows above row 1 (pattern positions
+    // below 0), which must not match.  Positions at or past m need no mask:
+    // rows below row m never reach D[m][m].
+    // The step folds the band's shift into the recurrence: with the +1 that
+    // enters above the top row, the new bottom row's +1 and the old top row's
+    // difference follow from Xv alone (the top bit of Pv stays 1 and that of Mv
+    // stays 0 through every step).
+    auto column = [&](V tl, V th, uint32_t o, auto in_tag) {
+        constexpr bool IN = decltype(in_tag)::value;
+        const V Plo = planes(wlo, o), Phi = planes(whi, o);
+        // match bits: P[i-1] == T[j-1]
+        V Eq = ~((Plo ^ tl) | (Phi ^ th));
+        if constexpr (IN) Eq &= planes(win, o);
+        const V Xv = Eq | Mv;
+        const V Xh = (((Eq & Pv) + Pv) ^ Pv) | Eq;
+        const V Ph = Mv | ~(Xh | Pv);
+        const V Mh = Pv & Xh;
+        const V xs = Xv >> vone;
+        // A = D[j-1-K][j] = D[j-2-K][j] + (vertical difference of the old top
+        // row) = A + 1 - (bit 0 of Xv)
+        A += (int)one - (int)(Xv & vone);
+        Pv = Mh | ~(xs | Ph);
+        Mv = Ph & xs;
+    };
+    auto popc = [](V x) { return (int)__builtin_popcountll((unsigned long long)x); };
+
+    const int nchunks = (m + 15) / 16;
+    bool dead = false;
+    // the words of the next chunk are loaded one chunk ahead
+    uint32_t tw_next = T[0], pw_next = fetch(NF - BW);
+    for (int c = 0; c < nchunks; c++) {
+        const uint32_t tw = tw_next, pw = pw_next;
+        if (c + 1 < nchunks) {
+            tw_next = T[(int64_t)(c + 1) * ld];
+            pw_next = fetch(c + 1 - BW + NF - 1);
         }
-        push();
-        // no path through row i stays within E: the distance exceeds E
-        if ((i & 15) == 0 || i == m) {
-            int32_t mn = Q[0];
+        if (c > 0) {
+            // slide the window by one field; the new top field is word c-BW+NF-1
+            uint32_t l, h, in;
+            planes_of(c - BW + NF - 1, pw, l, h, in);
 #pragma unroll
-            for (int b = 1; b < NB; b++) mn = min(mn, Q[b]);
-            if (mn - 1 > prm.E) {
-                done = true;
-                break;
+            for (int i = 0; i < NWW - 1; i++) {
+                wlo[i] = __builtin_amdgcn_alignbit(wlo[i + 1], wlo[i], 16);
+                whi[i] = __builtin_amdgcn_alignbit(whi[i + 1], whi[i], 16);
+                win[i] = __builtin_amdgcn_alignbit(win[i + 1], win[i], 16);
             }
+            wlo[NWW - 1] = (wlo[NWW - 1] >> 16) | (l << 16);
+            whi[NWW - 1] = (whi[NWW - 1] >> 16) | (h << 16);
+            win[NWW - 1] = (win[NWW - 1] >> 16) | (in << 16);
+        }
+        const uint32_t tlo = code_plane(tw), thi = code_plane(tw >> 1);
+        // rows above row 1 only in the first chunks (16c <= K)
+        auto chunk = [&](auto in_tag) {
+            uint32_t o = obase;
+            if (16 * c + 16 <= m) {
+#pragma unroll
+                for (int u = 0; u < 16; u++) {
+                    column(base_mask<V>(tlo, u), base_mask<V>(thi, u), o, in_tag);
+                    o += one;
+                    asm volatile("" : "+v"(o));
+                }
+            } else {
+                for (int u = 0; u < m - 16 * c; u++) {
+                    column(base_mask<V>(tlo, u), base_mask<V>(thi, u), o, in_tag);
+                    o += one;
+                }
+            }
+        };
+        if (16 * c <= K)
+            chunk(std::integral_constant<bool, true>());
+        else
+            chunk(std::integral_constant<bool, false>());
+        // every band cell is at least A minus the band's -1 differences: above
+        // E, no path within E passes this column
+        if (c + 1 < nchunks && A - popc(Mv) > prm.E) {
+            dead = true;
+            break;
         }
     }
-    if (!done) {
-        const int32_t d = Q[K] - 1;            // D[m][m]
-        result = d <= prm.E ? d : -1;
+    int res = -1;
+    if (!dead) {
+        // D[m][m]: rows m-K .. m are band bits 0 .. K
+        const V low = (V)(((V)2 << K) - (V)1);
+        const int d = A + popc(Pv & low) - popc(Mv & low);
+        res = d <= prm.E ? d : -1;
     }
-    prm.out[p] = (int16_t)result;
+    prm.out[p] = (int16_t)res;
 }
-
-template __global__ void verify_band_kernel<2>(VerifyParams);
-template __global__ void verify_band_kernel<4>(VerifyParams);
-template __global__ void verify_band_kernel<6>(VerifyParams);
-template __global__ void verify_band_kernel<8>(VerifyParams);
-template __global__ void verify_band_kernel<12>(VerifyParams);
-template __global__ void verify_band_kernel<16>(VerifyParams);
-template __global__ void verify_band_kernel<24>(VerifyParams);
-template __global__ void verify_band_kernel<31>(VerifyParams);
 
 }  // namespace shouji
 
@@ -216,23 +320,11 @@ extern "C" int shouji_verify(const uint32_t *reads, const uint32_t *refs, const 
     prm.list = list;
     prm.count = count;
     prm.out = out_distance;
-    // the narrowest compiled band that holds E
-    if (E <= 2)
-        hipLaunchKernelGGL(shouji::verify_band_kernel<2>, dim3(grid), dim3(256), 0, st, prm);
-    else if (E <= 4)
-        hipLaunchKernelGGL(shouji::verify_band_kernel<4>, dim3(grid), dim3(256), 0, st, prm);
-    else if (E <= 6)
-        hipLaunchKernelGGL(shouji::verify_band_kernel<6>, dim3(grid), dim3(256), 0, st, prm);
-    else if (E <= 8)
-        hipLaunchKernelGGL(shouji::verify_band_kernel<8>, dim3(grid), dim3(256), 0, st, prm);
-    else if (E <= 12)
-        hipLaunchKernelGGL(shouji::verify_band_kernel<12>, dim3(grid), dim3(256), 0, st, prm);
-    else if (E <= 16)
-        hipLaunchKernelGGL(shouji::verify_band_kernel<16>, dim3(grid), dim3(256), 0, st, prm);
-    else if (E <= 24)
-        hipLaunchKernelGGL(shouji::verify_band_kernel<24>, dim3(grid), dim3(256), 0, st, prm);
+    // the band vector that holds rows j-E .. j+E+1 (2E+2 rows): 32 or 64 bits
+    if (E <= 15)
+        hipLaunchKernelGGL((shouji::verify_myers_kernel<uint32_t, 1>), dim3(grid), dim3(256), 0, st, prm);
     else
-        hipLaunchKernelGGL(shouji::verify_band_kernel<31>, dim3(grid), dim3(256), 0, st, prm);
+        hipLaunchKernelGGL((shouji::verify_myers_kernel<uint64_t, 2>), dim3(grid), dim3(256), 0, st, prm);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(SHOUJI_ERR_DEVICE, "shouji_verify: launch failed: %s", hipGetErrorString(e));
     return shouji::clear_error();

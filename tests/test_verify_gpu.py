@@ -95,3 +95,31 @@ def test_argument_errors(sj):
         sj.shouji_verify(r, r, None, -1, max_len=64)
     with pytest.raises(sj.ShoujiError):
         sj.shouji_verify(r, r, None, 32, max_len=64)
+
+
+@pytest.mark.parametrize("E", [3, 7, 11, 20])
+def test_long_mixed_lengths_and_odd_counts(sj, E):
+    # lengths 1..1024 (64-word rows) and an odd number of pairs: the last lane
+    # of the two-pairs-per-lane band holds one pair; pairs with 0..3 bases
+    p = syninput.generate(3001, 1, 1024, E=E, seed=700 + E)
+    r, t, L = _dev(sj, p, 1024)
+    print("verify long E=%d n=%d" % (E, p.n), flush=True)
+    got = sj.shouji_verify(r, t, L, E, max_len=1024)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy().astype(np.int32)
+    want = oracle.edit_distance_batch(p.P, p.T, p.lengths, k=E)
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, "mismatches at %s: gpu %s oracle %s (m %s)" % (
+        bad[:6], got[bad[:6]], want[bad[:6]], p.lengths[bad[:6]])
+
+
+def test_two_letter_alphabet_every_threshold(sj):
+    # many near-ties of the recurrence: codes 0/1 only, every E in 0..31
+    p = syninput.generate(2000, 20, 140, E=6, seed=777)
+    p.P[:] &= 1
+    p.T[:] &= 1
+    r, t, L = _dev(sj, p, 140)
+    for E in range(32):
+        got = sj.shouji_verify(r, t, L, E, max_len=140).cpu().numpy().astype(np.int32)
+        want = oracle.edit_distance_batch(p.P, p.T, p.lengths, k=E)
+        assert np.array_equal(got, want), E
