@@ -62,6 +62,11 @@ int raise_lds_limit(const void *kernel, size_t &limit, size_t bytes) {
 extern "C" int shouji_version(void) { return 1 * 10000 + 0 * 100 + 0; }
 
 namespace {
+// Largest E at which the layout with 32 pair lanes per half keeps two
+// wavefronts per SIMD: with a length array (ring, masks and length planes)
+// and without one (ring only).  Above it the quarter layout is launched.
+constexpr int kPlainHalfMaxE = 13;
+constexpr int kRingOnlyHalfMaxE = 22;
 // Wavefronts a CU holds with workgroups of wpg wavefronts of wl LDS bytes
 // each (registers allow two per SIMD).
 int waves_per_cu(size_t wl, int wpg) {
@@ -109,35 +114,55 @@ extern "C" int shouji_filter(const uint32_t *reads, const uint32_t *refs, const 
     // hold two of them, i.e. two wavefronts per SIMD.  Without a length array
     // every pair has max_len bases: the boundary masks follow from the
     // positions, and a wavefront's LDS holds the pattern ring only (two
-    // wavefronts per SIMD up to E = 22 instead of 13).
+    // wavefronts per SIMD up to E = 22 instead of 13).  Above that (E >= 14
+    // with lengths, E >= 23 without) the quarter layout (512 pairs per
+    // wavefront, half the ring per wavefront) keeps two wavefronts per SIMD.
     prm.ring_only = lengths == nullptr ? 1 : 0;
-    if (prm.ring_only) {
-        const int a = shouji::ring_slots_aligned(Ee), m = shouji::ring_slots(Ee);
-        prm.R = waves_per_cu(shouji::ring_lds_wave_bytes(a), shouji::kWavesPerGroup) >=
-                        waves_per_cu(shouji::ring_lds_wave_bytes(m), shouji::kWavesPerGroup)
+    const bool quarter = prm.ring_only ? Ee > kRingOnlyHalfMaxE : Ee > kPlainHalfMaxE;
+    prm.qh = shouji::quarter_h(Ee);
+    size_t wave_lds;
+    int64_t pairs_per_wave;
+    if (quarter) {
+        const int a = shouji::quarter_ring_slots_aligned(Ee), m = shouji::quarter_ring_slots(Ee);
+        const bool ro = prm.ring_only != 0;
+        prm.R = waves_per_cu(shouji::quarter_lds_wave_bytes(Ee, a, ro), shouji::kWavesPerGroup) >=
+                        waves_per_cu(shouji::quarter_lds_wave_bytes(Ee, m, ro), shouji::kWavesPerGroup)
                     ? a
                     : m;
+        wave_lds = shouji::quarter_lds_wave_bytes(Ee, prm.R, ro);
+        pairs_per_wave = shouji::kQuarterPairs;
     } else {
-        prm.R = plain_ring(Ee, shouji::kWavesPerGroup);
+        if (prm.ring_only) {
+            const int a = shouji::ring_slots_aligned(Ee), m = shouji::ring_slots(Ee);
+            prm.R = waves_per_cu(shouji::ring_lds_wave_bytes(a), shouji::kWavesPerGroup) >=
+                            waves_per_cu(shouji::ring_lds_wave_bytes(m), shouji::kWavesPerGroup)
+                        ? a
+                        : m;
+        } else {
+            prm.R = plain_ring(Ee, shouji::kWavesPerGroup);
+        }
+        wave_lds = prm.ring_only ? shouji::ring_lds_wave_bytes(prm.R) : shouji::plain_lds_wave_bytes(Ee, prm.R);
+        pairs_per_wave = shouji::kPairsPerWave;
     }
-    const size_t wave_lds =
-        prm.ring_only ? shouji::ring_lds_wave_bytes(prm.R) : shouji::plain_lds_wave_bytes(Ee, prm.R);
     const size_t lds = wave_lds * shouji::kWavesPerGroup;
     if (lds > shouji::kLdsPerCU) return fail(SHOUJI_ERR_RANGE, "E %d needs more LDS than one CU holds", E);
-    const int64_t waves = (n_pairs + shouji::kPairsPerWave - 1) / shouji::kPairsPerWave;
+    const int64_t waves = (n_pairs + pairs_per_wave - 1) / pairs_per_wave;
     const int64_t grid = (waves + shouji::kWavesPerGroup - 1) / shouji::kWavesPerGroup;
     if (grid > 0x7fffffff) return fail(SHOUJI_ERR_ARG, "n_pairs too large");
     prm.lds_wave_bytes = (int32_t)wave_lds;
-    static size_t lds_limit = 0, lds_limit_ring = 0;
-    const void *kernel = prm.ring_only ? (const void *)shouji::shouji_plain_ring_kernel
-                                       : (const void *)shouji::shouji_plain_kernel;
-    if (int rc = raise_lds_limit(kernel, prm.ring_only ? lds_limit_ring : lds_limit, lds)) return rc;
-    if (prm.ring_only)
-        hipLaunchKernelGGL(shouji::shouji_plain_ring_kernel, dim3((unsigned)grid),
-                           dim3(shouji::kWave * shouji::kWavesPerGroup), lds, (hipStream_t)stream, prm);
-    else
-        hipLaunchKernelGGL(shouji::shouji_plain_kernel, dim3((unsigned)grid),
-                           dim3(shouji::kWave * shouji::kWavesPerGroup), lds, (hipStream_t)stream, prm);
+    static size_t lds_limit[4] = {0, 0, 0, 0};
+    const int which = (quarter ? 2 : 0) + (prm.ring_only ? 1 : 0);
+    const void *kernels[4] = {(const void *)shouji::shouji_plain_kernel, (const void *)shouji::shouji_plain_ring_kernel,
+                              (const void *)shouji::shouji_plain_q_kernel,
+                              (const void *)shouji::shouji_plain_ring_q_kernel};
+    if (int rc = raise_lds_limit(kernels[which], lds_limit[which], lds)) return rc;
+    const dim3 gdim((unsigned)grid), bdim(shouji::kWave * shouji::kWavesPerGroup);
+    switch (which) {
+        case 0: hipLaunchKernelGGL(shouji::shouji_plain_kernel, gdim, bdim, lds, (hipStream_t)stream, prm); break;
+        case 1: hipLaunchKernelGGL(shouji::shouji_plain_ring_kernel, gdim, bdim, lds, (hipStream_t)stream, prm); break;
+        case 2: hipLaunchKernelGGL(shouji::shouji_plain_q_kernel, gdim, bdim, lds, (hipStream_t)stream, prm); break;
+        default: hipLaunchKernelGGL(shouji::shouji_plain_ring_q_kernel, gdim, bdim, lds, (hipStream_t)stream, prm);
+    }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(SHOUJI_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return ok();
@@ -327,14 +352,22 @@ extern "C" int shouji_filter_batched(const uint32_t *reads, const uint32_t *refs
     sp.out_accept = out_accept;
     sp.out_popcount = out_popcount;
     sp.nbins = L.nbins;
-    if (L.nbins <= shouji::kScatterMaxBins) {
-        static size_t slimit = 0;
-        if (int rc = raise_lds_limit((const void *)shouji::bin_scatter_lds_kernel, slimit,
-                                     shouji::scatter_lds_bytes(L.nbins)))
-            return rc;
-        const int64_t chunks = (n_pairs + shouji::kScatterChunk - 1) / shouji::kScatterChunk;
-        hipLaunchKernelGGL(shouji::bin_scatter_lds_kernel, dim3((unsigned)chunks),
-                           dim3(shouji::kScatterThreads), shouji::scatter_lds_bytes(L.nbins), st, sp);
+    const int chunk = L.nbins <= shouji::scatter_max_bins(shouji::kScatterChunkLarge) ? shouji::kScatterChunkLarge
+                                                                                        : shouji::kScatterChunkSmall;
+    if (L.nbins <= shouji::scatter_max_bins(chunk)) {
+        static size_t slimit_large = 0, slimit_small = 0;
+        const bool large = chunk == shouji::kScatterChunkLarge;
+        const void *sk = large ? (const void *)shouji::bin_scatter_lds_kernel<shouji::kScatterChunkLarge>
+                               : (const void *)shouji::bin_scatter_lds_kernel<shouji::kScatterChunkSmall>;
+        const size_t slds = shouji::scatter_lds_bytes(L.nbins, chunk);
+        if (int rc = raise_lds_limit(sk, large ? slimit_large : slimit_small, slds)) return rc;
+        const int64_t chunks = (n_pairs + chunk - 1) / chunk;
+        if (large)
+            hipLaunchKernelGGL(shouji::bin_scatter_lds_kernel<shouji::kScatterChunkLarge>, dim3((unsigned)chunks),
+                               dim3(shouji::kScatterThreads), slds, st, sp);
+        else
+            hipLaunchKernelGGL(shouji::bin_scatter_lds_kernel<shouji::kScatterChunkSmall>, dim3((unsigned)chunks),
+                               dim3(shouji::kScatterThreads), slds, st, sp);
     } else {
         const int64_t blocks = (n_pairs + 255) / 256;
         hipLaunchKernelGGL(shouji::bin_scatter_kernel, dim3((unsigned)(blocks < 8192 ? blocks : 8192)),
@@ -370,25 +403,43 @@ extern "C" int shouji_filter_batched(const uint32_t *reads, const uint32_t *refs
             }
             return wpg_;
         };
+        // the large-E class runs the quarter layout (two wavefronts of 512
+        // pairs per tile), which keeps two wavefronts per SIMD
+        const bool quarter = c > 0;
+        auto wave_bytes = [&](int R) {
+            return quarter ? shouji::quarter_lds_wave_bytes(Ecls, R, false) : shouji::plain_lds_wave_bytes(Ecls, R);
+        };
+        const int Ra = quarter ? shouji::quarter_ring_slots_aligned(Ecls) : shouji::ring_slots_aligned(Ecls);
+        const int Rm = quarter ? shouji::quarter_ring_slots(Ecls) : shouji::ring_slots(Ecls);
         int best_waves = 0, best_min = 0;
-        int wpg = best_group(shouji::plain_lds_wave_bytes(Ecls, shouji::ring_slots_aligned(Ecls)), best_waves);
-        tp.R = shouji::ring_slots_aligned(Ecls);
-        const int wpg_min = best_group(shouji::plain_lds_wave_bytes(Ecls, shouji::ring_slots(Ecls)), best_min);
+        int wpg = best_group(wave_bytes(Ra), best_waves);
+        tp.R = Ra;
+        const int wpg_min = best_group(wave_bytes(Rm), best_min);
         if (best_min > best_waves) {
             wpg = wpg_min;
-            tp.R = shouji::ring_slots(Ecls);
+            tp.R = Rm;
         }
-        const size_t wave_lds = shouji::plain_lds_wave_bytes(Ecls, tp.R);
+        const size_t wave_lds = wave_bytes(tp.R);
         if (wpg == 0) return fail(SHOUJI_ERR_RANGE, "LDS too small for E %d", Ecls);
         tp.lds_wave_bytes = (int32_t)wave_lds;
         tp.waves_per_group = wpg;
-        if (int rc = raise_lds_limit((const void *)shouji::shouji_tiles_kernel, tlimit, wave_lds * wpg))
-            return rc;
+        tp.qh = shouji::quarter_h(Ecls);
         tp.out_accept = out_accept;
         tp.out_popcount = out_popcount;
-        const int64_t grid = (L.max_tiles + wpg - 1) / wpg;
-        hipLaunchKernelGGL(shouji::shouji_tiles_kernel, dim3((unsigned)grid), dim3(shouji::kWave * wpg),
-                           wave_lds * wpg, st, tp);
+        const int64_t waves_needed = quarter ? 2 * L.max_tiles : L.max_tiles;
+        const int64_t grid = (waves_needed + wpg - 1) / wpg;
+        if (quarter) {
+            static size_t qlimit = 0;
+            if (int rc = raise_lds_limit((const void *)shouji::shouji_tiles_q_kernel, qlimit, wave_lds * wpg))
+                return rc;
+            hipLaunchKernelGGL(shouji::shouji_tiles_q_kernel, dim3((unsigned)grid), dim3(shouji::kWave * wpg),
+                               wave_lds * wpg, st, tp);
+        } else {
+            if (int rc = raise_lds_limit((const void *)shouji::shouji_tiles_kernel, tlimit, wave_lds * wpg))
+                return rc;
+            hipLaunchKernelGGL(shouji::shouji_tiles_kernel, dim3((unsigned)grid), dim3(shouji::kWave * wpg),
+                               wave_lds * wpg, st, tp);
+        }
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(SHOUJI_ERR_DEVICE, "batched launch failed: %s", hipGetErrorString(e));

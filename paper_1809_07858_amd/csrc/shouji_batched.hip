@@ -179,12 +179,13 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(ScatterParams prm) {
     }
 }
 
-// Scatter staged through LDS.  A workgroup takes a chunk of kScatterChunk
+// Scatter staged through LDS.  A workgroup takes a chunk of CHUNK
 // consecutive pairs, reserves one run per bin in the binned workspace (one
 // global atomic per bin and chunk), ranks its pairs by bin in LDS, and then
 // writes every word row, the lengths, thresholds and original indices in
 // slot order, so consecutive threads write consecutive slots of a run.
-// Reads of the input rows stay coalesced.  Needs nbins <= kScatterMaxBins.
+// Reads of the input rows stay coalesced.  Needs nbins <= scatter_max_bins(CHUNK).
+template <int CHUNK>
 __global__ __launch_bounds__(kScatterThreads) void bin_scatter_lds_kernel(ScatterParams prm) {
     extern __shared__ int32_t sm[];
     const int nbins = prm.nbins;
@@ -192,12 +193,12 @@ __global__ __launch_bounds__(kScatterThreads) void bin_scatter_lds_kernel(Scatte
     int32_t *loff = cnt + nbins;                               // local run offsets
     int64_t *gbase = reinterpret_cast<int64_t *>(loff + nbins + (nbins & 1));
     uint16_t *slotbin = reinterpret_cast<uint16_t *>(gbase + nbins);
-    uint16_t *slotsrc = slotbin + kScatterChunk;
-    uint32_t *buf = reinterpret_cast<uint32_t *>(slotsrc + kScatterChunk);
+    uint16_t *slotsrc = slotbin + CHUNK;
+    uint32_t *buf = reinterpret_cast<uint32_t *>(slotsrc + CHUNK);
     __shared__ int32_t part[kScatterThreads];
     const int tid = threadIdx.x;
-    const int64_t c0 = (int64_t)blockIdx.x * kScatterChunk;
-    constexpr int PER = kScatterChunk / kScatterThreads;
+    const int64_t c0 = (int64_t)blockIdx.x * CHUNK;
+    constexpr int PER = CHUNK / kScatterThreads;
 
     for (int b = tid; b < nbins; b += kScatterThreads) cnt[b] = 0;
     __syncthreads();
@@ -309,5 +310,8 @@ __global__ __launch_bounds__(kScatterThreads) void bin_scatter_lds_kernel(Scatte
         }
     }
 }
+
+template __global__ void bin_scatter_lds_kernel<kScatterChunkLarge>(ScatterParams);
+template __global__ void bin_scatter_lds_kernel<kScatterChunkSmall>(ScatterParams);
 
 }  // namespace shouji

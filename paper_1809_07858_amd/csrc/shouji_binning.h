@@ -16,17 +16,26 @@ constexpr int kCountThreads = 1024;           // histogram workgroup
 constexpr int kCountGroups = 512;             // histogram workgroups at most
 constexpr int kCountLds = 64 * 1024;          // LDS of the histogram copies at most
 constexpr int kCostBuckets = 16;
-// Tiles are launched per E class, each with the LDS its largest E needs:
-// Ee <= 13 fits two wavefronts per SIMD, Ee <= 31 one.
+// Tiles are launched per E class, each with the layout and LDS its largest E
+// needs: Ee <= 13 takes the two-half layout (1024 pairs per wavefront), Ee <= 31
+// the quarter layout (512 pairs per wavefront, two wavefronts per tile); both
+// keep two wavefronts per SIMD.
 constexpr int kEClasses = 2;
 __host__ __device__ inline int e_class(int Ee) { return Ee <= 13 ? 0 : 1; }
 __host__ __device__ inline int e_class_bound(int c) { return c == 0 ? 13 : 31; }
 constexpr int kMinBinWidth = 4;
-constexpr int kScatterChunk = 8192;           // pairs per workgroup of the staged scatter
+// The staged scatter takes chunks of 16,384 pairs per workgroup when its bin
+// tables leave LDS room for them (longer runs per bin and chunk make longer
+// writes), else chunks of 8,192 pairs.
+constexpr int kScatterChunkLarge = 16384;
+constexpr int kScatterChunkSmall = 8192;
 constexpr int kScatterThreads = 1024;
-constexpr int kScatterMaxBins = 4128;         // LDS tables of the staged scatter
-inline size_t scatter_lds_bytes(int nbins) {
-    return (size_t)nbins * 4 * 2 + 8 + (size_t)nbins * 8 + (size_t)kScatterChunk * (2 + 2 + 4);
+inline size_t scatter_lds_bytes(int nbins, int chunk) {
+    return (size_t)nbins * 4 * 2 + 8 + (size_t)nbins * 8 + (size_t)chunk * (2 + 2 + 4);
+}
+// bins the staged scatter holds with chunks of `chunk` pairs (LDS of one CU)
+inline int scatter_max_bins(int chunk) {
+    return (int)((kLdsPerCU - 8 - (size_t)chunk * 8) / 16);
 }
 
 struct PlanOut {
@@ -89,6 +98,7 @@ __global__ void bin_count_kernel(const int32_t *lengths, const int32_t *Ep, int6
                                  int bw, int nbins, int ncopies, int32_t *counts);
 __global__ void bin_plan_kernel(const int32_t *counts, int nbins, int nbucket_len, PlanOut out);
 __global__ void bin_scatter_kernel(ScatterParams prm);
+template <int CHUNK>
 __global__ void bin_scatter_lds_kernel(ScatterParams prm);
 
 }  // namespace shouji

@@ -31,6 +31,7 @@ struct PlainParams {
     int64_t n;
     int32_t lds_wave_bytes;  // LDS bytes owned by one wavefront
     int32_t ring_only;       // no length array: LDS holds the pattern ring only
+    int32_t qh;              // quarter layout: pattern word offset of the passes
 };
 
 // Two-length form: reads and references of different lengths, with a
@@ -100,6 +101,7 @@ struct TilesParams {
     int32_t R;
     int32_t lds_wave_bytes;
     int32_t waves_per_group;
+    int32_t qh;               // quarter layout: pattern word offset of the passes
     uint8_t *out_accept;
     int16_t *out_popcount;
 };
@@ -141,7 +143,29 @@ inline size_t local_lds_wave_bytes(int Ee, int len_bits, int R) {
            (size_t)pattern_mask_slots(Ee) * kPairLanes * 4 + (size_t)(2 * len_bits) * kPairLanes * 4;
 }
 
+// Quarter layout (four lane groups of 16 lanes, 512 pairs per wavefront,
+// iterations of 32 windows) for large thresholds.  Pass k writes pattern words
+// 2k+h and 2k+h+1, h = floor((34+Ee)/16) - 3; the ring must keep iteration j's
+// positions [32j-Ee, 32j+34+Ee] while pass j+2 writes words 2j+4+h, 2j+5+h.
+constexpr int kQuarterLanes = 16;
+constexpr int kQuarterPairs = 512;
+inline int quarter_h(int Ee) { return (34 + Ee) / 16 - 3; }
+inline int quarter_ring_slots(int Ee) {
+    const int a = 64 + 16 * quarter_h(Ee) + Ee, b = 2 * Ee + 35;
+    return a > b ? a : b;
+}
+inline int quarter_ring_slots_aligned(int Ee) { return (quarter_ring_slots(Ee) + 7) / 8 * 8; }
+inline size_t quarter_lds_wave_bytes(int Ee, int R, bool ring_only) {
+    size_t b = (size_t)(R + kMirror) * kQuarterLanes * 8;
+    if (!ring_only)
+        b += (size_t)(3 * kBlock + kCols + Ee) * kQuarterLanes * 4 + (size_t)(kLenBits + 1) * kQuarterLanes * 4;
+    return b;
+}
+
 __global__ void shouji_plain_kernel(PlainParams prm);
+__global__ void shouji_plain_q_kernel(PlainParams prm);
+__global__ void shouji_plain_ring_q_kernel(PlainParams prm);
+__global__ void shouji_tiles_q_kernel(TilesParams prm);
 __global__ void shouji_plain_ring_kernel(PlainParams prm);
 __global__ void shouji_local_kernel(LocalParams prm);
 __global__ void shouji_tiles_kernel(TilesParams prm);

@@ -162,7 +162,7 @@ struct Winner {
 // masks text position i0+s and nvp[s] pattern position i0-Ee+s.  REGM: every
 // pair has length reg_mlen, and the masks are computed from the positions
 // instead of read from nv.
-template <bool FIRST, int NB, bool TWO, bool REGM>
+template <bool FIRST, int NB, bool TWO, bool REGM, int PL = kPairLanes>
 __device__ __forceinline__ void candidate(Winner<NB> &W, const uint2 (&pv)[NB + 3],
                                           const uint32_t *__restrict__ nv, const uint32_t *__restrict__ nvp,
                                           int Ee, int i0, int d, bool masked,
@@ -178,9 +178,9 @@ __device__ __forceinline__ void candidate(Winner<NB> &W, const uint2 (&pv)[NB + 
     if (masked && TWO) {
         // text column i0+t past the reference, pattern position i0+t-d
         // outside the read
-        const uint32_t *np = nvp + (Ee - d) * kPairLanes;
+        const uint32_t *np = nvp + (Ee - d) * PL;
 #pragma unroll
-        for (int t = 0; t < C; t++) cell[t] |= nv[t * kPairLanes] | np[t * kPairLanes];
+        for (int t = 0; t < C; t++) cell[t] |= nv[t * PL] | np[t * PL];
     } else if (REGM && masked) {
         // d < 0: the pattern index i0+t-d runs out first; d >= 0: the text
         // column i0+t, and pattern indices below 0
@@ -192,14 +192,14 @@ __device__ __forceinline__ void candidate(Winner<NB> &W, const uint2 (&pv)[NB + 
     } else if (masked) {
         if (d < 0) {
             // pattern index j - d > j: the pattern side runs out first
-            const uint32_t *np = nv + (-d) * kPairLanes;
+            const uint32_t *np = nv + (-d) * PL;
 #pragma unroll
-            for (int t = 0; t < C; t++) cell[t] |= np[t * kPairLanes];
+            for (int t = 0; t < C; t++) cell[t] |= np[t * PL];
         } else {
             const uint32_t *np = nv;
 #pragma unroll
             for (int t = 0; t < C; t++) {
-                cell[t] |= np[t * kPairLanes];
+                cell[t] |= np[t * PL];
                 if (i0 + t - d < 0) cell[t] = ~0u;  // before the pattern's start
             }
         }
@@ -253,16 +253,16 @@ __device__ __forceinline__ bool needs_mask(int d, int lo, int hi_col, int m_min)
 
 // The C ring entries (pattern planes of C consecutive positions) of one
 // candidate, starting at ring slot `slot`.
-template <int C>
+template <int C, int PL = kRingStride>
 __device__ __forceinline__ void ring_load(const uint2 *__restrict__ rb, int slot, uint2 (&pv)[C]) {
-    const uint2 *rp = rb + slot * kRingStride;
+    const uint2 *rp = rb + slot * PL;
 #pragma unroll
-    for (int t = 0; t < C; t++) pv[t] = rp[t * kRingStride];
+    for (int t = 0; t < C; t++) pv[t] = rp[t * PL];
 }
 
 // Window search of one block of NB windows at i0 (sb = ring slot of i0): the
 // winner of every window over all 2E+1 diagonals.
-template <int NB, bool TWO, bool MASKS = true, bool REGM = false>
+template <int NB, bool TWO, bool MASKS = true, bool REGM = false, int PL = kPairLanes>
 __device__ __forceinline__ void block_winners(Winner<NB> &W, const uint2 *__restrict__ ring,
                                               const uint32_t *__restrict__ nv,
                                               const uint32_t *__restrict__ nvp, int pl, int i0,
@@ -281,30 +281,30 @@ __device__ __forceinline__ void block_winners(Winner<NB> &W, const uint2 *__rest
     // MASKS = false: the caller knows that no cell of the block leaves the map
     auto mk = [&](int d) { return MASKS && needs_mask(d, lo, hi_col, m_min); };
     if (Ee == 0) {
-        ring_load<C>(rb, sb, A);
-        candidate<true, NB, TWO, REGM>(W, A, nv, nvp, Ee, i0, 0, mk(0), tl, th, reg_mlen);
+        ring_load<C, PL>(rb, sb, A);
+        candidate<true, NB, TWO, REGM, PL>(W, A, nv, nvp, Ee, i0, 0, mk(0), tl, th, reg_mlen);
         return;
     }
     int sP = sb == 0 ? R - 1 : sb - 1;   // slot of d = +k
     int sN = sb + 1 == R ? 0 : sb + 1;   // slot of d = -k
-    ring_load<C>(rb, sP, A);
-    ring_load<C>(rb, sN, B);
-    candidate<true, NB, TWO, REGM>(W, A, nv, nvp, Ee, i0, 1, mk(1), tl, th, reg_mlen);
+    ring_load<C, PL>(rb, sP, A);
+    ring_load<C, PL>(rb, sN, B);
+    candidate<true, NB, TWO, REGM, PL>(W, A, nv, nvp, Ee, i0, 1, mk(1), tl, th, reg_mlen);
     // A <- the next d > 0 (or the main diagonal when E = 1)
     sP = sP == 0 ? R - 1 : sP - 1;
-    ring_load<C>(rb, Ee >= 2 ? sP : sb, A);
-    candidate<false, NB, TWO, REGM>(W, B, nv, nvp, Ee, i0, -1, mk(-1), tl, th, reg_mlen);
+    ring_load<C, PL>(rb, Ee >= 2 ? sP : sb, A);
+    candidate<false, NB, TWO, REGM, PL>(W, B, nv, nvp, Ee, i0, -1, mk(-1), tl, th, reg_mlen);
     for (int k = 2; k <= Ee; k++) {
         // A holds d = +k; B <- d = -k
         sN = sN + 1 == R ? 0 : sN + 1;
-        ring_load<C>(rb, sN, B);
-        candidate<false, NB, TWO, REGM>(W, A, nv, nvp, Ee, i0, k, mk(k), tl, th, reg_mlen);
+        ring_load<C, PL>(rb, sN, B);
+        candidate<false, NB, TWO, REGM, PL>(W, A, nv, nvp, Ee, i0, k, mk(k), tl, th, reg_mlen);
         // A <- d = +(k+1), or the main diagonal after the last k
         sP = sP == 0 ? R - 1 : sP - 1;
-        ring_load<C>(rb, k < Ee ? sP : sb, A);
-        candidate<false, NB, TWO, REGM>(W, B, nv, nvp, Ee, i0, -k, mk(-k), tl, th, reg_mlen);
+        ring_load<C, PL>(rb, k < Ee ? sP : sb, A);
+        candidate<false, NB, TWO, REGM, PL>(W, B, nv, nvp, Ee, i0, -k, mk(-k), tl, th, reg_mlen);
     }
-    candidate<false, NB, TWO, REGM>(W, A, nv, nvp, Ee, i0, 0, mk(0), tl, th, reg_mlen);
+    candidate<false, NB, TWO, REGM, PL>(W, A, nv, nvp, Ee, i0, 0, mk(0), tl, th, reg_mlen);
 }
 
 // Where the zeros of the final bit-vector lie, for the local and glocal
@@ -438,17 +438,18 @@ __device__ __forceinline__ void block_count(FsmState &F, const uint32_t (&o)[NB]
 // (its bits are never written out), so no load is predicated; the bound is
 // made opaque so that the per-pair indices are not hoisted out of the
 // caller's loop and kept live in registers.
+template <int PL = kPairLanes>
 __device__ __forceinline__ void load_word(const uint32_t *__restrict__ row, bool full, int left, int pl,
                                           uint32_t (&raw)[32]) {
     const uint32_t *q = row + pl;
     if (full) {
 #pragma unroll
-        for (int k = 0; k < 32; k++) raw[k] = q[k * kPairLanes];
+        for (int k = 0; k < 32; k++) raw[k] = q[k * PL];
     } else {
         int last = left - 1 - pl;            // q[last] is the wavefront's last pair
         asm volatile("" : "+v"(last));
 #pragma unroll
-        for (int k = 0; k < 32; k++) raw[k] = q[min(k * kPairLanes, last)];
+        for (int k = 0; k < 32; k++) raw[k] = q[min(k * PL, last)];
     }
 }
 
@@ -995,6 +996,372 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     }
 }
 
+// ------------------------------------------------------------ quarter layout
+// For large thresholds the pattern ring of the layout above (32 pair lanes,
+// 2E+19 positions and a word of look-ahead) fills LDS so that a CU holds one
+// wavefront per SIMD.  Here a wavefront filters 512 pairs in four lane groups
+// of 16 lanes (g = lane >> 4; bit k of a plane is pair base + 16k + (lane &
+// 15)), all holding the same pairs: an iteration covers 32 windows and group g
+// searches block q(g) of 8 of them, q = 0, 1, 2, 3 for g = 0, 1, 3, 2, so that
+// the bit-vector update's 3-plane state moves from block to block with one
+// lane swap per plane (0 -> 1 and 3 -> 2 within a 32-lane half, 1 -> 3 and
+// 2 -> 0 across the halves).  The ring holds 16 pair lanes per position, so a
+// wavefront needs about half the LDS at the same threshold, and two per SIMD
+// fit up to E = 31.  The search, the update, the count and the cell masking
+// are the functions above with a lane stride of 16.
+//
+// Passes: pass k transposes text word 2k (group 0) and 2k+1 (group 3) and
+// pattern words 2k+h and 2k+h+1 (groups 1 and 2; h = floor((34+E)/16) - 3,
+// so that pass k+1 completes the pattern words iteration k reads).  Text
+// planes of iteration k: group 0 takes word 2k's positions 0..10, group 3 word
+// 2k+1's; group 1 word 2k's positions 8..15 (from group 0) and 2k+1's 0..2
+// (from group 3); group 2 word 2k+1's 8..15 (from group 3) and word 2k+2's
+// 0..2 (from group 0 of pass k+1).
+constexpr int kQLanes = 16;
+constexpr int kQPairs = kQLanes * kPairsPerLane;   // 512 pairs per wavefront
+constexpr int kQWin = 4 * kBlock;                   // windows per iteration
+
+template <bool RO>
+__device__ __forceinline__ void filter_group4(const GroupJob &J, uint32_t *lds, int R, int h, int lane) {
+    const int g = lane >> 4;
+    const int q = g == 0 ? 0 : (g == 1 ? 1 : (g == 3 ? 2 : 3));   // block of the iteration
+    const int pl = lane & (kQLanes - 1);
+    const int Ee = J.Ee;
+    uint2 *ring = reinterpret_cast<uint2 *>(lds);
+    // masks of positions lo + s at nv[s * 16 + pl] (s < 35 + Ee), then the
+    // bit planes of the 32 lengths per pair lane
+    uint32_t *nv = lds + (R + kMirror) * kQLanes * 2;
+    uint32_t *nvg = nv + kBlock * q * kQLanes + pl;
+    uint32_t *lbv = nv + (3 * kBlock + kCols + Ee) * kQLanes + pl;
+    const int64_t base = J.base;
+    const int64_t n = J.n;
+    const bool full = base + kQPairs <= n;
+    // groups 0 and 3 read text words, groups 1 and 2 pattern words
+    const bool text_group = g == 0 || g == 3;
+    const uint32_t *seq = reinterpret_cast<const uint32_t *>(
+        text_group ? reinterpret_cast<uintptr_t>(J.refs) : reinterpret_cast<uintptr_t>(J.reads));
+    const int left = (int)min(n - base, (int64_t)kQPairs);
+
+    // ---- lengths (as in filter_group, one length per pair)
+    uint32_t lenw[32];
+    uint32_t valid = 0u;
+    int lmin = 0x7fffffff, lmax = -1;
+    const int32_t *lp = J.lengths ? J.lengths + base : nullptr;
+    int mv[32];
+    if (full) {
+#pragma unroll
+        for (int k = 0; k < 32; k++) mv[k] = lp ? lp[k * kQLanes + pl] : J.max_len;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 32; k++) {
+            const int qi = min(k * kQLanes + pl, left - 1);
+            mv[k] = lp ? lp[qi] : J.max_len;
+        }
+    }
+    bool fast = false;
+    {
+        int a = 0x7fffffff, b = -1;
+#pragma unroll
+        for (int k = 0; k < 32; k++) {
+            a = min(a, mv[k]);
+            b = max(b, mv[k]);
+        }
+        a = __builtin_amdgcn_readfirstlane(wave_min(a));
+        b = __builtin_amdgcn_readfirstlane(wave_max(b));
+        if (full && a >= 0 && b <= J.max_len) {
+            fast = true;
+#pragma unroll
+            for (int k = 0; k < 32; k++) lenw[k] = (uint32_t)mv[k];
+            valid = ~0u;
+            lmin = a;
+            lmax = b;
+        }
+    }
+    if (!fast) {
+#pragma unroll
+        for (int k = 0; k < 32; k++) {
+            const int qq = k * kQLanes + pl;
+            const uint32_t inm = (full || qq < left) ? ~0u : 0u;
+            const int m = (int)(((uint32_t)mv[k] & inm) | ~inm);   // -1 for a missing pair
+            const uint32_t okm = (uint32_t)m <= (uint32_t)J.max_len ? ~0u : 0u;
+            lenw[k] = (uint32_t)m & okm;
+            valid |= okm & (1u << k);
+            lmin = min(lmin, (int)(((uint32_t)m & okm) | (~okm & 0x7fffffffu)));
+            lmax = max(lmax, (int)(((uint32_t)m & okm) | ~okm));
+            asm volatile("" : "+v"(lenw[k]), "+v"(valid), "+v"(lmin), "+v"(lmax));
+        }
+        lmin = __builtin_amdgcn_readfirstlane(wave_min(lmin));
+        lmax = __builtin_amdgcn_readfirstlane(wave_max(lmax));
+    }
+    const int m_max = lmax < 0 ? 0 : lmax;
+    const int m_min = lmax < 0 ? 0 : lmin;
+    const bool uniform = m_min == m_max;
+    const int reg_mlen = RO ? m_max : -1;
+    if (!uniform) {
+        transpose32(lenw);             // lenw[b] = bit b of the 32 lengths
+#pragma unroll
+        for (int b = 0; b < kLenBits; b++) lbv[b * kQLanes] = lenw[b];
+    }
+
+    FsmState F;
+    F.s0 = F.s1 = F.s2 = ~0u;
+    F.ones = F.twos = F.fours = 0u;
+#pragma unroll
+    for (int b = 0; b < 8; b++) F.e[b] = 0u;
+    Ends X;   // unused (global counting)
+
+    const int niter = (m_max + kQWin - 1) / kQWin;
+    const int ebits = 32 - __builtin_clz((unsigned)niter | 1u);   // bits of niter (one block per group and iteration)
+    const int nhalves = (m_max + kHalf - 1) / kHalf;   // words holding positions < m_max
+
+    // masks "position x is past the pair's end" for positions x0 .. x0+count-1
+    // (as in filter_group)
+    auto fill_masks = [&](int i0, uint32_t *dst, int count) {
+        if (uniform) {
+            for (int s = 0; s < count; s++) dst[s * kQLanes] = i0 + s >= m_max ? ~0u : 0u;
+        } else {
+            int x0 = i0;
+            asm volatile("" : "+v"(x0));
+            uint32_t lb[kLenBits];
+#pragma unroll
+            for (int b = 0; b < kLenBits; b++) lb[b] = lbv[b * kQLanes];
+            uint32_t msk = ~0u;
+            for (int s = 0; s < count; s++) {
+                const int x = x0 + s;
+                if (s == 0) {
+                    uint32_t gt = 0u;  // gt = (length > x)
+#pragma unroll
+                    for (int b = 0; b < kLenBits; b++) {
+                        const uint32_t sx = ((x >> b) & 1) ? ~0u : 0u;
+                        gt = mux(sx, lb[b] & gt, lb[b] | gt);
+                    }
+                    msk = ~gt;
+                } else {
+                    uint32_t e = ~0u;  // e = (length == x)
+#pragma unroll
+                    for (int b = 0; b < kLenBits; b++) {
+                        const uint32_t sx = ((x >> b) & 1) ? ~0u : 0u;
+                        e = gate<kTTAndXnor>(e, lb[b], sx);
+                    }
+                    msk |= e;
+                }
+                dst[s * kQLanes] = msk;
+            }
+        }
+    };
+
+    // One pass: load (word indices clamped into [0, limit); a word outside it
+    // is loaded from a valid index, its planes lie beyond every pair's length
+    // or are never used), then transpose and write the pattern words.
+    auto pass_load = [&](int k, uint32_t (&raw)[32]) {
+        const int w = g == 0 ? 2 * k : (g == 3 ? 2 * k + 1 : (g == 1 ? 2 * k + h : 2 * k + h + 1));
+        const int wc = min(max(w, 0), nhalves - 1);
+        load_word<kQLanes>(seq + (int64_t)wc * J.ld + base, full, left, pl, raw);
+    };
+    auto pass_finish = [&](int k, uint32_t (&raw)[32]) {
+        transpose32(raw);
+        if (!text_group) {
+            const int pw = g == 1 ? 2 * k + h : 2 * k + h + 1;
+            if (pw >= 0 && pw < nhalves) {
+                if ((R & 7) != 0) {
+                    int slot = (pw * kHalf) % R;
+#pragma unroll
+                    for (int u = 0; u < kHalf; u++) {
+                        const uint2 v = make_uint2(raw[2 * u], raw[2 * u + 1]);
+                        ring[slot * kQLanes + pl] = v;
+                        if (slot < kMirror) ring[(slot + R) * kQLanes + pl] = v;
+                        slot = slot + 1 == R ? 0 : slot + 1;
+                    }
+                } else {
+#pragma unroll
+                    for (int hh = 0; hh < 2; hh++) {
+                        const int s0 = (pw * kHalf + 8 * hh) % R;
+                        uint2 *dst = ring + s0 * kQLanes + pl;
+#pragma unroll
+                        for (int u = 0; u < 8; u++)
+                            dst[u * kQLanes] = make_uint2(raw[2 * (8 * hh + u)], raw[2 * (8 * hh + u) + 1]);
+                        if (s0 < kMirror) {
+#pragma unroll
+                            for (int u = 0; u < 8; u++)
+                                if (s0 + u < kMirror)
+                                    dst[(R + u) * kQLanes] =
+                                        make_uint2(raw[2 * (8 * hh + u)], raw[2 * (8 * hh + u) + 1]);
+                        }
+                    }
+                }
+            }
+        }
+    };
+    // Text planes of an iteration's block (11 positions, low and high plane):
+    // start_text from pass k (all but group 2's positions 8..10), finish_text
+    // from pass k+1 (group 2's positions 8..10 = word 2k+2's 0..2, from group 0).
+    auto start_text = [&](uint32_t (&T)[2 * kCols], const uint32_t (&raw)[32]) {
+#pragma unroll
+        for (int t = 0; t < 2 * kBlock; t++) {
+            // groups 1 / 2: positions 8..15 of group 0's / group 3's word
+            const auto sw = __builtin_amdgcn_permlane16_swap(raw[2 * kBlock + t], raw[2 * kBlock + t], false, false);
+            T[t] = text_group ? raw[t] : (g == 1 ? (uint32_t)sw[0] : (uint32_t)sw[1]);
+        }
+#pragma unroll
+        for (int t = 2 * kBlock; t < 2 * kCols; t++) {
+            // group 1: positions 0..2 of group 3's word
+            const auto sw = __builtin_amdgcn_permlane32_swap(raw[t - 2 * kBlock], raw[t - 2 * kBlock], false, false);
+            T[t] = text_group ? raw[t] : (uint32_t)sw[1];
+        }
+    };
+    auto finish_text = [&](uint32_t (&T)[2 * kCols], const uint32_t (&raw)[32]) {
+#pragma unroll
+        for (int t = 2 * kBlock; t < 2 * kCols; t++) {
+            // group 2: positions 0..2 of group 0's word (the next text word)
+            const auto sw = __builtin_amdgcn_permlane32_swap(raw[t - 2 * kBlock], raw[t - 2 * kBlock], false, false);
+            T[t] = g == 2 ? (uint32_t)sw[0] : T[t];
+        }
+    };
+
+    uint32_t TA[2 * kCols], TB[2 * kCols];
+    if (niter > 0) {
+        // pattern-only passes for words 0 .. h-1 (h > 0 only for E >= 30)
+        for (int k = -((h + 1) / 2); k < 0; k++) {
+            uint32_t raw[32];
+            pass_load(k, raw);
+            pass_finish(k, raw);
+        }
+        uint32_t raw[32];
+        pass_load(0, raw);
+        pass_finish(0, raw);
+        start_text(TA, raw);
+        pass_load(1, raw);
+        pass_finish(1, raw);
+        finish_text(TA, raw);
+        start_text(TB, raw);
+    }
+
+    auto iteration = [&](int j, uint32_t (&Tc)[2 * kCols], uint32_t (&Tn)[2 * kCols]) {
+        const int lo = kQWin * j;
+        const int i0 = lo + kBlock * q;
+        const int hi_col = lo + 3 * kBlock + kCols - 1;   // last text column of the iteration
+        Winner<kBlock> W;
+        {
+            uint32_t tl[kCols], th[kCols];
+#pragma unroll
+            for (int t = 0; t < kCols; t++) { tl[t] = Tc[2 * t]; th[t] = Tc[2 * t + 1]; }
+            const int sb = i0 % R;
+            if ((Ee > lo) || (hi_col + Ee >= m_min)) {
+                if (!RO) fill_masks(i0, nvg, kCols + Ee);
+                block_winners<kBlock, false, true, RO, kQLanes>(W, ring, nvg, nvg, pl, i0, sb, Ee, R, lo, hi_col,
+                                                                m_min, tl, th, reg_mlen);
+            } else {
+                block_winners<kBlock, false, false, RO, kQLanes>(W, ring, nvg, nvg, pl, i0, sb, Ee, R, lo, hi_col,
+                                                                 m_min, tl, th);
+            }
+        }
+        // the next pass's loads before the serial update (their latency is
+        // covered by it)
+        const bool do_pass = j + 2 <= niter;
+        uint32_t raw[32];
+        if (do_pass) pass_load(j + 2, raw);
+        // serial update: blocks in the order of groups 0, 1, 3, 2
+        uint32_t o[kBlock];
+        if (g == 0) block_fsm<kBlock>(F, W, o);
+        {   // 0 -> 1
+            auto a = __builtin_amdgcn_permlane16_swap(F.s0, F.s0, false, false);
+            auto b = __builtin_amdgcn_permlane16_swap(F.s1, F.s1, false, false);
+            auto c = __builtin_amdgcn_permlane16_swap(F.s2, F.s2, false, false);
+            F.s0 = a[0]; F.s1 = b[0]; F.s2 = c[0];
+        }
+        if (g == 1) block_fsm<kBlock>(F, W, o);
+        {   // 1 -> 3
+            auto a = __builtin_amdgcn_permlane32_swap(F.s0, F.s0, false, false);
+            auto b = __builtin_amdgcn_permlane32_swap(F.s1, F.s1, false, false);
+            auto c = __builtin_amdgcn_permlane32_swap(F.s2, F.s2, false, false);
+            F.s0 = a[0]; F.s1 = b[0]; F.s2 = c[0];
+        }
+        if (g == 3) block_fsm<kBlock>(F, W, o);
+        {   // 3 -> 2
+            auto a = __builtin_amdgcn_permlane16_swap(F.s0, F.s0, false, false);
+            auto b = __builtin_amdgcn_permlane16_swap(F.s1, F.s1, false, false);
+            auto c = __builtin_amdgcn_permlane16_swap(F.s2, F.s2, false, false);
+            F.s0 = a[1]; F.s1 = b[1]; F.s2 = c[1];
+        }
+        if (g == 2) block_fsm<kBlock>(F, W, o);
+        {   // 2 -> 0
+            auto a = __builtin_amdgcn_permlane32_swap(F.s0, F.s0, false, false);
+            auto b = __builtin_amdgcn_permlane32_swap(F.s1, F.s1, false, false);
+            auto c = __builtin_amdgcn_permlane32_swap(F.s2, F.s2, false, false);
+            F.s0 = a[1]; F.s1 = b[1]; F.s2 = c[1];
+        }
+        block_count<kBlock, false>(F, o, X, i0, ebits);
+        if (do_pass) {
+            pass_finish(j + 2, raw);
+            finish_text(Tn, raw);
+            start_text(Tc, raw);
+        }
+    };
+    int j = 0;
+    for (; j + 1 < niter; j += 2) {
+        iteration(j, TA, TB);
+        iteration(j + 1, TB, TA);
+    }
+    if (j < niter) iteration(j, TA, TB);
+    const int nwin = kQWin * niter;
+
+    // ---- sum the four groups' counters (each group then holds the total)
+    uint32_t cnt[32];
+    cnt[0] = F.ones; cnt[1] = F.twos; cnt[2] = F.fours;
+#pragma unroll
+    for (int b = 0; b < 8; b++) cnt[3 + b] = F.e[b];
+    {
+        uint32_t cy = 0u;
+#pragma unroll
+        for (int b = 0; b < 11; b++) {   // + the partner group in the same 32-lane half
+            const auto sw = __builtin_amdgcn_permlane16_swap(cnt[b], cnt[b], false, false);
+            const uint32_t o = (g & 1) ? (uint32_t)sw[0] : (uint32_t)sw[1];
+            const uint32_t s_ = gate<kTTXor3>(cnt[b], o, cy);
+            cy = gate<kTTMaj>(cnt[b], o, cy);
+            cnt[b] = s_;
+        }
+        cy = 0u;
+#pragma unroll
+        for (int b = 0; b < 11; b++) {   // + the other half
+            const auto sw = __builtin_amdgcn_permlane32_swap(cnt[b], cnt[b], false, false);
+            const uint32_t o = (g >= 2) ? (uint32_t)sw[0] : (uint32_t)sw[1];
+            const uint32_t s_ = gate<kTTXor3>(cnt[b], o, cy);
+            cy = gate<kTTMaj>(cnt[b], o, cy);
+            cnt[b] = s_;
+        }
+    }
+#pragma unroll
+    for (int b = 11; b < 32; b++)
+        cnt[b] = (b >= 16 && b < 16 + kLenBits && !uniform) ? lbv[(b - 16) * kQLanes] : 0u;
+    cnt[16 + kLenBits] = valid;
+    transpose32(cnt);  // cnt[k]: ones of S over windows [0, nwin) | length << 16 | valid << 27
+    // group g writes pairs k = 8g .. 8g+7 of its lanes
+    int left_out = __builtin_amdgcn_readfirstlane(left);
+    asm volatile("" : "+s"(left_out));
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        const uint32_t w = g == 0 ? cnt[i] : (g == 1 ? cnt[8 + i] : (g == 2 ? cnt[16 + i] : cnt[24 + i]));
+        const int kk = 8 * g + i;
+        const int64_t p = base + (int64_t)kk * kQLanes + pl;
+        if (!full && kk * kQLanes + pl >= left_out) continue;
+        const int m = uniform ? m_max : (int)((w >> 16) & ((1u << kLenBits) - 1));
+        uint8_t acc;
+        int16_t pc;
+        if (!((w >> (16 + kLenBits)) & 1u)) {
+            acc = 0xFF;
+            pc = -1;
+        } else {
+            const int ones = (int)(w & 0xFFFFu) - (nwin - m);   // S stays 1 on [m, nwin)
+            const int E = J.Edec ? J.Edec[p] : J.E;
+            acc = ones <= E ? 1 : 0;
+            pc = (int16_t)ones;
+        }
+        const int64_t o = J.perm ? J.perm[p] : p;
+        J.out_accept[o] = acc;
+        if (J.out_popcount) J.out_popcount[o] = pc;
+    }
+}
+
 template <bool RO>
 __device__ __forceinline__ void plain_wave(const PlainParams &prm, uint32_t *lds_all) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -1089,6 +1456,73 @@ __global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_tiles_kernel
     J.base = tile.x;
     J.n = (int64_t)tile.x + tile.y;
     filter_group<false>(J, lds_all + (size_t)wave * (prm.lds_wave_bytes / 4), prm.R, lane);
+}
+
+// Quarter layout (large E): wavefronts of 512 pairs.
+template <bool RO>
+__device__ __forceinline__ void plain_wave4(const PlainParams &prm, uint32_t *lds_all) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    GroupJob J;
+    J.reads = prm.reads;
+    J.refs = prm.refs;
+    J.ld = prm.ld;
+    J.lengths = prm.lengths;
+    J.max_len = prm.max_len;
+    J.Ee = prm.Ee;
+    J.E = prm.E;
+    J.Edec = nullptr;
+    J.perm = nullptr;
+    J.out_accept = prm.out_accept;
+    J.out_popcount = prm.out_popcount;
+    J.ref_lengths = nullptr;
+    J.len_bits = kLenBits;
+    J.mode = 0;
+    J.base = ((int64_t)blockIdx.x * kWavesPerGroup + wave) * kQPairs;
+    J.n = prm.n;
+    if (J.base >= J.n) return;
+    filter_group4<RO>(J, lds_all + (size_t)wave * (prm.lds_wave_bytes / 4), prm.R, prm.qh, lane);
+}
+
+__global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_plain_q_kernel(PlainParams prm) {
+    extern __shared__ uint32_t lds_all[];
+    plain_wave4<false>(prm, lds_all);
+}
+
+__global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_plain_ring_q_kernel(PlainParams prm) {
+    extern __shared__ uint32_t lds_all[];
+    plain_wave4<true>(prm, lds_all);
+}
+
+// Batched tiles of the large-E class in the quarter layout: two wavefronts
+// per tile of at most 1024 pairs (512 each).
+__global__ __launch_bounds__(kWave * kWavesPerGroup, 2) void shouji_tiles_q_kernel(TilesParams prm) {
+    extern __shared__ uint32_t lds_all[];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int64_t t2 = (int64_t)blockIdx.x * prm.waves_per_group + wave;
+    const int64_t t = t2 >> 1;
+    if (wave >= prm.waves_per_group || t >= *prm.ntiles) return;
+    const int4 tile = prm.tiles[t];                      // start, count, Ee, -
+    GroupJob J;
+    J.reads = prm.breads;
+    J.refs = prm.brefs;
+    J.ld = prm.ld;
+    J.lengths = prm.blens;
+    J.ref_lengths = nullptr;
+    J.len_bits = kLenBits;
+    J.mode = 0;
+    J.max_len = prm.max_len;
+    J.Ee = tile.z;
+    J.E = 0;
+    J.Edec = prm.bE;
+    J.perm = prm.bperm;
+    J.out_accept = prm.out_accept;
+    J.out_popcount = prm.out_popcount;
+    J.base = (int64_t)tile.x + (t2 & 1) * kQPairs;
+    J.n = (int64_t)tile.x + tile.y;
+    if (J.base >= J.n) return;
+    filter_group4<false>(J, lds_all + (size_t)wave * (prm.lds_wave_bytes / 4), prm.R, prm.qh, lane);
 }
 
 }  // namespace shouji

@@ -237,3 +237,23 @@ def test_no_lengths_around_word_and_block_edges(sj):
         p = syninput.generate(1_500, m, E=min(3, max(m - 1, 0)), seed=1900 + m)
         for E in (0, 1, 5, 20):
             _check(sj, p, E, m, with_lengths=False)
+
+
+@pytest.mark.parametrize("E", [14, 20, 29, 30, 31])
+def test_quarter_layout_edges(sj, E):
+    # thresholds above 13 (with a length array) and above 22 (without) run the
+    # layout of four 16-lane groups with iterations of 32 windows: lengths at
+    # and next to those iterations' edges, a ragged wavefront (1,100 pairs),
+    # thresholds that clamp to m-1 for short pairs
+    for m in (1, 2, 3, 4, 31, 32, 33, 63, 64, 65, 96, 97, 250, 511, 512, 513, 1024):
+        p = syninput.generate(1_100, m, E=min(E, max(m - 1, 0)), seed=5100 + m + 7 * E)
+        for with_lengths in (True, False):
+            _check(sj, p, E, m, with_lengths=with_lengths)
+
+
+@pytest.mark.parametrize("E", [14, 23, 31])
+def test_quarter_layout_mixed_lengths(sj, E):
+    # mixed lengths inside every wavefront of 512 pairs: per-pair boundary
+    # masks from the length planes
+    p = syninput.generate(7_000, 40, 700, E=E, seed=5300 + E, p_repeat=0.3)
+    _check(sj, p, E, 700)
