@@ -63,8 +63,9 @@ struct VerifyParams {
     const int32_t *lengths;
     int32_t max_len;
     int32_t E;
-    const int64_t *list;              // pairs to verify
-    const unsigned long long *count;  // entries in list
+    const uint16_t *list;             // per segment of pairs, the indices to verify within it
+    const int32_t *seg_count;         // entries of each segment's list
+    int64_t nseg;                     // segments
     int16_t *out;
 };
 

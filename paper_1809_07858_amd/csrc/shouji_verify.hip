@@ -43,56 +43,77 @@
 
 namespace shouji {
 
-// out: -2 for pairs the filter did not accept, -3 for invalid lengths;
-// pairs to verify are appended to list (count in *count).  A workgroup
-// handles kCollectPairs pairs and reserves its slice of the list with one
-// atomic (one per 64 lanes serialises on the counter's address).
+// out: -2 for pairs the filter did not accept, -3 for invalid lengths.  A
+// workgroup handles one segment of kCollectPairs pairs: it writes the indices
+// (within the segment) of the pairs to verify to the segment's own slice of
+// the list and their number to seg_count, so that no workgroup waits on
+// another (a shared counter, taken with one atomic per workgroup, cost more
+// than the rest of the pass) and nothing needs clearing between calls.
 constexpr int kCollectBlock = 256;
 constexpr int kCollectPer = 16;
 constexpr int kCollectPairs = kCollectBlock * kCollectPer;
+static_assert(kCollectPairs <= 65536 && kCollectPairs % 256 == 0,
+              "indices within a segment are 16-bit; a verify workgroup lies in one segment");
 
 __global__ __launch_bounds__(kCollectBlock) void verify_collect_kernel(
         const uint8_t *__restrict__ accept, const int32_t *__restrict__ lengths, int32_t max_len, int64_t n,
-        int16_t *__restrict__ out, int64_t *__restrict__ list, unsigned long long *__restrict__ count) {
-    __shared__ int wave_total[kCollectBlock / 64];
-    __shared__ unsigned long long block_base;
+        int16_t *__restrict__ out, uint16_t *__restrict__ list, int32_t *__restrict__ seg_count) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t base = (int64_t)blockIdx.x * kCollectPairs + tid;
+    // every load of the lane first (none depends on another), then the tests
+    int32_t mv[kCollectPer];
+    uint32_t av[kCollectPer];
+#pragma unroll
+    for (int i = 0; i < kCollectPer; i++) {
+        const int64_t p = base + (int64_t)i * kCollectBlock;
+        const bool in = p < n;
+        mv[i] = in && lengths ? lengths[p] : max_len;
+        av[i] = in && accept ? accept[p] : 1u;
+    }
     uint32_t want = 0u;                        // bit i: pair base + i * kCollectBlock is verified
 #pragma unroll
     for (int i = 0; i < kCollectPer; i++) {
         const int64_t p = base + (int64_t)i * kCollectBlock;
-        if (p >= n) break;
-        const int32_t m = lengths ? lengths[p] : max_len;
-        if (m < 0 || m > max_len)
+        if (p >= n) continue;
+        if (mv[i] < 0 || mv[i] > max_len)
             out[p] = -3;
-        else if (accept && accept[p] != 1)
+        else if (av[i] != 1u)
             out[p] = -2;
         else
             want |= 1u << i;
     }
-    // exclusive prefix of the per-lane counts over the workgroup
-    const int c = __popc(want);
-    int incl = c;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int v = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += v;
+    // the list in pair order (pair tid + i * kCollectBlock is cell (i, wave)
+    // of the workgroup, cells ordered i first), so that a verify wavefront
+    // reads the words of neighbouring pairs: per cell the wanted pairs of
+    // lower lanes, then an exclusive scan over the 64 cells
+    constexpr int NW = kCollectBlock / 64;
+    static_assert(kCollectPer * NW == 64, "one lane per cell in the scan");
+    __shared__ int cell[kCollectPer * NW];
+    const uint64_t lower = (1ull << lane) - 1ull;
+    int below[kCollectPer];
+#pragma unroll
+    for (int i = 0; i < kCollectPer; i++) {
+        const uint64_t b = __ballot((want >> i) & 1u);
+        below[i] = __popcll(b & lower);
+        if (lane == 0) cell[i * NW + wave] = __popcll(b);
     }
-    if (lane == 63) wave_total[wave] = incl;
     __syncthreads();
-    int before = 0, total = 0;
-    for (int w = 0; w < kCollectBlock / 64; w++) {
-        before += w < wave ? wave_total[w] : 0;
-        total += wave_total[w];
+    if (wave == 0) {
+        const int v = cell[lane];
+        int incl = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += u;
+        }
+        cell[lane] = incl - v;
+        if (lane == 63) seg_count[blockIdx.x] = incl;
     }
-    if (tid == 0) block_base = total ? atomicAdd(count, (unsigned long long)total) : 0ull;
     __syncthreads();
-    int64_t slot = (int64_t)block_base + before + incl - c;
+    uint16_t *seg = list + (int64_t)blockIdx.x * kCollectPairs;
+#pragma unroll
     for (int i = 0; i < kCollectPer; i++)
-        if (want & (1u << i)) list[slot++] = base + (int64_t)i * kCollectBlock;
+        if (want & (1u << i)) seg[cell[i * NW + wave] + below[i]] = (uint16_t)(tid + i * kCollectBlock);
 }
-
-__global__ void zero_counter_kernel(unsigned long long *count) { *count = 0ull; }
 
 // The 16 low code bits (or, for w >> 1, high code bits) of a packed word of
 // 16 bases, as bits 0..15.
@@ -126,9 +147,14 @@ __global__ __launch_bounds__(256) void verify_myers_kernel(VerifyParams prm) {
     constexpr int NF = 4 * BW;                 // 16-bit fields of the window
     constexpr int NWW = NF / 2;                // 32-bit words of the window
     const int K = prm.E;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)*prm.count) return;
-    const int64_t p = prm.list[t];
+    // workgroup g takes entries 256 (g / nseg) .. +255 of segment g % nseg's
+    // list: consecutive workgroups, which the dispatcher deals round the XCDs,
+    // take different segments, and the workgroups past a segment's count
+    // (which return at once) come last
+    const int64_t s = (int64_t)blockIdx.x % prm.nseg;
+    const int k = (int)((int64_t)blockIdx.x / prm.nseg) * 256 + (int)threadIdx.x;
+    if (k >= prm.seg_count[s]) return;
+    const int64_t p = s * kCollectPairs + prm.list[s * kCollectPairs + k];
     const int m = prm.lengths ? prm.lengths[p] : prm.max_len;
     if (m == 0) {                              // empty pair: distance 0, no word to read
         prm.out[p] = 0;
@@ -170,10 +196,18 @@ __global__ __launch_bounds__(256) void verify_myers_kernel(VerifyParams prm) {
     int A = K + 1;
     // Operands of the column step held in VGPRs (opaque to the compiler): the
     // SIMD runs two wavefronts' VALU instructions side by side only when every
-    // operand is a VGPR.  obase: window offset of column 16c+1.
+    // operand is a VGPR.  obase: window offset of column 16c+1; ou[u] = obase+u,
+    // the offset of column 16c+1+u, which is also where bit u of the chunk's
+    // reference code planes sits once they are shifted left by obase.
     uint32_t obase = (uint32_t)(16 * BW - 1 - K), one = 1u;
     asm volatile("" : "+v"(obase), "+v"(one));
     const V vone = (V)one;
+    uint32_t ou[16];
+#pragma unroll
+    for (int u = 0; u < 16; u++) {
+        ou[u] = obase + (uint32_t)u;
+        asm volatile("" : "+v"(ou[u]));
+    }
 
     // the planes of the band at window offset o (0 <= o <= 30)
     auto planes = [&](const uint32_t (&w)[NWW], uint32_t o) -> V {
@@ -192,8 +226,9 @@ __global__ __launch_bounds__(256) void verify_myers_kernel(VerifyParams prm) {
     // The step folds the band's shift into the recurrence: with the +1 that
     // enters above the top row, the new bottom row's +1 and the old top row's
     // difference follow from Xv alone (the top bit of Pv stays 1 and that of Mv
-    // stays 0 through every step).
-    auto column = [&](V tl, V th, uint32_t o, auto in_tag) {
+    // stays 0 through every step).  Returns Xv, whose bit 0 gives the change
+    // of A = D[j-1-K][j]: A_new = A + 1 - (bit 0 of Xv).
+    auto column = [&](V tl, V th, uint32_t o, auto in_tag) -> V {
         constexpr bool IN = decltype(in_tag)::value;
         const V Plo = planes(wlo, o), Phi = planes(whi, o);
         // match bits: P[i-1] == T[j-1]
@@ -204,11 +239,9 @@ __global__ __launch_bounds__(256) void verify_myers_kernel(VerifyParams prm) {
         const V Ph = Mv | ~(Xh | Pv);
         const V Mh = Pv & Xh;
         const V xs = Xv >> vone;
-        // A = D[j-1-K][j] = D[j-2-K][j] + (vertical difference of the old top
-        // row) = A + 1 - (bit 0 of Xv)
-        A += (int)one - (int)(Xv & vone);
         Pv = Mh | ~(xs | Ph);
         Mv = Ph & xs;
+        return Xv;
     };
     auto popc = [](V x) { return (int)__builtin_popcountll((unsigned long long)x); };
 
@@ -239,17 +272,24 @@ __global__ __launch_bounds__(256) void verify_myers_kernel(VerifyParams prm) {
         const uint32_t tlo = code_plane(tw), thi = code_plane(tw >> 1);
         // rows above row 1 only in the first chunks (16c <= K)
         auto chunk = [&](auto in_tag) {
-            uint32_t o = obase;
             if (16 * c + 16 <= m) {
+                // bit 0 of each column's Xv enters at bit 31 of xb; after the
+                // 16 columns bits 16..31 hold them all
+                const uint32_t tls = tlo << obase, ths = thi << obase;
+                uint32_t xb = 0u;
 #pragma unroll
                 for (int u = 0; u < 16; u++) {
-                    column(base_mask<V>(tlo, u), base_mask<V>(thi, u), o, in_tag);
-                    o += one;
-                    asm volatile("" : "+v"(o));
+                    const V tl = (V)(int64_t)(int32_t)__builtin_amdgcn_sbfe(tls, ou[u], one);
+                    const V th = (V)(int64_t)(int32_t)__builtin_amdgcn_sbfe(ths, ou[u], one);
+                    const V Xv = column(tl, th, ou[u], in_tag);
+                    xb = __builtin_amdgcn_alignbit((uint32_t)Xv, xb, one);
                 }
+                A += 16 - __popc(xb >> 16);
             } else {
+                uint32_t o = obase;
                 for (int u = 0; u < m - 16 * c; u++) {
-                    column(base_mask<V>(tlo, u), base_mask<V>(thi, u), o, in_tag);
+                    const V Xv = column(base_mask<V>(tlo, u), base_mask<V>(thi, u), o, in_tag);
+                    A += (int)one - (int)((uint32_t)Xv & one);
                     o += one;
                 }
             }
@@ -280,7 +320,8 @@ __global__ __launch_bounds__(256) void verify_myers_kernel(VerifyParams prm) {
 extern "C" int64_t shouji_verify_workspace_bytes(int64_t n_pairs) {
     if (n_pairs < 0) return shouji::set_error(SHOUJI_ERR_ARG, "shouji_verify_workspace_bytes: n_pairs < 0");
     shouji::clear_error();
-    return 256 + n_pairs * (int64_t)sizeof(int64_t);
+    const int64_t nseg = (n_pairs + shouji::kCollectPairs - 1) / shouji::kCollectPairs;
+    return (nseg * 4 + 255) / 256 * 256 + nseg * shouji::kCollectPairs * (int64_t)sizeof(uint16_t);
 }
 
 extern "C" int shouji_verify(const uint32_t *reads, const uint32_t *refs, const int32_t *lengths, int32_t E,
@@ -301,15 +342,17 @@ extern "C" int shouji_verify(const uint32_t *reads, const uint32_t *refs, const 
     if (workspace_bytes < shouji_verify_workspace_bytes(n_pairs))
         return set_error(SHOUJI_ERR_ARG, "shouji_verify: workspace of %lld bytes, %lld needed",
                          (long long)workspace_bytes, (long long)shouji_verify_workspace_bytes(n_pairs));
-    if ((n_pairs + 255) / 256 > 0x7fffffff) return set_error(SHOUJI_ERR_ARG, "shouji_verify: n_pairs too large");
+    if ((n_pairs + shouji::kCollectPairs - 1) / shouji::kCollectPairs * (shouji::kCollectPairs / 256) > 0x7fffffff)
+        return set_error(SHOUJI_ERR_ARG, "shouji_verify: n_pairs too large");
     hipStream_t st = (hipStream_t)stream;
-    auto *count = reinterpret_cast<unsigned long long *>(workspace);
-    auto *list = reinterpret_cast<int64_t *>(reinterpret_cast<char *>(workspace) + 256);
-    const unsigned grid = (unsigned)((n_pairs + 255) / 256);
-    const unsigned cgrid = (unsigned)((n_pairs + shouji::kCollectPairs - 1) / shouji::kCollectPairs);
-    hipLaunchKernelGGL(shouji::zero_counter_kernel, dim3(1), dim3(1), 0, st, count);
-    hipLaunchKernelGGL(shouji::verify_collect_kernel, dim3(cgrid), dim3(shouji::kCollectBlock), 0, st,
-                       filter_accept, lengths, max_len, n_pairs, out_distance, list, count);
+    // workspace: per segment of kCollectPairs pairs, its count (int32), then
+    // its list of indices within the segment (uint16)
+    const int64_t nseg = (n_pairs + shouji::kCollectPairs - 1) / shouji::kCollectPairs;
+    auto *seg_count = reinterpret_cast<int32_t *>(workspace);
+    auto *list = reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(workspace) + (nseg * 4 + 255) / 256 * 256);
+    const unsigned grid = (unsigned)(nseg * (shouji::kCollectPairs / 256));
+    hipLaunchKernelGGL(shouji::verify_collect_kernel, dim3((unsigned)nseg), dim3(shouji::kCollectBlock), 0, st,
+                       filter_accept, lengths, max_len, n_pairs, out_distance, list, seg_count);
     shouji::VerifyParams prm;
     prm.reads = reads;
     prm.refs = refs;
@@ -318,7 +361,8 @@ extern "C" int shouji_verify(const uint32_t *reads, const uint32_t *refs, const 
     prm.max_len = max_len;
     prm.E = E;
     prm.list = list;
-    prm.count = count;
+    prm.seg_count = seg_count;
+    prm.nseg = nseg;
     prm.out = out_distance;
     // the band vector that holds rows j-E .. j+E+1 (2E+2 rows): 32 or 64 bits
     if (E <= 15)
