@@ -55,20 +55,6 @@ struct LocalParams {
     int32_t lds_wave_bytes;
 };
 
-// Verifier of filtered pairs (banded edit distance, one pair per lane).
-struct VerifyParams {
-    const uint32_t *reads;
-    const uint32_t *refs;
-    int64_t ld;
-    const int32_t *lengths;
-    int32_t max_len;
-    int32_t E;
-    const uint16_t *list;             // per segment of pairs, the indices to verify within it
-    const int32_t *seg_count;         // entries of each segment's list
-    int64_t nseg;                     // segments
-    int16_t *out;
-};
-
 // One group of up to 1024 pairs [base, min(base+1024, n)) for filter_group.
 struct GroupJob {
     const uint32_t *reads;

@@ -43,6 +43,20 @@
 
 namespace shouji {
 
+// Verifier of filtered pairs (banded edit distance, one pair per lane).
+struct VerifyParams {
+    const uint32_t *reads;
+    const uint32_t *refs;
+    int64_t ld;
+    const int32_t *lengths;
+    int32_t max_len;
+    int32_t E;
+    const uint16_t *list;             // per segment of pairs, the indices to verify within it
+    const int32_t *seg_count;         // entries of each segment's list
+    int64_t nseg;                     // segments
+    int16_t *out;
+};
+
 // out: -2 for pairs the filter did not accept, -3 for invalid lengths.  A
 // workgroup handles one segment of kCollectPairs pairs: it writes the indices
 // (within the segment) of the pairs to verify to the segment's own slice of
