@@ -607,9 +607,9 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     const int m_words = lmax < 0 ? 0 : (TWO ? max(lmax, rmax) : lmax);
     const bool uniform = !TWO && (m_min == m_max);
     // RO: the wavefront's LDS holds the ring only (every pair has max_len
-    // bases, so the lengths are uniform): masks from the positions
+    // bases, so the lengths are uniform): masks from the positions, as for
+    // any group whose valid pairs all have one length
     static_assert(!(TWO && RO), "the two-length form keeps its masks in LDS");
-    const int reg_mlen = RO ? m_max : -1;
     if (!uniform) {
         // bit planes of the lengths, kept in LDS (read by the boundary masks
         // and the output only); with one length for all valid pairs none are
@@ -681,13 +681,9 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
         }
     };
     // per-lane masks of positions i0 .. i0+count-1, stored at dst[s * 32]
-    auto fill_masks = [&](int i0, uint32_t *dst, int count) {
-        if (uniform) {
-            for (int s = 0; s < count; s++) dst[s * kPairLanes] = i0 + s >= m_max ? ~0u : 0u;
-        } else {
-            fill_range(i0, count, lbv, dst);
-        }
-    };
+    // (groups of mixed lengths; a group of one length takes its masks from
+    // the positions)
+    auto fill_masks = [&](int i0, uint32_t *dst, int count) { fill_range(i0, count, lbv, dst); };
     // TWO: text masks of i0 .. i0+C-1 and pattern masks of i0-Ee .. i0+C-1+Ee
     // (a negative pattern position is outside the read)
     auto fill_masks2 = [&](int i0, uint32_t *dst, uint32_t *dstp, int C) {
@@ -804,12 +800,20 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
             for (int t = 0; t < kCols; t++) { tl[t] = Tc[2 * t]; th[t] = Tc[2 * t + 1]; }
             const int sb = i0 % R;
             if ((Ee > lo) || (hi_col + Ee >= m_min)) {
-                if constexpr (TWO)
+                if constexpr (TWO) {
                     fill_masks2(i0, nvh, nvph, kCols);
-                else if (!RO)
+                    block_winners<kBlock, TWO, true, false>(W, ring, nvh, nvph, pl, i0, sb, Ee, R, lo, hi_col,
+                                                            m_min, tl, th);
+                } else if (RO || uniform) {
+                    // one length for every valid pair: the masks follow from
+                    // the positions, as without a length array
+                    block_winners<kBlock, false, true, true>(W, ring, nvh, nvph, pl, i0, sb, Ee, R, lo, hi_col,
+                                                             m_min, tl, th, m_max);
+                } else {
                     fill_masks(i0, nvh, kCols + Ee);
-                block_winners<kBlock, TWO, true, RO>(W, ring, nvh, nvph, pl, i0, sb, Ee, R, lo, hi_col, m_min,
-                                                     tl, th, reg_mlen);
+                    block_winners<kBlock, false, true, false>(W, ring, nvh, nvph, pl, i0, sb, Ee, R, lo, hi_col,
+                                                              m_min, tl, th);
+                }
             } else {
                 // interior: every pattern index i0+t-d lies in [0, m_min) and every
                 // text column below m_min, so no candidate needs a mask
@@ -856,13 +860,19 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
         }
         uint32_t *nvs = nv + NB * half * kPairLanes + pl;
         uint32_t *nvps = nvp + NB * half * kPairLanes + pl;
-        if constexpr (TWO)
-            fill_masks2(i0, nvs, nvps, C);
-        else if (!RO)
-            fill_masks(i0, nvs, C + Ee);
         Winner<NB> W;
-        block_winners<NB, TWO, true, RO>(W, ring, nvs, nvps, pl, i0, i0 % R, Ee, R, lo, lo + NB + C - 1, m_min,
-                                         tl, th, reg_mlen);
+        if constexpr (TWO) {
+            fill_masks2(i0, nvs, nvps, C);
+            block_winners<NB, TWO, true, false>(W, ring, nvs, nvps, pl, i0, i0 % R, Ee, R, lo, lo + NB + C - 1,
+                                                m_min, tl, th);
+        } else if (RO || uniform) {
+            block_winners<NB, false, true, true>(W, ring, nvs, nvps, pl, i0, i0 % R, Ee, R, lo, lo + NB + C - 1,
+                                                 m_min, tl, th, m_max);
+        } else {
+            fill_masks(i0, nvs, C + Ee);
+            block_winners<NB, false, true, false>(W, ring, nvs, nvps, pl, i0, i0 % R, Ee, R, lo, lo + NB + C - 1,
+                                                  m_min, tl, th);
+        }
         uint32_t o[NB];
         if (half == 0) block_fsm<NB>(F, W, o);
         F.s0 = from_half0(F.s0); F.s1 = from_half0(F.s1); F.s2 = from_half0(F.s2);
@@ -1096,7 +1106,6 @@ __device__ __forceinline__ void filter_group4(const GroupJob &J, uint32_t *lds, 
     const int m_max = lmax < 0 ? 0 : lmax;
     const int m_min = lmax < 0 ? 0 : lmin;
     const bool uniform = m_min == m_max;
-    const int reg_mlen = RO ? m_max : -1;
     if (!uniform) {
         transpose32(lenw);             // lenw[b] = bit b of the 32 lengths
 #pragma unroll
@@ -1115,38 +1124,35 @@ __device__ __forceinline__ void filter_group4(const GroupJob &J, uint32_t *lds, 
     const int nhalves = (m_max + kHalf - 1) / kHalf;   // words holding positions < m_max
 
     // masks "position x is past the pair's end" for positions x0 .. x0+count-1
-    // (as in filter_group)
+    // (as in filter_group; groups of mixed lengths only, a group of one
+    // length takes its masks from the positions)
     auto fill_masks = [&](int i0, uint32_t *dst, int count) {
-        if (uniform) {
-            for (int s = 0; s < count; s++) dst[s * kQLanes] = i0 + s >= m_max ? ~0u : 0u;
-        } else {
-            int x0 = i0;
-            asm volatile("" : "+v"(x0));
-            uint32_t lb[kLenBits];
+        int x0 = i0;
+        asm volatile("" : "+v"(x0));
+        uint32_t lb[kLenBits];
 #pragma unroll
-            for (int b = 0; b < kLenBits; b++) lb[b] = lbv[b * kQLanes];
-            uint32_t msk = ~0u;
-            for (int s = 0; s < count; s++) {
-                const int x = x0 + s;
-                if (s == 0) {
-                    uint32_t gt = 0u;  // gt = (length > x)
+        for (int b = 0; b < kLenBits; b++) lb[b] = lbv[b * kQLanes];
+        uint32_t msk = ~0u;
+        for (int s = 0; s < count; s++) {
+            const int x = x0 + s;
+            if (s == 0) {
+                uint32_t gt = 0u;  // gt = (length > x)
 #pragma unroll
-                    for (int b = 0; b < kLenBits; b++) {
-                        const uint32_t sx = ((x >> b) & 1) ? ~0u : 0u;
-                        gt = mux(sx, lb[b] & gt, lb[b] | gt);
-                    }
-                    msk = ~gt;
-                } else {
-                    uint32_t e = ~0u;  // e = (length == x)
-#pragma unroll
-                    for (int b = 0; b < kLenBits; b++) {
-                        const uint32_t sx = ((x >> b) & 1) ? ~0u : 0u;
-                        e = gate<kTTAndXnor>(e, lb[b], sx);
-                    }
-                    msk |= e;
+                for (int b = 0; b < kLenBits; b++) {
+                    const uint32_t sx = ((x >> b) & 1) ? ~0u : 0u;
+                    gt = mux(sx, lb[b] & gt, lb[b] | gt);
                 }
-                dst[s * kQLanes] = msk;
+                msk = ~gt;
+            } else {
+                uint32_t e = ~0u;  // e = (length == x)
+#pragma unroll
+                for (int b = 0; b < kLenBits; b++) {
+                    const uint32_t sx = ((x >> b) & 1) ? ~0u : 0u;
+                    e = gate<kTTAndXnor>(e, lb[b], sx);
+                }
+                msk |= e;
             }
+            dst[s * kQLanes] = msk;
         }
     };
 
@@ -1247,9 +1253,14 @@ __device__ __forceinline__ void filter_group4(const GroupJob &J, uint32_t *lds, 
             for (int t = 0; t < kCols; t++) { tl[t] = Tc[2 * t]; th[t] = Tc[2 * t + 1]; }
             const int sb = i0 % R;
             if ((Ee > lo) || (hi_col + Ee >= m_min)) {
-                if (!RO) fill_masks(i0, nvg, kCols + Ee);
-                block_winners<kBlock, false, true, RO, kQLanes>(W, ring, nvg, nvg, pl, i0, sb, Ee, R, lo, hi_col,
-                                                                m_min, tl, th, reg_mlen);
+                if (RO || uniform) {
+                    block_winners<kBlock, false, true, true, kQLanes>(W, ring, nvg, nvg, pl, i0, sb, Ee, R, lo,
+                                                                      hi_col, m_min, tl, th, m_max);
+                } else {
+                    fill_masks(i0, nvg, kCols + Ee);
+                    block_winners<kBlock, false, true, false, kQLanes>(W, ring, nvg, nvg, pl, i0, sb, Ee, R, lo,
+                                                                       hi_col, m_min, tl, th);
+                }
             } else {
                 block_winners<kBlock, false, false, RO, kQLanes>(W, ring, nvg, nvg, pl, i0, sb, Ee, R, lo, hi_col,
                                                                  m_min, tl, th);
