@@ -521,20 +521,24 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
 #pragma unroll
         for (int k = 0; k < 32; k++) raw0[k] = 0u;
     }
-    const int32_t *lp = J.lengths ? J.lengths + base : nullptr;
+    // RO kernels are launched without a length array (every pair has
+    // max_len bases), the others always with one: the choice is made at
+    // compile time, so the length is not a per-lane select that keeps
+    // max_len in a vector register
+    const int32_t *lp = RO ? nullptr : J.lengths + base;
     const int32_t *tp = TWO ? J.ref_lengths + base : nullptr;
     int mv[32], mtv[TWO ? 32 : 1];
     if (full) {
 #pragma unroll
         for (int k = 0; k < 32; k++) {
-            mv[k] = lp ? lp[k * kPairLanes + pl] : J.max_len;
+            mv[k] = RO ? J.max_len : lp[k * kPairLanes + pl];
             if constexpr (TWO) mtv[k] = tp[k * kPairLanes + pl];
         }
     } else {
 #pragma unroll
         for (int k = 0; k < 32; k++) {
             const int qi = min(k * kPairLanes + pl, left - 1);
-            mv[k] = lp ? lp[qi] : J.max_len;
+            mv[k] = RO ? J.max_len : lp[qi];
             if constexpr (TWO) mtv[k] = tp[qi];
         }
     }
@@ -1056,16 +1060,16 @@ __device__ __forceinline__ void filter_group4(const GroupJob &J, uint32_t *lds, 
     uint32_t lenw[32];
     uint32_t valid = 0u;
     int lmin = 0x7fffffff, lmax = -1;
-    const int32_t *lp = J.lengths ? J.lengths + base : nullptr;
+    const int32_t *lp = RO ? nullptr : J.lengths + base;   // as in filter_group
     int mv[32];
     if (full) {
 #pragma unroll
-        for (int k = 0; k < 32; k++) mv[k] = lp ? lp[k * kQLanes + pl] : J.max_len;
+        for (int k = 0; k < 32; k++) mv[k] = RO ? J.max_len : lp[k * kQLanes + pl];
     } else {
 #pragma unroll
         for (int k = 0; k < 32; k++) {
             const int qi = min(k * kQLanes + pl, left - 1);
-            mv[k] = lp ? lp[qi] : J.max_len;
+            mv[k] = RO ? J.max_len : lp[qi];
         }
     }
     bool fast = false;

@@ -257,3 +257,16 @@ def test_quarter_layout_mixed_lengths(sj, E):
     # masks from the length planes
     p = syninput.generate(7_000, 40, 700, E=E, seed=5300 + E, p_repeat=0.3)
     _check(sj, p, E, 700)
+
+
+@pytest.mark.parametrize("E", [3, 13, 14, 22, 31])
+def test_one_length_below_max_len(sj, E):
+    # wavefronts whose valid pairs share one length below max_len take their
+    # boundary masks from the positions, bounded by that length: a group of
+    # length m, a group of m and m-1 (per-pair masks), a ragged group of m-1,
+    # in both layouts (E <= 13: 1,024 pairs per wavefront, above: 512)
+    for m, max_len in ((90, 100), (33, 64), (200, 250)):
+        p = syninput.generate(3_000, m, E=min(E, m - 1), seed=7000 + m + E)
+        _check(sj, p, E, max_len)
+        p.lengths[1536:] = m - 1
+        _check(sj, p, E, max_len)
