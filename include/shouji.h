@@ -89,6 +89,32 @@ int shouji_filter(const uint32_t *reads, const uint32_t *refs, const int32_t *le
                   int64_t n_pairs, int32_t max_len, int64_t ld, void *stream);
 
 /*
+ * Relayout into the filters' input layout.
+ *
+ * The bases are stored in 2 bits each (Sec. 2.3: the filter streams four
+ * bases per byte of its link).  This converts sequences kept pair by pair,
+ * 32 bases per 64-bit word, into the word-major 16-base layout above (row r
+ * of a sequence, bases 16r..16r+15, at r * ld + p), on the device.
+ *
+ *   src           n_pairs * words_per_seq uint64 (device): pair p's words at
+ *                 src[p * words_per_seq + w], base j of the sequence in bits
+ *                 2(j mod 32)..2(j mod 32)+1 of its word j / 32 (the code of
+ *                 each base is kept as it is: only equality matters).
+ *   words_per_seq >= ceil(max_len / 32), else SHOUJI_ERR_ARG.
+ *   n_pairs       >= 0; 0 is a successful no-op.
+ *   max_len       0..SHOUJI_MAX_LEN: dst receives ceil(max_len / 16) rows.
+ *   dst           ceil(max_len / 16) rows of ld uint32 (device), written for
+ *                 pairs 0..n_pairs-1 (other columns untouched); owned by the
+ *                 caller, nothing is allocated.
+ *   ld            leading dimension of dst in words, >= n_pairs.
+ *   stream        hipStream_t or NULL.
+ * Call it once for the reads and once for the references.  Errors
+ * (SHOUJI_ERR_ARG / _RANGE / _NULL) are reported before anything is launched.
+ */
+int shouji_relayout_pair_major(const uint64_t *src, int64_t words_per_seq, int64_t n_pairs, int32_t max_len,
+                               uint32_t *dst, int64_t ld, void *stream);
+
+/*
  * Two-length form: reads and reference segments of different lengths, and
  * local or glocal counting.
  *

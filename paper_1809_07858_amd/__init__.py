@@ -95,6 +95,8 @@ def lib():
         L.shouji_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
         L.shouji_server_destroy.restype = ctypes.c_int
         L.shouji_server_destroy.argtypes = [vp]
+        L.shouji_relayout_pair_major.restype = ctypes.c_int
+        L.shouji_relayout_pair_major.argtypes = [vp, i64, i64, i32, vp, i64, vp]
         L.shouji_last_error.restype = ctypes.c_char_p
         L.shouji_version.restype = ctypes.c_int
         _lib = L
@@ -152,6 +154,45 @@ def pack_words_device(codes, max_len=None, ld=None, chunk=1 << 20):
         words = (buf.view(hi - lo, nw, BASES_PER_WORD) << shifts).sum(dim=2)
         words = torch.where(words >= 2 ** 31, words - 2 ** 32, words)
         out[:, lo:hi] = words.to(torch.int32).t()
+    return out
+
+
+def pack_pair_major(codes, max_len=None, words_per_seq=None):
+    """Base codes [n, stride] (uint8 0..3) -> [n, words_per_seq] uint64: each pair's
+    sequence 32 bases per 64-bit word, base j in bits 2(j%32)..2(j%32)+1 of word j/32
+    (words_per_seq defaults to ceil(max_len/32)).  The input of relayout_pair_major."""
+    codes = np.asarray(codes)
+    n, stride = codes.shape
+    max_len = stride if max_len is None else int(max_len)
+    need = (max_len + 31) // 32
+    wps = need if words_per_seq is None else int(words_per_seq)
+    if wps < need:
+        raise ValueError("words_per_seq %d < %d for max_len %d" % (wps, need, max_len))
+    buf = np.zeros((n, wps * 32), dtype=np.uint64)
+    w = min(stride, max_len)
+    buf[:, :w] = codes[:, :w] & 3
+    shifts = 2 * np.arange(32, dtype=np.uint64)
+    return np.bitwise_or.reduce(buf.reshape(n, wps, 32) << shifts, axis=2)
+
+
+def relayout_pair_major(src, max_len, n_pairs=None, ld=None, out=None, stream=None):
+    """Device relayout of pair-major 64-bit words (an int64 CUDA tensor [n, words_per_seq],
+    as from pack_pair_major) into the filters' word-major layout: an int32 CUDA tensor
+    [ceil(max_len/16), ld] (the same words pack_words gives for the same bases)."""
+    import torch
+    if src.dim() != 2 or not src.is_cuda or src.dtype != torch.int64 or not src.is_contiguous():
+        raise ValueError("src must be a contiguous int64 CUDA tensor [n_pairs, words_per_seq]")
+    n = src.shape[0] if n_pairs is None else int(n_pairs)
+    if n > src.shape[0]:
+        raise ValueError("n_pairs exceeds the rows of src")
+    ld = n if ld is None else int(ld)
+    if out is None:
+        out = torch.zeros((nwords(max_len), ld), dtype=torch.int32, device=src.device)
+    if out.dim() != 2 or out.dtype != torch.int32 or not out.is_contiguous() or out.shape[0] < nwords(max_len) \
+            or out.shape[1] != ld:
+        raise ValueError("out must be a contiguous int32 tensor [ceil(max_len/16), ld]")
+    _check(lib().shouji_relayout_pair_major(ctypes.c_void_p(src.data_ptr()), int(src.shape[1]), n, int(max_len),
+                                            ctypes.c_void_p(out.data_ptr()), ld, _stream_handle(stream)))
     return out
 
 

@@ -7,7 +7,7 @@ ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "libshouji.so")
 SOURCES = ["csrc/shouji_plain.hip", "csrc/shouji_batched.hip", "csrc/shouji_abi.hip",
            "csrc/shouji_server.hip", "csrc/shouji_verify.hip", "csrc/shouji_window.hip",
-           "csrc/shouji_magnet.hip"]
+           "csrc/shouji_magnet.hip", "csrc/shouji_relayout.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # no packed-FP32 instructions anywhere in the device code

@@ -161,3 +161,44 @@ def test_noalloc_batched_refuses_sizes_beyond_its_scratch():
     assert L.shouji_filter_batched_noalloc(vp, vp, None, vp, vp, None, -1, 300, 0, None, None) == -2
     assert L.shouji_filter_batched_noalloc(vp, vp, None, vp, vp, None, 10, 5000, 10, None, None) == -3
     assert L.shouji_filter_batched_noalloc(None, None, None, None, None, None, 0, 300, 0, None, None) == 0
+
+
+def _relayout(**kw):
+    a = dict(src=ctypes.c_void_p(16), wps=4, n=10, max_len=100, dst=ctypes.c_void_p(16), ld=10, stream=None)
+    a.update(kw)
+    return sj.lib().shouji_relayout_pair_major(a["src"], a["wps"], a["n"], a["max_len"], a["dst"], a["ld"],
+                                               a["stream"])
+
+
+def test_relayout_argument_errors_are_reported_before_launch():
+    assert _relayout(wps=3) == -2                  # 100 bases need 4 words of 32
+    assert b"words_per_seq" in sj.lib().shouji_last_error()
+    assert _relayout(n=-1) == -2
+    assert _relayout(max_len=2000) == -3
+    assert _relayout(src=None) == -1
+    assert _relayout(dst=None) == -1
+    assert _relayout(ld=9) == -2
+    assert _relayout(n=0, src=None, dst=None) == 0  # nothing to do
+    assert _relayout(max_len=0, wps=0, src=None, dst=None) == 0
+
+
+def test_pair_major_words_are_two_rows_of_the_filter_layout():
+    # a 64-bit word w of a pair (32 bases) is rows 2w (low half) and 2w+1 (high
+    # half) of the word-major 16-base layout: the relayout's expected output
+    rng = np.random.default_rng(5)
+    for m, max_len in ((100, 100), (33, 64), (250, 300), (16, 16), (1, 1)):
+        codes = rng.integers(0, 4, size=(37, m), dtype=np.uint8)
+        pm = sj.pack_pair_major(codes, max_len)
+        assert pm.shape == (37, (max_len + 31) // 32) and pm.dtype == np.uint64
+        wm = sj.pack_words(codes, max_len).view(np.uint32)
+        nr = wm.shape[0]
+        for r in range(nr):
+            half = (pm[:, r // 2] >> np.uint64(32 * (r % 2))) & np.uint64(0xFFFFFFFF)
+            assert np.array_equal(half.astype(np.uint32), wm[r])
+        # rows past ceil(max_len/16) are zero in the last 64-bit word
+        if nr % 2:
+            assert not np.any(pm[:, -1] >> np.uint64(32))
+    # base j of a sequence: bits 2(j%32).. of word j/32
+    codes = np.zeros((1, 64), dtype=np.uint8)
+    codes[0, 33] = 3
+    assert sj.pack_pair_major(codes)[0, 1] == np.uint64(3 << 2)
