@@ -175,7 +175,15 @@ __device__ __forceinline__ void candidate(Winner<NB> &W, const uint2 (&pv)[NB + 
         // Eq. 1: mismatch iff either code bit differs
         cell[t] = gate<kTTCell>(pv[t].x ^ tl[t], pv[t].y, th[t]);
     }
-    if (masked && TWO) {
+    if (masked && TWO && REGM) {
+        // text column i0+t past the reference (per-pair masks), pattern
+        // position i0+t-d outside the read (every read has length reg_mlen)
+#pragma unroll
+        for (int t = 0; t < C; t++) {
+            cell[t] |= nv[t * PL];
+            if (i0 + t - d < 0 || i0 + t - d >= reg_mlen) cell[t] = ~0u;
+        }
+    } else if (masked && TWO) {
         // text column i0+t past the reference, pattern position i0+t-d
         // outside the read
         const uint32_t *np = nvp + (Ee - d) * PL;
@@ -610,6 +618,9 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
     const int m_min = lmax < 0 ? 0 : (TWO ? min(lmin, rmin) : lmin);
     const int m_words = lmax < 0 ? 0 : (TWO ? max(lmax, rmax) : lmax);
     const bool uniform = !TWO && (m_min == m_max);
+    // TWO: every valid read has one length (rmax): the pattern-side masks
+    // follow from the positions, only the reference side needs its table
+    const bool read_uniform = TWO && lmax >= 0 && rmin == rmax;
     // RO: the wavefront's LDS holds the ring only (every pair has max_len
     // bases, so the lengths are uniform): masks from the positions, as for
     // any group whose valid pairs all have one length
@@ -805,9 +816,16 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
             const int sb = i0 % R;
             if ((Ee > lo) || (hi_col + Ee >= m_min)) {
                 if constexpr (TWO) {
-                    fill_masks2(i0, nvh, nvph, kCols);
-                    block_winners<kBlock, TWO, true, false>(W, ring, nvh, nvph, pl, i0, sb, Ee, R, lo, hi_col,
-                                                            m_min, tl, th);
+                    if (read_uniform) {
+                        // one read length: pattern masks from the positions
+                        fill_range(i0, kCols, lbv, nvh);
+                        block_winners<kBlock, TWO, true, true>(W, ring, nvh, nvph, pl, i0, sb, Ee, R, lo, hi_col,
+                                                               m_min, tl, th, rmax);
+                    } else {
+                        fill_masks2(i0, nvh, nvph, kCols);
+                        block_winners<kBlock, TWO, true, false>(W, ring, nvh, nvph, pl, i0, sb, Ee, R, lo, hi_col,
+                                                                m_min, tl, th);
+                    }
                 } else if (RO || uniform) {
                     // one length for every valid pair: the masks follow from
                     // the positions, as without a length array
@@ -866,9 +884,15 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
         uint32_t *nvps = nvp + NB * half * kPairLanes + pl;
         Winner<NB> W;
         if constexpr (TWO) {
-            fill_masks2(i0, nvs, nvps, C);
-            block_winners<NB, TWO, true, false>(W, ring, nvs, nvps, pl, i0, i0 % R, Ee, R, lo, lo + NB + C - 1,
-                                                m_min, tl, th);
+            if (read_uniform) {
+                fill_range(i0, C, lbv, nvs);
+                block_winners<NB, TWO, true, true>(W, ring, nvs, nvps, pl, i0, i0 % R, Ee, R, lo, lo + NB + C - 1,
+                                                   m_min, tl, th, rmax);
+            } else {
+                fill_masks2(i0, nvs, nvps, C);
+                block_winners<NB, TWO, true, false>(W, ring, nvs, nvps, pl, i0, i0 % R, Ee, R, lo, lo + NB + C - 1,
+                                                    m_min, tl, th);
+            }
         } else if (RO || uniform) {
             block_winners<NB, false, true, true>(W, ring, nvs, nvps, pl, i0, i0 % R, Ee, R, lo, lo + NB + C - 1,
                                                  m_min, tl, th, m_max);
