@@ -135,3 +135,30 @@ def test_argument_errors(sj):
         sj.shouji_filter_local(r, r, L, L, 2, mode=4, max_len=64)
     with pytest.raises(sj.ShoujiError):
         sj.shouji_filter_local(r, r, L, L, 40, mode=1, max_len=64)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+def test_reads_of_one_length(sj, mode):
+    # every valid read has one length: the pattern-side masks come from the
+    # positions (the reference side keeps its per-pair table); reads inside
+    # longer references, reads longer than their references, some invalid
+    # lengths among them, a ragged wavefront
+    rng = np.random.default_rng(40 + mode)
+    for m, max_len, E in ((100, 128, 5), (37, 64, 3), (60, 60, 8)):
+        n = 2_500
+        P = rng.integers(0, 4, (n, max_len)).astype(np.uint8)
+        T = rng.integers(0, 4, (n, max_len)).astype(np.uint8)
+        off = rng.integers(0, max_len - m + 1, n)
+        for i in range(n):
+            T[i, off[i]:off[i] + m] = P[i, :m]
+        T[rng.random((n, max_len)) < 0.03] = rng.integers(0, 4)
+        LP = np.full(n, m, np.int32)
+        LT = np.minimum(max_len, off + m + rng.integers(-20, 20, n)).astype(np.int32)
+        LT = np.maximum(LT, 0)
+        LP[5::97] = max_len + 3
+        print("case m=%d max_len=%d E=%d mode=%d" % (m, max_len, E, mode), flush=True)
+        ga, gp = _run(sj, P, T, LP, LT, E, mode, max_len)
+        bad = LP > max_len
+        assert (ga[bad] == 0xFF).all() and (gp[bad] == -1).all()
+        ea, ep = oracle.shouji_batch2(P[~bad], T[~bad], LP[~bad], LT[~bad], E=E, mode=mode)
+        assert np.array_equal(ga[~bad], ea) and np.array_equal(gp[~bad], ep)
