@@ -270,3 +270,29 @@ def test_one_length_below_max_len(sj, E):
         _check(sj, p, E, max_len)
         p.lengths[1536:] = m - 1
         _check(sj, p, E, max_len)
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_shapes(sj, seed):
+    # random batch sizes, maximum lengths and thresholds, with four length
+    # patterns: every pair max_len (also without the length array), one
+    # length below max_len for all, one length per block of 512 pairs (each
+    # wavefront's group of one length in either layout, a different one per
+    # group), and lengths mixed inside every group
+    rng = np.random.default_rng(9000 + seed)
+    n = int(rng.integers(1, 5_000))
+    max_len = int(rng.integers(1, 400))
+    E = int(rng.integers(0, 32))
+    pattern = seed % 4
+    p = syninput.generate(n, max_len, E=min(E, max(max_len - 1, 0)), seed=9100 + seed)
+    if pattern == 1:
+        p.lengths[:] = int(rng.integers(0, max_len + 1))
+    elif pattern == 2:
+        for b in range(0, n, 512):
+            p.lengths[b:b + 512] = int(rng.integers(0, max_len + 1))
+    elif pattern == 3:
+        p.lengths[:] = rng.integers(0, max_len + 1, n)
+    print("case seed=%d n=%d max_len=%d E=%d pattern=%d" % (seed, n, max_len, E, pattern), flush=True)
+    _check(sj, p, E, max_len)
+    if pattern == 0:
+        _check(sj, p, E, max_len, with_lengths=False)
