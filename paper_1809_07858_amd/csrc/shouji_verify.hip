@@ -140,6 +140,23 @@ __device__ __forceinline__ uint32_t code_plane(uint32_t w) {
     return x;
 }
 
+// Truth table of a three-input function for v_bitop3_b32 (bit a<<2|b<<1|c
+// of the immediate is f(a, b, c)) and the gate itself.
+template <class F>
+constexpr unsigned vtt(F f) {
+    unsigned t = 0;
+    for (int i = 0; i < 8; i++)
+        if (f((i >> 2) & 1, (i >> 1) & 1, i & 1)) t |= 1u << i;
+    return t;
+}
+constexpr unsigned kTTNotOrXor = vtt([](int a, int b, int c) { return !(a | (b ^ c)); });
+constexpr unsigned kTTXorOr = vtt([](int a, int b, int c) { return (a ^ b) | c; });
+constexpr unsigned kTTOrNor = vtt([](int a, int b, int c) { return a | !(b | c); });
+template <unsigned TT>
+__device__ __forceinline__ uint32_t bop3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, TT);
+}
+
 // All ones when bit u of a code plane is set, else zero, as a band vector
 // (the bit-field extract's result is unsigned: it is made signed before it
 // is widened, so that a 64-bit mask is all ones in both halves).
@@ -245,17 +262,31 @@ __global__ __launch_bounds__(256) void verify_myers_kernel(VerifyParams prm) {
     auto column = [&](V tl, V th, uint32_t o, auto in_tag) -> V {
         constexpr bool IN = decltype(in_tag)::value;
         const V Plo = planes(wlo, o), Phi = planes(whi, o);
-        // match bits: P[i-1] == T[j-1]
-        V Eq = ~((Plo ^ tl) | (Phi ^ th));
-        if constexpr (IN) Eq &= planes(win, o);
-        const V Xv = Eq | Mv;
-        const V Xh = (((Eq & Pv) + Pv) ^ Pv) | Eq;
-        const V Ph = Mv | ~(Xh | Pv);
-        const V Mh = Pv & Xh;
-        const V xs = Xv >> vone;
-        Pv = Mh | ~(xs | Ph);
-        Mv = Ph & xs;
-        return Xv;
+        if constexpr (W == 32 && !IN) {
+            // the same step with every three-input function as one gate
+            // (16 instructions per column with the extracts, the window
+            // offsets and the bit-0 collection)
+            const uint32_t Eq = bop3<kTTNotOrXor>(Plo ^ tl, Phi, th);   // P[i-1] == T[j-1]
+            const uint32_t Xv = Eq | Mv;
+            const uint32_t Xh = bop3<kTTXorOr>((Eq & Pv) + Pv, Pv, Eq);
+            const uint32_t Ph = bop3<kTTOrNor>(Mv, Xh, Pv);
+            const uint32_t xs = Xv >> vone;
+            Pv = bop3<kTTOrNor>(Pv & Xh, xs, Ph);
+            Mv = Ph & xs;
+            return Xv;
+        } else {
+            // match bits: P[i-1] == T[j-1]
+            V Eq = ~((Plo ^ tl) | (Phi ^ th));
+            if constexpr (IN) Eq &= planes(win, o);
+            const V Xv = Eq | Mv;
+            const V Xh = (((Eq & Pv) + Pv) ^ Pv) | Eq;
+            const V Ph = Mv | ~(Xh | Pv);
+            const V Mh = Pv & Xh;
+            const V xs = Xv >> vone;
+            Pv = Mh | ~(xs | Ph);
+            Mv = Ph & xs;
+            return Xv;
+        }
     };
     auto popc = [](V x) { return (int)__builtin_popcountll((unsigned long long)x); };
 
