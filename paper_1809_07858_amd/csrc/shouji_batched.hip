@@ -196,6 +196,7 @@ __global__ __launch_bounds__(kScatterThreads) void bin_scatter_lds_kernel(Scatte
     uint16_t *slotsrc = slotbin + CHUNK;
     uint32_t *buf = reinterpret_cast<uint32_t *>(slotsrc + CHUNK);
     __shared__ int32_t part[kScatterThreads];
+    static_assert(sizeof(part) == kScatterStaticLds, "the bin limit of the scatter counts this array");
     const int tid = threadIdx.x;
     const int64_t c0 = (int64_t)blockIdx.x * CHUNK;
     constexpr int PER = CHUNK / kScatterThreads;

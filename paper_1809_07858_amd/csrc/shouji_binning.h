@@ -33,9 +33,13 @@ constexpr int kScatterThreads = 1024;
 inline size_t scatter_lds_bytes(int nbins, int chunk) {
     return (size_t)nbins * 4 * 2 + 8 + (size_t)nbins * 8 + (size_t)chunk * (2 + 2 + 4);
 }
-// bins the staged scatter holds with chunks of `chunk` pairs (LDS of one CU)
+// LDS the staged scatter holds in static arrays (its scan's partial sums),
+// beside the dynamic LDS of scatter_lds_bytes
+constexpr size_t kScatterStaticLds = (size_t)kScatterThreads * 4;
+// bins the staged scatter holds with chunks of `chunk` pairs (LDS of one CU):
+// 1,791 with 16,384-pair chunks, 5,887 with 8,192
 inline int scatter_max_bins(int chunk) {
-    return (int)((kLdsPerCU - 8 - (size_t)chunk * 8) / 16);
+    return (int)((kLdsPerCU - kScatterStaticLds - 8 - (size_t)chunk * 8) / 16);
 }
 
 struct PlanOut {

@@ -59,6 +59,17 @@ def test_longest_lengths_and_largest_thresholds(sj, config):
     _check(sj, p, 1024, config=config)
 
 
+@pytest.mark.parametrize("max_len", [216, 220, 728, 732])
+def test_bin_counts_at_the_staged_scatter_limits(sj, max_len):
+    # bin width 4: (ceil(max_len/4) + 1) * 32 bins = 1,760 / 1,792 / 5,856 /
+    # 5,888, on both sides of what the staged scatter holds beside its scan's
+    # static LDS with chunks of 16,384 pairs (1,791 bins) and of 8,192 (5,887)
+    p = syninput.generate(4_000, max_len - 60, max_len, E=None, r_max=min(0.10, 31.0 / max_len),
+                          seed=3200 + max_len)
+    assert p.E.max() <= 31
+    _check(sj, p, max_len, config=(4, 2))
+
+
 @pytest.mark.parametrize("config", [(4, 2), (8, 4), (16, 1), (32, 4)])
 def test_every_config_exact(sj, config):
     p = syninput.generate(20_000, 30, 200, E=None, r_max=0.15, seed=31)
