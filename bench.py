@@ -555,8 +555,8 @@ def bench_window(reads, refs, lens, pairs, E, widths=(1, 2, 3, 4, 5, 6, 8, 12, 1
     """Window width against accuracy (Suppl. Sec. 6.1, Fig. 4) on the headline batch:
     per width W the false accept rate (dissimilar pairs accepted, over all dissimilar
     pairs) and the false rejects (pairs within E rejected), labels from the GPU
-    verifier's banded edit distance of every pair; with the time of the one-pair-per-lane
-    window kernel.  A sample is checked against the oracle's window-width filter."""
+    verifier's banded edit distance of every pair; with the time of the bit-sliced
+    window-width kernel.  A sample is checked against the oracle's window-width filter."""
     import numpy as np
     import torch
     import paper_1809_07858_amd as sj

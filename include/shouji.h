@@ -243,8 +243,10 @@ int shouji_filter_batched_noalloc(const uint32_t *reads, const uint32_t *refs, c
  * the winner (most zeros, then a leading zero, then the order of
  * shouji_filter) is copied into S[i..i+W-1] when it has strictly more zeros,
  * and accept = ones(S[0..m)) <= E.  With W = 4 the results equal
- * shouji_filter's.  A study variant (one pair per lane), far slower than the
- * W = 4 kernel.
+ * shouji_filter's.  Bit-sliced (32 pairs per register, 2048 pairs per
+ * wavefront, every lane its own pairs); the LDS per wavefront grows with W
+ * and E (pattern and text rings), so it runs fewer wavefronts per CU than
+ * shouji_filter.
  *
  *   W             1..SHOUJI_MAX_WINDOW, else SHOUJI_ERR_RANGE.
  *   other arguments, sentinels and errors as for shouji_filter.

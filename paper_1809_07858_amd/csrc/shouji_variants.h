@@ -1,13 +1,13 @@
-// Parameters of the one-pair-per-lane variant kernels (window width,
-// MAGNET).  Kept apart from shouji_internal.h, which the bit-sliced kernels
-// include.
+// Parameters of the variant kernels (window width, MAGNET).  Kept apart
+// from shouji_internal.h, which the plain, batched and two-length kernels
+// share.
 #pragma once
 
 #include <stdint.h>
 
 namespace shouji {
 
-// Window-width variant (one pair per lane).
+// Window-width variant (bit-sliced, 2048 pairs per wavefront).
 struct WindowParams {
     const uint32_t *reads;
     const uint32_t *refs;
