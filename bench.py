@@ -34,6 +34,7 @@ METRIC = "filtered pairs/sec at m=100,E=5 (1 GPU) vs plain; serving p50/p99 late
 VALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_1809_07858_amd/csrc/shouji_plain.hip",
+                  "paper_1809_07858_amd/csrc/shouji_bitslice.h",
                   "paper_1809_07858_amd/csrc/shouji_internal.h"]
 
 

@@ -70,31 +70,55 @@ __device__ __forceinline__ void csa(uint32_t &h, uint32_t &l, uint32_t a, uint32
 }
 
 // Ones of the N planes x[0..N-1] (N <= 16) as bit planes o[0..4] of the
-// count: a carry-save adder tree over 16 inputs, the missing ones zero (the
-// compiler folds the gates they reach).
+// count: column by column (weights 1, 2, 4, ...), three planes of a column
+// are replaced by their sum while at least three remain, a last pair by a
+// half adder, the carries going to the next column.  The plane counts are
+// compile-time constants once the loops are unrolled.
 template <int N>
 __device__ __forceinline__ void count_planes(const uint32_t *x, uint32_t (&o)[5]) {
     static_assert(N >= 0 && N <= 16, "at most 16 planes");
-    uint32_t v[16];
+    uint32_t col[5][16];
+    int cnt[5] = {N, 0, 0, 0, 0};
 #pragma unroll
-    for (int i = 0; i < 16; i++) v[i] = i < N ? x[i] : 0u;
-    uint32_t ones = 0u, twos = 0u, fours = 0u, eights = 0u, sixteens, ta, tb, fa, fb, ea, eb;
-    csa(ta, ones, ones, v[0], v[1]);
-    csa(tb, ones, ones, v[2], v[3]);
-    csa(fa, twos, twos, ta, tb);
-    csa(ta, ones, ones, v[4], v[5]);
-    csa(tb, ones, ones, v[6], v[7]);
-    csa(fb, twos, twos, ta, tb);
-    csa(ea, fours, fours, fa, fb);
-    csa(ta, ones, ones, v[8], v[9]);
-    csa(tb, ones, ones, v[10], v[11]);
-    csa(fa, twos, twos, ta, tb);
-    csa(ta, ones, ones, v[12], v[13]);
-    csa(tb, ones, ones, v[14], v[15]);
-    csa(fb, twos, twos, ta, tb);
-    csa(eb, fours, fours, fa, fb);
-    csa(sixteens, eights, eights, ea, eb);
-    o[0] = ones; o[1] = twos; o[2] = fours; o[3] = eights; o[4] = sixteens;
+    for (int i = 0; i < N; i++) col[0][i] = x[i];
+#pragma unroll
+    for (int w = 0; w < 5; w++) {
+#pragma unroll
+        for (int it = 0; it < 8; it++) {
+            if (cnt[w] >= 3) {
+                uint32_t h, l;
+                csa(h, l, col[w][cnt[w] - 3], col[w][cnt[w] - 2], col[w][cnt[w] - 1]);
+                col[w][cnt[w] - 3] = l;
+                cnt[w] -= 2;
+                if (w + 1 < 5) col[w + 1 < 5 ? w + 1 : 0][cnt[w + 1 < 5 ? w + 1 : 0]++] = h;
+            }
+        }
+        if (cnt[w] == 2) {
+            const uint32_t a = col[w][0], b = col[w][1];
+            col[w][0] = a ^ b;
+            cnt[w] = 1;
+            if (w + 1 < 5) col[w + 1 < 5 ? w + 1 : 0][cnt[w + 1 < 5 ? w + 1 : 0]++] = a & b;
+        }
+        o[w] = cnt[w] ? col[w][0] : 0u;
+    }
+}
+
+// core + a + b + c as bit planes out[0..4]: the three planes by one full
+// adder into a 2-bit sum, then a ripple add into the core count's planes.
+__device__ __forceinline__ void add_three(const uint32_t (&core)[5], uint32_t a, uint32_t b, uint32_t c,
+                                          uint32_t (&out)[5]) {
+    uint32_t s1, s0;
+    csa(s1, s0, a, b, c);
+    out[0] = core[0] ^ s0;
+    uint32_t cy = core[0] & s0;
+    uint32_t h;
+    csa(h, out[1], core[1], s1, cy);
+    cy = h;
+#pragma unroll
+    for (int k = 2; k < 5; k++) {
+        out[k] = core[k] ^ cy;
+        cy = core[k] & cy;
+    }
 }
 
 // C consecutive ring slots from slot s (wave-uniform) of a ring of R slots.
@@ -228,10 +252,8 @@ __global__ __launch_bounds__(kWinLanes, 1) void window_bs_kernel(WindowParams pr
         uint32_t wc[NB][KB], wz[NB][W];
         const bool any_mask = i0 < Ew || near_end;
         // one candidate diagonal d whose pattern position i0-d sits at slot ps
-        auto candidate = [&](auto first_tag, int d, int ps) {
+        auto candidate = [&](auto first_tag, int d, const uint2 (&pv)[C]) {
             constexpr bool FIRST = decltype(first_tag)::value;
-            uint2 pv[C];
-            win_ring_read<C>(pring, Rp, ps, lane, pv);
             uint32_t c[C];
 #pragma unroll
             for (int t = 0; t < C; t++) c[t] = (pv[t].x ^ tl[t]) | (pv[t].y ^ th[t]);   // Eq. 1
@@ -256,10 +278,24 @@ __global__ __launch_bounds__(kWinLanes, 1) void window_bs_kernel(WindowParams pr
                         if (i0 + t - d < 0) c[t] = ~0u;
                 }
             }
+            // the NB windows share cells NB-1 .. W-1: their ones are counted
+            // once, each window then adds its NB-1 other cells
+            constexpr bool kShared = W >= 6;
+            static_assert(NB == 4, "each window has three cells outside the shared part");
+            uint32_t core[5];
+            if constexpr (kShared) count_planes<kShared ? W - (NB - 1) : 0>(c + (NB - 1), core);
 #pragma unroll
             for (int w = 0; w < NB; w++) {
                 uint32_t k[5];
-                count_planes<W>(c + w, k);
+                if constexpr (kShared) {
+                    // cells w .. NB-2 before the shared part, W .. W+w-1 after it
+                    uint32_t e[NB - 1];
+#pragma unroll
+                    for (int j = 0; j < NB - 1; j++) e[j] = j < NB - 1 - w ? c[w + j] : c[W + j - (NB - 1 - w)];
+                    add_three(core, e[0], e[1], e[2], k);
+                } else {
+                    count_planes<W>(c + w, k);
+                }
                 if constexpr (FIRST) {
 #pragma unroll
                     for (int b = 0; b < KB; b++) wc[w][b] = k[b];
@@ -282,20 +318,29 @@ __global__ __launch_bounds__(kWinLanes, 1) void window_bs_kernel(WindowParams pr
         };
         using First = std::integral_constant<bool, true>;
         using Later = std::integral_constant<bool, false>;
+        // pattern planes of a candidate: C ring slots from slot ps
+        uint2 pv[C];
+        auto rd = [&](int ps) { win_ring_read<C>(pring, Rp, ps, lane, pv); };
         if (Ew == 0) {
-            candidate(First{}, 0, sb);
+            rd(sb);
+            candidate(First{}, 0, pv);
         } else {
             int sP = sb == 0 ? Rp - 1 : sb - 1;     // slot of position i0 - k
             int sN = sb + 1 == Rp ? 0 : sb + 1;     // slot of position i0 + k
-            candidate(First{}, 1, sP);
-            candidate(Later{}, -1, sN);
+            rd(sP);
+            candidate(First{}, 1, pv);
+            rd(sN);
+            candidate(Later{}, -1, pv);
             for (int k = 2; k <= Ew; k++) {
                 sP = sP == 0 ? Rp - 1 : sP - 1;
                 sN = sN + 1 == Rp ? 0 : sN + 1;
-                candidate(Later{}, k, sP);
-                candidate(Later{}, -k, sN);
+                rd(sP);
+                candidate(Later{}, k, pv);
+                rd(sN);
+                candidate(Later{}, -k, pv);
             }
-            candidate(Later{}, 0, sb);
+            rd(sb);
+            candidate(Later{}, 0, pv);
         }
 
         // ---- the bit-vector update, window by window
