@@ -26,9 +26,9 @@
 //  * windows are processed in blocks of 8.  For each candidate diagonal (in
 //    Algorithm 1's order d = +1, -1, ..., +E, -E, main) the 11 cells of
 //    the block's columns are built (XOR of code planes, OR of the two bits:
-//    Eq. 1), counted with 2-bit pair sums, and each window's segment is
-//    compared with the running winner by the key (ones, first bit) -- fewer
-//    ones first, then a leading zero -- keeping the earliest on full ties;
+//    Eq. 1), and each window's segment is compared with the running winner
+//    by the key (ones, first bit) -- fewer ones first, then a leading zero --
+//    kept as a 3-bit rank, keeping the earliest on full ties;
 //  * then the Shouji bit-vector update runs as a bit-sliced 8-state machine
 //    whose state is S[i..i+2] (S[i+3] is still 1 when window i runs): write iff
 //    ones(Z) <= ones(S[i..i+2]), which is "more zeros" for the 4-bit window.
@@ -54,13 +54,29 @@
 
 namespace shouji {
 
+// A window's key -- ones of its 4-bit segment (0..4), then its first bit --
+// takes 8 values, so it is kept as a 3-bit rank R2 R1 R0 in key order:
+// (0,0) (1,0) (1,1) (2,0) (2,1) (3,0) (3,1) (4,1) -> 0..7.  With c0 the first
+// cell and o' the ones of the other three: rank bit 2 = c0 ? o' >= 1 : o' == 3,
+// bit 0 = c0 ? o' == 3 : o' >= 1, bit 1 = c0 ? o' != 1 : o' == 2; the first
+// bit is 1 for ranks 2, 4, 6, 7, and ones <= q iff rank <= 2q.
+constexpr unsigned kTTOrIfAndElse = truth_table([](int a, int b, int c) { return a ? (b | c) : (b & c); });
+constexpr unsigned kTTAndIfOrElse = truth_table([](int a, int b, int c) { return a ? (b & c) : (b | c); });
+constexpr unsigned kTTOrIfXorElse = truth_table([](int a, int b, int c) { return a ? (b | c) : (b ^ c); });
+constexpr unsigned kTTXnorIfAndElse = truth_table([](int a, int b, int c) { return a ? (b == c) : (b & c); });
+constexpr unsigned kTTRankFirst = truth_table([](int a, int b, int c) {
+    const int r = a << 2 | b << 1 | c;
+    return r == 2 || r == 4 || r == 6 || r == 7;
+});
+constexpr unsigned kTTOr = truth_table([](int a, int b, int) { return a | b; });
+
 // Running winner of the window search for the NB windows of a block (8, or
-// 4 in a short last iteration), one register per plane and window: key
-// planes (ones = K3 K2 K1, first bit K0) and the segment's remaining bits
-// Z1..Z3 (Z0 == K0).
+// 4 in a short last iteration), one register per plane and window: the key's
+// rank planes R2 R1 R0 and the segment's bits Z1..Z3 (Z0 follows from the
+// rank).
 template <int NB>
 struct Winner {
-    uint32_t K0[NB], K1[NB], K2[NB], K3[NB];
+    uint32_t R0[NB], R1[NB], R2[NB];
     uint32_t Z1[NB], Z2[NB], Z3[NB];
 };
 
@@ -123,37 +139,27 @@ __device__ __forceinline__ void candidate(Winner<NB> &W, const uint2 (&pv)[NB + 
             }
         }
     }
-    // 2-bit sums of neighbouring cells: x = exactly one is 1, a = both are 1
-    uint32_t x[C - 1], a[C - 1];
-#pragma unroll
-    for (int t = 0; t < C - 1; t++) {
-        x[t] = cell[t] ^ cell[t + 1];
-        a[t] = cell[t] & cell[t + 1];
-    }
 #pragma unroll
     for (int w = 0; w < NB; w++) {
-        // ones of cells w..w+3 = pair sum (w) + pair sum (w+2): 3-bit r2 r1 r0
-        const uint32_t r0 = x[w] ^ x[w + 2];
-        const uint32_t u = x[w] & x[w + 2];
-        const uint32_t r1 = gate<kTTXor3>(a[w], a[w + 2], u);
-        const uint32_t r2 = a[w] & a[w + 2];
-        const uint32_t k0 = cell[w];
+        // rank of the key of cells w..w+3 (7 gates)
+        const uint32_t c0 = cell[w], c1 = cell[w + 1], c2 = cell[w + 2], c3 = cell[w + 3];
+        const uint32_t r2 = gate<kTTOrIfAndElse>(c0, c1, gate<kTTOrIfAndElse>(c0, c2, c3));
+        const uint32_t r0 = gate<kTTAndIfOrElse>(c0, c1, gate<kTTAndIfOrElse>(c0, c2, c3));
+        const uint32_t r1 = mux(c1, gate<kTTOrIfXorElse>(c0, c2, c3), gate<kTTXnorIfAndElse>(c0, c2, c3));
         if (FIRST) {
-            W.K0[w] = k0; W.K1[w] = r0; W.K2[w] = r1; W.K3[w] = r2;
-            W.Z1[w] = cell[w + 1]; W.Z2[w] = cell[w + 2]; W.Z3[w] = cell[w + 3];
+            W.R0[w] = r0; W.R1[w] = r1; W.R2[w] = r2;
+            W.Z1[w] = c1; W.Z2[w] = c2; W.Z3[w] = c3;
         } else {
-            // lt = (r2 r1 r0 k0) < (K3 K2 K1 K0): borrow chain from the low bit
-            const uint32_t b0 = gate<kTTAndNotA>(k0, W.K0[w], W.K0[w]);
-            const uint32_t b1 = gate<kTTMajNotA>(r0, W.K1[w], b0);
-            const uint32_t b2 = gate<kTTMajNotA>(r1, W.K2[w], b1);
-            const uint32_t lt = gate<kTTMajNotA>(r2, W.K3[w], b2);
-            W.K0[w] = mux(lt, k0, W.K0[w]);
-            W.K1[w] = mux(lt, r0, W.K1[w]);
-            W.K2[w] = mux(lt, r1, W.K2[w]);
-            W.K3[w] = mux(lt, r2, W.K3[w]);
-            W.Z1[w] = mux(lt, cell[w + 1], W.Z1[w]);
-            W.Z2[w] = mux(lt, cell[w + 2], W.Z2[w]);
-            W.Z3[w] = mux(lt, cell[w + 3], W.Z3[w]);
+            // lt = (r2 r1 r0) < (R2 R1 R0): borrow chain from the low bit
+            const uint32_t b0 = gate<kTTAndNotA>(r0, W.R0[w], W.R0[w]);
+            const uint32_t b1 = gate<kTTMajNotA>(r1, W.R1[w], b0);
+            const uint32_t lt = gate<kTTMajNotA>(r2, W.R2[w], b1);
+            W.R0[w] = mux(lt, r0, W.R0[w]);
+            W.R1[w] = mux(lt, r1, W.R1[w]);
+            W.R2[w] = mux(lt, r2, W.R2[w]);
+            W.Z1[w] = mux(lt, c1, W.Z1[w]);
+            W.Z2[w] = mux(lt, c2, W.Z2[w]);
+            W.Z3[w] = mux(lt, c3, W.Z3[w]);
         }
     }
 }
@@ -291,15 +297,15 @@ __device__ __forceinline__ void block_fsm(FsmState &F, const Winner<NB> &W, uint
     for (int w = 0; w < NB; w++) {
         const uint32_t q0 = gate<kTTXor3>(F.s0, F.s1, F.s2);  // ones(S[i..i+2]) = q1 q0
         const uint32_t q1 = gate<kTTMaj>(F.s0, F.s1, F.s2);
-        // c1 = (q1 q0) < (K2 K1)
-        const uint32_t c0 = gate<kTTAndNotA>(q0, W.K1[w], W.K1[w]);
-        const uint32_t c1 = gate<kTTMajNotA>(q1, W.K2[w], c0);
-        // write iff ones(Z) <= ones(S[i..i+2]):  K3 == 0 and not c1
-        const uint32_t wr = gate<kTTNor>(W.K3[w], c1, c1);
-        o[w] = mux(wr, W.K0[w], F.s0);
-        const uint32_t n1 = mux(wr, W.Z1[w], F.s1);
-        const uint32_t n2 = mux(wr, W.Z2[w], F.s2);
-        const uint32_t n3 = gate<kTTOrNotA>(wr, W.Z3[w], W.Z3[w]);
+        // write iff ones(Z) <= ones(S[i..i+2]) iff rank <= (q1 q0 0):
+        // keep = (q1 q0 0) < (R2 R1 R0), a borrow chain whose low step is R0
+        const uint32_t b1 = gate<kTTMajNotA>(q0, W.R1[w], W.R0[w]);
+        const uint32_t keep = gate<kTTMajNotA>(q1, W.R2[w], b1);
+        const uint32_t z0 = gate<kTTRankFirst>(W.R2[w], W.R1[w], W.R0[w]);
+        o[w] = mux(keep, F.s0, z0);
+        const uint32_t n1 = mux(keep, F.s1, W.Z1[w]);
+        const uint32_t n2 = mux(keep, F.s2, W.Z2[w]);
+        const uint32_t n3 = gate<kTTOr>(keep, W.Z3[w], W.Z3[w]);
         F.s0 = n1; F.s1 = n2; F.s2 = n3;
     }
 }
