@@ -59,7 +59,8 @@ namespace shouji {
 // (0,0) (1,0) (1,1) (2,0) (2,1) (3,0) (3,1) (4,1) -> 0..7.  With c0 the first
 // cell and o' the ones of the other three: rank bit 2 = c0 ? o' >= 1 : o' == 3,
 // bit 0 = c0 ? o' == 3 : o' >= 1, bit 1 = c0 ? o' != 1 : o' == 2; the first
-// bit is 1 for ranks 2, 4, 6, 7, and ones <= q iff rank <= 2q.
+// bit is 1 for ranks 2, 4, 6, 7, o' is odd for ranks 1, 4, 5, 7 (so the third
+// bit after the first is o' ^ Z1 ^ Z2), and ones <= q iff rank <= 2q.
 constexpr unsigned kTTOrIfAndElse = truth_table([](int a, int b, int c) { return a ? (b | c) : (b & c); });
 constexpr unsigned kTTAndIfOrElse = truth_table([](int a, int b, int c) { return a ? (b & c) : (b | c); });
 constexpr unsigned kTTOrIfXorElse = truth_table([](int a, int b, int c) { return a ? (b | c) : (b ^ c); });
@@ -68,16 +69,20 @@ constexpr unsigned kTTRankFirst = truth_table([](int a, int b, int c) {
     const int r = a << 2 | b << 1 | c;
     return r == 2 || r == 4 || r == 6 || r == 7;
 });
+constexpr unsigned kTTRankOddRest = truth_table([](int a, int b, int c) {
+    const int r = a << 2 | b << 1 | c;
+    return r == 1 || r == 4 || r == 5 || r == 7;
+});
 constexpr unsigned kTTOr = truth_table([](int a, int b, int) { return a | b; });
 
 // Running winner of the window search for the NB windows of a block (8, or
 // 4 in a short last iteration), one register per plane and window: the key's
-// rank planes R2 R1 R0 and the segment's bits Z1..Z3 (Z0 follows from the
-// rank).
+// rank planes R2 R1 R0 and the segment's bits Z1, Z2 (Z0 and Z3 follow from
+// the rank and them).
 template <int NB>
 struct Winner {
     uint32_t R0[NB], R1[NB], R2[NB];
-    uint32_t Z1[NB], Z2[NB], Z3[NB];
+    uint32_t Z1[NB], Z2[NB];
 };
 
 // One candidate diagonal d over one block of NB windows: build NB+3 cells,
@@ -148,7 +153,7 @@ __device__ __forceinline__ void candidate(Winner<NB> &W, const uint2 (&pv)[NB + 
         const uint32_t r1 = mux(c1, gate<kTTOrIfXorElse>(c0, c2, c3), gate<kTTXnorIfAndElse>(c0, c2, c3));
         if (FIRST) {
             W.R0[w] = r0; W.R1[w] = r1; W.R2[w] = r2;
-            W.Z1[w] = c1; W.Z2[w] = c2; W.Z3[w] = c3;
+            W.Z1[w] = c1; W.Z2[w] = c2;
         } else {
             // lt = (r2 r1 r0) < (R2 R1 R0): borrow chain from the low bit
             const uint32_t b0 = gate<kTTAndNotA>(r0, W.R0[w], W.R0[w]);
@@ -159,7 +164,6 @@ __device__ __forceinline__ void candidate(Winner<NB> &W, const uint2 (&pv)[NB + 
             W.R2[w] = mux(lt, r2, W.R2[w]);
             W.Z1[w] = mux(lt, c1, W.Z1[w]);
             W.Z2[w] = mux(lt, c2, W.Z2[w]);
-            W.Z3[w] = mux(lt, c3, W.Z3[w]);
         }
     }
 }
@@ -302,10 +306,11 @@ __device__ __forceinline__ void block_fsm(FsmState &F, const Winner<NB> &W, uint
         const uint32_t b1 = gate<kTTMajNotA>(q0, W.R1[w], W.R0[w]);
         const uint32_t keep = gate<kTTMajNotA>(q1, W.R2[w], b1);
         const uint32_t z0 = gate<kTTRankFirst>(W.R2[w], W.R1[w], W.R0[w]);
+        const uint32_t z3 = gate<kTTXor3>(gate<kTTRankOddRest>(W.R2[w], W.R1[w], W.R0[w]), W.Z1[w], W.Z2[w]);
         o[w] = mux(keep, F.s0, z0);
         const uint32_t n1 = mux(keep, F.s1, W.Z1[w]);
         const uint32_t n2 = mux(keep, F.s2, W.Z2[w]);
-        const uint32_t n3 = gate<kTTOr>(keep, W.Z3[w], W.Z3[w]);
+        const uint32_t n3 = gate<kTTOr>(keep, z3, z3);
         F.s0 = n1; F.s1 = n2; F.s2 = n3;
     }
 }
