@@ -43,14 +43,15 @@ def algorithmic_lane_ops_per_pair(m, E):
     op evaluates a gate for 32 pairs).
 
     Per window and candidate diagonal: 2 ops to build a cell (Eq. 1: XOR of
-    code planes, OR of the two bits), 6 to count the segment's ones (2-bit
-    pair sums shared by two windows + one 2-bit add); per window and each of
-    the 2E candidates after the first: 4 ops to compare keys and 7 to keep the
-    winner; per window: 9 ops for the bit-vector update and 3.25 for the
+    code planes, OR of the two bits) and 7 for the 3-bit rank of the
+    segment's key (ones, first bit); per window and each of the 2E
+    candidates after the first: 3 ops to compare ranks and 5 to keep the
+    winner (rank and two segment bits); per window: 11 ops for the bit-vector
+    update (the other two segment bits follow from the rank) and 3.25 for the
     carry-save count of its final bit.  Unpack: two sequences of ceil(m/16)
     16-base words, each a 32x32 bit transpose of 256 ops per 32 pairs.
     """
-    per32 = m * (2 * E + 1) * 8 + m * (2 * E) * 11 + m * 12.25
+    per32 = m * (2 * E + 1) * 9 + m * (2 * E) * 8 + m * 14.25
     unpack = 2 * ((m + 15) // 16) * 256
     return (per32 + unpack) / 32.0
 

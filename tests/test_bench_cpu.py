@@ -14,16 +14,16 @@ import bench  # noqa: E402
 
 
 def test_gate_count_model():
-    # m=100, E=5: 100*11*8 + 100*10*11 + 100*12.25 = 20,025 gates per 32
+    # m=100, E=5: 100*11*9 + 100*10*8 + 100*14.25 = 19,325 gates per 32
     # pairs, plus two sequences of 7 words at 256 ops per 32 pairs
-    assert bench.algorithmic_lane_ops_per_pair(100, 5) == pytest.approx((8800 + 11000 + 1225 + 2 * 7 * 256) / 32)
-    assert bench.algorithmic_lane_ops_per_pair(100, 5) == pytest.approx(769.03125)
+    assert bench.algorithmic_lane_ops_per_pair(100, 5) == pytest.approx((9900 + 8000 + 1425 + 2 * 7 * 256) / 32)
+    assert bench.algorithmic_lane_ops_per_pair(100, 5) == pytest.approx(715.90625)
     # E=0: one candidate, no comparisons
-    assert bench.algorithmic_lane_ops_per_pair(100, 0) == pytest.approx((800 + 1225 + 3584) / 32)
-    # grows linearly in E
+    assert bench.algorithmic_lane_ops_per_pair(100, 0) == pytest.approx((900 + 1425 + 3584) / 32)
+    # grows linearly in E: two more candidates per window, each 9 + 8 gates
     d1 = bench.algorithmic_lane_ops_per_pair(250, 11) - bench.algorithmic_lane_ops_per_pair(250, 10)
     d2 = bench.algorithmic_lane_ops_per_pair(250, 21) - bench.algorithmic_lane_ops_per_pair(250, 20)
-    assert d1 == pytest.approx(d2) == pytest.approx(250 * (16 + 22) / 32)
+    assert d1 == pytest.approx(d2) == pytest.approx(250 * (18 + 16) / 32)
 
 
 def test_bytes_and_peak():
