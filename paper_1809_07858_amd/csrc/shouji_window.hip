@@ -34,6 +34,7 @@
 #include <stdint.h>
 
 #include <mutex>
+#include <type_traits>
 
 #include "../../include/shouji.h"
 #include "shouji_bitslice.h"
@@ -251,7 +252,8 @@ __global__ __launch_bounds__(kWinLanes, 1) void window_bs_kernel(WindowParams pr
         // running winner of each window: count planes and the segment
         uint32_t wc[NB][KB], wz[NB][W];
         const bool any_mask = i0 < Ew || near_end;
-        // one candidate diagonal d whose pattern position i0-d sits at slot ps
+        // one candidate diagonal d, with pv the pattern planes of positions
+        // i0-d .. i0-d+C-1
         auto candidate = [&](auto first_tag, int d, const uint2 (&pv)[C]) {
             constexpr bool FIRST = decltype(first_tag)::value;
             uint32_t c[C];
