@@ -57,8 +57,13 @@ __host__ __device__ constexpr int win_pattern_slots(int W, int Ee) { return win_
 __host__ __device__ constexpr int win_text_slots(int W) {
     return win_cols(W) + kHalf - 1 < 2 * kHalf ? win_cols(W) + kHalf - 1 : 2 * kHalf;
 }
+// The pattern ring's first C-1 slots are also kept past its end (a mirror),
+// so that a candidate's C slots are one run from any start, where the mirror
+// leaves four wavefronts per CU at E = 5 (W <= 10); wider windows read a
+// wrapping run in two parts.
+__host__ __device__ constexpr int win_mirror_slots(int W) { return W <= 10 ? win_cols(W) - 1 : 0; }
 inline size_t win_lds_bytes(int W, int Ee) {
-    return (size_t)(win_pattern_slots(W, Ee) + win_text_slots(W)) * kWinLanes * 8;
+    return (size_t)(win_pattern_slots(W, Ee) + win_mirror_slots(W) + win_text_slots(W)) * kWinLanes * 8;
 }
 // bits of a count 0..v
 __host__ __device__ constexpr int count_bits(int v) { return v <= 1 ? 1 : 1 + count_bits(v >> 1); }
@@ -147,8 +152,9 @@ __global__ __launch_bounds__(kWinLanes, 1) void window_bs_kernel(WindowParams pr
     const int lane = threadIdx.x;
     const int Ee = prm.Ee;
     const int Rp = win_pattern_slots(W, Ee), Rt = win_text_slots(W);
+    constexpr int MIR = win_mirror_slots(W);
     uint2 *pring = reinterpret_cast<uint2 *>(lds_win);
-    uint2 *tring = pring + Rp * kWinLanes;
+    uint2 *tring = pring + (Rp + MIR) * kWinLanes;
     static_assert(win_cols(W) <= 20, "a block's text columns span at most two words");
 
     const int64_t base = (int64_t)blockIdx.x * kWinPairsPerWave;
@@ -221,7 +227,9 @@ __global__ __launch_bounds__(kWinLanes, 1) void window_bs_kernel(WindowParams pr
         transpose32(raw);                      // raw[2u], raw[2u+1]: code bits of position 16pw+u
 #pragma unroll
         for (int u = 0; u < kHalf; u++) {
-            ring[slot * kWinLanes + lane] = make_uint2(raw[2 * u], raw[2 * u + 1]);
+            const uint2 v = make_uint2(raw[2 * u], raw[2 * u + 1]);
+            ring[slot * kWinLanes + lane] = v;
+            if (MIR > 0 && pk == 0 && slot < MIR) ring[(slot + R) * kWinLanes + lane] = v;
             slot = slot + 1 == R ? 0 : slot + 1;
         }
     };
@@ -322,7 +330,15 @@ __global__ __launch_bounds__(kWinLanes, 1) void window_bs_kernel(WindowParams pr
         using Later = std::integral_constant<bool, false>;
         // pattern planes of a candidate: C ring slots from slot ps
         uint2 pv[C];
-        auto rd = [&](int ps) { win_ring_read<C>(pring, Rp, ps, lane, pv); };
+        auto rd = [&](int ps) {
+            if constexpr (MIR > 0) {
+                const uint2 *p = pring + ps * kWinLanes + lane;
+#pragma unroll
+                for (int t = 0; t < C; t++) pv[t] = p[t * kWinLanes];
+            } else {
+                win_ring_read<C>(pring, Rp, ps, lane, pv);
+            }
+        };
         if (Ew == 0) {
             rd(sb);
             candidate(First{}, 0, pv);
