@@ -59,8 +59,8 @@ namespace shouji {
 // (0,0) (1,0) (1,1) (2,0) (2,1) (3,0) (3,1) (4,1) -> 0..7.  With c0 the first
 // cell and o' the ones of the other three: rank bit 2 = c0 ? o' >= 1 : o' == 3,
 // bit 0 = c0 ? o' == 3 : o' >= 1, bit 1 = c0 ? o' != 1 : o' == 2; the first
-// bit is 1 for ranks 2, 4, 6, 7, o' is odd for ranks 1, 4, 5, 7 (so the third
-// bit after the first is o' ^ Z1 ^ Z2), and ones <= q iff rank <= 2q.
+// bit is 1 for ranks 2, 4, 6, 7, o' is odd for ranks 1, 4, 5, 7 (so the last
+// bit is Z3 = (o' mod 2) ^ Z1 ^ Z2), and ones <= q iff rank <= 2q.
 constexpr unsigned kTTOrIfAndElse = truth_table([](int a, int b, int c) { return a ? (b | c) : (b & c); });
 constexpr unsigned kTTAndIfOrElse = truth_table([](int a, int b, int c) { return a ? (b & c) : (b | c); });
 constexpr unsigned kTTOrIfXorElse = truth_table([](int a, int b, int c) { return a ? (b | c) : (b ^ c); });
@@ -86,7 +86,7 @@ struct Winner {
 };
 
 // One candidate diagonal d over one block of NB windows: build NB+3 cells,
-// count each window's segment, and fold it into the running winner.  `rp`
+// rank each window's key, and fold it into the running winner.  `rp`
 // points at this lane's ring entry for pattern position i0 - d; consecutive
 // positions are kRingStride entries apart (all entries are loaded before the
 // first use).  `masked` (uniform): some cell may lie outside the map.  With
