@@ -75,6 +75,32 @@ constexpr unsigned kTTRankOddRest = truth_table([](int a, int b, int c) {
 });
 constexpr unsigned kTTOr = truth_table([](int a, int b, int) { return a | b; });
 
+// The rank gates, checked on every 4-cell segment at compile time: the rank
+// orders the keys (fewer ones first, then a leading zero), the first bit and
+// the last bit follow from it (the latter with the two middle bits), and
+// "ones <= q iff rank <= 2q" holds for every state count q in 0..3.
+constexpr int tt_eval(unsigned tt, int a, int b, int c) { return (int)((tt >> (a << 2 | b << 1 | c)) & 1u); }
+constexpr int rank_of(int c0, int c1, int c2, int c3) {
+    const int r2 = tt_eval(kTTOrIfAndElse, c0, c1, tt_eval(kTTOrIfAndElse, c0, c2, c3));
+    const int r0 = tt_eval(kTTAndIfOrElse, c0, c1, tt_eval(kTTAndIfOrElse, c0, c2, c3));
+    const int r1 = c1 ? tt_eval(kTTOrIfXorElse, c0, c2, c3) : tt_eval(kTTXnorIfAndElse, c0, c2, c3);
+    return r2 << 2 | r1 << 1 | r0;
+}
+constexpr bool rank_gates_hold() {
+    for (int x = 0; x < 16; x++) {
+        const int c0 = x & 1, c1 = (x >> 1) & 1, c2 = (x >> 2) & 1, c3 = (x >> 3) & 1;
+        const int ones = c0 + c1 + c2 + c3;
+        const int r = rank_of(c0, c1, c2, c3);
+        if (r != (ones == 0 ? 0 : 2 * ones - 1 + c0 - (ones == 4 ? 1 : 0))) return false;
+        if (tt_eval(kTTRankFirst, r >> 2, (r >> 1) & 1, r & 1) != c0) return false;
+        if ((tt_eval(kTTRankOddRest, r >> 2, (r >> 1) & 1, r & 1) ^ c1 ^ c2) != c3) return false;
+        for (int q = 0; q < 4; q++)
+            if ((ones <= q) != (r <= 2 * q)) return false;
+    }
+    return true;
+}
+static_assert(rank_gates_hold(), "rank gates disagree with the key order");
+
 // Running winner of the window search for the NB windows of a block (8, or
 // 4 in a short last iteration), one register per plane and window: the key's
 // rank planes R2 R1 R0 and the segment's bits Z1, Z2 (Z0 and Z3 follow from
