@@ -466,20 +466,25 @@ extern "C" int shouji_tune_batched(const uint32_t *reads, const uint32_t *refs, 
             rc = shouji_filter_batched(reads, refs, lengths, E_per_pair, out_accept, out_popcount,
                                        n_pairs, max_len, ld, workspace, workspace_bytes, &c, stream);
             if (rc) break;
-            hipEventRecord(a, st);
+            if (hipEventRecord(a, st) != hipSuccess) { rc = fail(SHOUJI_ERR_DEVICE, "tuning event failed"); break; }
             for (int r = 0; r < 3 && rc == SHOUJI_OK; r++)
                 rc = shouji_filter_batched(reads, refs, lengths, E_per_pair, out_accept, out_popcount,
                                            n_pairs, max_len, ld, workspace, workspace_bytes, &c, stream);
-            hipEventRecord(b, st);
-            if (hipEventSynchronize(b) != hipSuccess) { rc = fail(SHOUJI_ERR_DEVICE, "tuning run failed"); break; }
+            if (rc) break;
             float ms = 0.f;
-            hipEventElapsedTime(&ms, a, b);
+            if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+                rc = fail(SHOUJI_ERR_DEVICE, "tuning run failed");
+                break;
+            }
             ms /= 3.f;
             if (ms < top_ms) { top_ms = ms; top = c; }
         }
     }
-    hipEventDestroy(a);
-    hipEventDestroy(b);
+    // the events are released whatever the tuning runs returned; a failure
+    // to release them does not change the tuned configuration
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
     if (rc) return rc;
     {
         std::lock_guard<std::mutex> g(g_tune_mu);

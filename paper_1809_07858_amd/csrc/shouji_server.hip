@@ -138,26 +138,29 @@ int64_t slot_device_bytes(int64_t B, int nw, int max_len) {
     return 3 * B * nw * 4 + B * (8 + 4 + 4 + 1 + 2) + (B + 1) * 4 + shouji_batched_workspace_bytes(B, max_len);
 }
 
+// Release a slot's streams, events and buffers.  Teardown is best-effort: a
+// failed release leaves nothing the server still uses, so its status is not
+// reported.
 void free_slot(Slot &s) {
-    if (s.stream) hipStreamDestroy(s.stream);
-    if (s.done) hipEventDestroy(s.done);
-    hipHostFree(s.h_reads);
-    hipHostFree(s.h_off);
-    hipHostFree(s.h_len);
-    hipHostFree(s.h_E);
-    hipHostFree(s.h_woff);
-    hipHostFree(s.h_acc);
-    hipHostFree(s.h_pc);
-    hipFree(s.d_reads_in);
-    hipFree(s.d_woff);
-    hipFree(s.d_reads);
-    hipFree(s.d_refs);
-    hipFree(s.d_off);
-    hipFree(s.d_len);
-    hipFree(s.d_E);
-    hipFree(s.d_acc);
-    hipFree(s.d_pc);
-    hipFree(s.d_ws);
+    if (s.stream) (void)hipStreamDestroy(s.stream);
+    if (s.done) (void)hipEventDestroy(s.done);
+    (void)hipHostFree(s.h_reads);
+    (void)hipHostFree(s.h_off);
+    (void)hipHostFree(s.h_len);
+    (void)hipHostFree(s.h_E);
+    (void)hipHostFree(s.h_woff);
+    (void)hipHostFree(s.h_acc);
+    (void)hipHostFree(s.h_pc);
+    (void)hipFree(s.d_reads_in);
+    (void)hipFree(s.d_woff);
+    (void)hipFree(s.d_reads);
+    (void)hipFree(s.d_refs);
+    (void)hipFree(s.d_off);
+    (void)hipFree(s.d_len);
+    (void)hipFree(s.d_E);
+    (void)hipFree(s.d_acc);
+    (void)hipFree(s.d_pc);
+    (void)hipFree(s.d_ws);
 }
 
 bool alloc_slot(Slot &s, int64_t B, int nw, int max_len) {
@@ -388,7 +391,8 @@ int enqueue_batch(shouji_server *S, Slot &s) {
 }
 
 void scheduler_loop(shouji_server *S) {
-    hipSetDevice(S->device);
+    // on the server's device, or every batch this thread would launch fails
+    const bool on_device = hipSetDevice(S->device) == hipSuccess;
     const int64_t B = S->cfg.max_batch_pairs;
     std::unique_lock<std::mutex> lk(S->mu);
     for (;;) {
@@ -434,7 +438,7 @@ void scheduler_loop(shouji_server *S) {
         s->busy = true;
         S->batches++;
         lk.unlock();
-        s->status = enqueue_batch(S, *s);
+        s->status = on_device ? enqueue_batch(S, *s) : SHOUJI_ERR_DEVICE;
         lk.lock();
         S->inflight.push_back(s);
         S->cv.notify_all();
@@ -442,7 +446,7 @@ void scheduler_loop(shouji_server *S) {
 }
 
 void reaper_loop(shouji_server *S) {
-    hipSetDevice(S->device);
+    const bool on_device = hipSetDevice(S->device) == hipSuccess;
     std::unique_lock<std::mutex> lk(S->mu);
     for (;;) {
         if (S->inflight.empty()) {
@@ -452,7 +456,8 @@ void reaper_loop(shouji_server *S) {
         }
         Slot &s = *S->inflight.front();
         lk.unlock();
-        if (hipEventSynchronize(s.done) != hipSuccess && s.status == SHOUJI_OK) s.status = SHOUJI_ERR_DEVICE;
+        if ((!on_device || hipEventSynchronize(s.done) != hipSuccess) && s.status == SHOUJI_OK)
+            s.status = SHOUJI_ERR_DEVICE;
         int64_t at = 0;
         for (const Part &pt : s.parts) {
             shouji_request &r = pt.r->req;
@@ -647,7 +652,7 @@ extern "C" int shouji_server_destroy(shouji_server *S) {
     }
     S->sched.join();
     S->reaper.join();
-    hipSetDevice(S->device);
+    (void)hipSetDevice(S->device);   // best-effort: the slots' buffers belong to it
     for (auto &s : S->slots) free_slot(*s);
     delete S;
     return SHOUJI_OK;
