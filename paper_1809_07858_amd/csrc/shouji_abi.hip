@@ -11,6 +11,7 @@
 
 #include "../../include/shouji.h"
 #include "shouji_binning.h"
+#include "shouji_launch.h"
 #include "shouji_internal.h"
 
 namespace {
@@ -43,20 +44,8 @@ inline int ok() { return shouji::clear_error(); }
 extern "C" const char *shouji_last_error(void) { return g_err; }
 
 namespace {
-
-// Raise the dynamic LDS limit of a kernel to at least `bytes` (the largest
-// limit set so far is remembered per kernel in `limit`).
-std::mutex g_attr_mu;
-int raise_lds_limit(const void *kernel, size_t &limit, size_t bytes) {
-    std::lock_guard<std::mutex> g(g_attr_mu);
-    if (bytes <= limit) return SHOUJI_OK;
-    if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
-        return fail(SHOUJI_ERR_DEVICE, "cannot raise the LDS limit to %zu bytes: %s", bytes,
-                    hipGetErrorString(hipGetLastError()));
-    limit = bytes;
-    return SHOUJI_OK;
-}
-
+using shouji::LdsLimit;
+using shouji::raise_lds_limit;
 }  // namespace
 
 extern "C" int shouji_version(void) { return 1 * 10000 + 0 * 100 + 0; }
@@ -150,7 +139,7 @@ extern "C" int shouji_filter(const uint32_t *reads, const uint32_t *refs, const 
     const int64_t grid = (waves + shouji::kWavesPerGroup - 1) / shouji::kWavesPerGroup;
     if (grid > 0x7fffffff) return fail(SHOUJI_ERR_ARG, "n_pairs too large");
     prm.lds_wave_bytes = (int32_t)wave_lds;
-    static size_t lds_limit[4] = {0, 0, 0, 0};
+    static LdsLimit lds_limit[4];
     const int which = (quarter ? 2 : 0) + (prm.ring_only ? 1 : 0);
     const void *kernels[4] = {(const void *)shouji::shouji_plain_kernel, (const void *)shouji::shouji_plain_ring_kernel,
                               (const void *)shouji::shouji_plain_q_kernel,
@@ -221,7 +210,7 @@ extern "C" int shouji_filter_local(const uint32_t *reads, const uint32_t *refs, 
     if (grid > 0x7fffffff) return fail(SHOUJI_ERR_ARG, "n_pairs too large");
     prm.waves_per_group = wpg;
     prm.lds_wave_bytes = (int32_t)wave_lds;
-    static size_t lds_limit = 0;
+    static LdsLimit lds_limit;
     if (int rc = raise_lds_limit((const void *)shouji::shouji_local_kernel, lds_limit, lds)) return rc;
     hipLaunchKernelGGL(shouji::shouji_local_kernel, dim3((unsigned)grid), dim3(shouji::kWave * wpg), lds,
                        (hipStream_t)stream, prm);
@@ -355,7 +344,7 @@ extern "C" int shouji_filter_batched(const uint32_t *reads, const uint32_t *refs
     const int chunk = L.nbins <= shouji::scatter_max_bins(shouji::kScatterChunkLarge) ? shouji::kScatterChunkLarge
                                                                                         : shouji::kScatterChunkSmall;
     if (L.nbins <= shouji::scatter_max_bins(chunk)) {
-        static size_t slimit_large = 0, slimit_small = 0;
+        static LdsLimit slimit_large, slimit_small;
         const bool large = chunk == shouji::kScatterChunkLarge;
         const void *sk = large ? (const void *)shouji::bin_scatter_lds_kernel<shouji::kScatterChunkLarge>
                                : (const void *)shouji::bin_scatter_lds_kernel<shouji::kScatterChunkSmall>;
@@ -374,7 +363,7 @@ extern "C" int shouji_filter_batched(const uint32_t *reads, const uint32_t *refs
                            dim3(256), 0, st, sp);
     }
     // 4. the filter over the tiles, largest E class first
-    static size_t tlimit = 0;
+    static LdsLimit tlimit;
     const int Emax_len = max_len > 0 ? max_len - 1 : 0;
     for (int c = shouji::kEClasses - 1; c >= 0; c--) {
         if (c > 0 && Emax_len <= shouji::e_class_bound(c - 1)) continue;   // the class is empty
@@ -429,7 +418,7 @@ extern "C" int shouji_filter_batched(const uint32_t *reads, const uint32_t *refs
         const int64_t waves_needed = quarter ? 2 * L.max_tiles : L.max_tiles;
         const int64_t grid = (waves_needed + wpg - 1) / wpg;
         if (quarter) {
-            static size_t qlimit = 0;
+            static LdsLimit qlimit;
             if (int rc = raise_lds_limit((const void *)shouji::shouji_tiles_q_kernel, qlimit, wave_lds * wpg))
                 return rc;
             hipLaunchKernelGGL(shouji::shouji_tiles_q_kernel, dim3((unsigned)grid), dim3(shouji::kWave * wpg),

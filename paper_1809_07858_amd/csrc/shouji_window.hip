@@ -33,12 +33,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <mutex>
 #include <type_traits>
 
 #include "../../include/shouji.h"
 #include "shouji_bitslice.h"
 #include "shouji_internal.h"
+#include "shouji_launch.h"
 #include "shouji_variants.h"
 
 namespace shouji {
@@ -426,19 +426,9 @@ __global__ __launch_bounds__(kWinLanes, 1) void window_bs_kernel(WindowParams pr
 
 template <int W>
 static int launch_window(const WindowParams &prm, unsigned grid, hipStream_t st) {
-    static std::mutex mu;
-    static size_t limit = 0;
+    static LdsLimit limit;
     const size_t bytes = win_lds_bytes(W, prm.Ee);
-    {
-        std::lock_guard<std::mutex> g(mu);
-        if (bytes > limit) {
-            if (hipFuncSetAttribute(reinterpret_cast<const void *>(&window_bs_kernel<W>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
-                return set_error(SHOUJI_ERR_DEVICE, "shouji_filter_window: cannot raise the LDS limit to %zu bytes",
-                                 bytes);
-            limit = bytes;
-        }
-    }
+    if (int rc = raise_lds_limit(reinterpret_cast<const void *>(&window_bs_kernel<W>), limit, bytes)) return rc;
     hipLaunchKernelGGL(window_bs_kernel<W>, dim3(grid), dim3(kWinLanes), bytes, st, prm);
     return SHOUJI_OK;
 }
