@@ -111,6 +111,32 @@ def test_ragged_count_and_no_lengths(sj):
         assert np.array_equal(acc.cpu().numpy(), wa) and np.array_equal(pc.cpu().numpy(), wp), n
 
 
+def test_longest_sequences_and_widest_rings(sj):
+    # lengths up to 1,024 (11-bit counts), the widest window with E = 31 (the
+    # largest LDS rings, past 64 KB per wavefront), W = 1 with E = 0, pair
+    # counts that leave a partial wavefront of 2,048 pairs, and lengths mixed
+    # inside wavefronts
+    max_len = 1024
+    rng = np.random.default_rng(11)
+    n = 2048 + 77
+    P = rng.integers(0, 4, (n, max_len)).astype(np.uint8)
+    T = P.copy()
+    T[rng.random((n, max_len)) < 0.004] = 1
+    for i in range(0, n, 7):
+        T[i] = np.roll(T[i], 1)
+    L = rng.integers(900, max_len + 1, n).astype(np.int32)
+    L[::5] = max_len
+    r, t, Ld = _dev(sj, P, T, L, max_len)
+    for W, E in ((16, 31), (1, 0), (9, 31), (12, 7)):
+        print("window W=%d E=%d n=%d max_len=%d" % (W, E, n, max_len), flush=True)
+        acc, pc = sj.shouji_filter_window(r, t, Ld, E, W, max_len=max_len)
+        torch.cuda.synchronize()
+        wa, wp = oracle.shouji_batch_w(P, T, L, E, W)
+        assert np.array_equal(acc.cpu().numpy(), wa) and np.array_equal(pc.cpu().numpy(), wp), (W, E)
+        if W == 1:
+            assert (pc.cpu().numpy() > 255).any()   # counts past 8 bits
+
+
 def test_argument_errors(sj):
     d = torch.device("cuda:0")
     r = torch.zeros((4, 10), dtype=torch.int32, device=d)
