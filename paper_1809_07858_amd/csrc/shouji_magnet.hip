@@ -99,16 +99,20 @@ __global__ __launch_bounds__(kMagnetBlock) void magnet_kernel(MagnetParams prm) 
         start = 0;
         if (a > b) return 0;
         int carry = 0, cs = (a >> 4) * 16;                  // run reaching the word's start
+        // read position 16w - d of field 0 of text word w lies in read word
+        // w + dq at bit 2 * ((-d) mod 16), the same for every w; a word's upper
+        // read word is the next word's lower one
+        const int dq = (-d) >> 4;                            // floor division
+        const int ob = ((-d) & 15) * 2;
+        auto rword = [&](int q) -> uint32_t { return (q >= 0 && q < nw) ? read_word(q) : 0u; };
+        uint32_t lo_w = rword((a >> 4) + dq);
         for (int w = a >> 4; w <= (b >> 4); w++) {
             const int rest = b - (a > 16 * w ? a : 16 * w) + 1;   // positions left in the range
             if (carry + rest <= (best > need - 1 ? best : need - 1)) break;
             const uint32_t tw = ref_word(w);
-            const int q0 = 16 * w - d;                       // read position of the word's field 0
-            const int qw = q0 >> 4;                          // floor division
-            const int ob = (q0 & 15) * 2;
-            const uint32_t lo_w = (qw >= 0 && qw < nw) ? read_word(qw) : 0u;
-            const uint32_t hi_w = (qw + 1 >= 0 && qw + 1 < nw) ? read_word(qw + 1) : 0u;
+            const uint32_t hi_w = rword(w + dq + 1);
             const uint32_t pv = __builtin_amdgcn_alignbit(hi_w, lo_w, ob);
+            lo_w = hi_w;
             const uint32_t xr = tw ^ pv;
             const int klo = a - 16 * w > 0 ? a - 16 * w : 0;
             const int khi = b - 16 * w < 15 ? b - 16 * w : 15;
