@@ -106,7 +106,10 @@ __global__ __launch_bounds__(kMagnetBlock) void magnet_kernel(MagnetParams prm) 
         const int ob = ((-d) & 15) * 2;
         auto rword = [&](int q) -> uint32_t { return (q >= 0 && q < nw) ? read_word(q) : 0u; };
         uint32_t lo_w = rword((a >> 4) + dq);
-        for (int w = a >> 4; w <= (b >> 4); w++) {
+        // fields inside [a, b]: only the first and the last word are cut
+        const int wa = a >> 4, wb = b >> 4;
+        const uint32_t m_first = ~field_mask(a - 16 * wa), m_last = field_mask(b - 16 * wb + 1);
+        for (int w = wa; w <= wb; w++) {
             const int rest = b - (a > 16 * w ? a : 16 * w) + 1;   // positions left in the range
             if (carry + rest <= (best > need - 1 ? best : need - 1)) break;
             const uint32_t tw = ref_word(w);
@@ -114,9 +117,10 @@ __global__ __launch_bounds__(kMagnetBlock) void magnet_kernel(MagnetParams prm) 
             const uint32_t pv = __builtin_amdgcn_alignbit(hi_w, lo_w, ob);
             lo_w = hi_w;
             const uint32_t xr = tw ^ pv;
-            const int klo = a - 16 * w > 0 ? a - 16 * w : 0;
-            const int khi = b - 16 * w < 15 ? b - 16 * w : 15;
-            const uint32_t x = ~(xr | (xr >> 1)) & field_mask(khi + 1) & ~field_mask(klo);   // matches
+            uint32_t in_range = 0x55555555u;
+            if (w == wa) in_range &= m_first;
+            if (w == wb) in_range &= m_last;
+            const uint32_t x = ~(xr | (xr >> 1)) & in_range;  // matches
             if (x == 0x55555555u) {                          // 16 matches: the run goes on
                 carry += 16;
                 continue;
