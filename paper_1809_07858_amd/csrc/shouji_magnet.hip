@@ -132,7 +132,9 @@ __global__ __launch_bounds__(kMagnetBlock) void magnet_kernel(MagnetParams prm) 
                 start = cs;
             }
             const int trail = 15 - ((31 - __builtin_clz(mis)) >> 1);
-            const uint32_t xi = x & ~field_mask(lead) & field_mask(16 - trail);
+            // matches strictly between the first and the last mismatch
+            // (lead <= 15, trail <= 15: the shifts stay below 32)
+            const uint32_t xi = x & (0x55555555u << (2 * lead)) & (0x55555555u >> (2 * trail));
             if (xi) {
                 const uint32_t r2 = xi & (xi >> 2), r4 = r2 & (r2 >> 4), r8 = r4 & (r4 >> 8);
                 int L = 1;
