@@ -101,10 +101,12 @@ __global__ __launch_bounds__(kMagnetBlock) void magnet_kernel(MagnetParams prm) 
         int carry = 0, cs = (a >> 4) * 16;                  // run reaching the word's start
         // read position 16w - d of field 0 of text word w lies in read word
         // w + dq at bit 2 * ((-d) mod 16), the same for every w; a word's upper
-        // read word is the next word's lower one
+        // read word is the next word's lower one.  Fields in [a, b] have read
+        // positions in [0, m), so a word index outside the read's words only
+        // feeds fields that are masked: it is clamped to a valid word.
         const int dq = (-d) >> 4;                            // floor division
         const int ob = ((-d) & 15) * 2;
-        auto rword = [&](int q) -> uint32_t { return (q >= 0 && q < nw) ? read_word(q) : 0u; };
+        auto rword = [&](int q) -> uint32_t { return read_word(min(max(q, 0), nw - 1)); };
         uint32_t lo_w = rword((a >> 4) + dq);
         // fields inside [a, b]: only the first and the last word are cut
         const int wa = a >> 4, wb = b >> 4;
