@@ -567,397 +567,415 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
                 if (b < nlb) lbvp[b * kPairLanes] = lenr[b];
         }
     }
-    Ends X;
-    if constexpr (TWO) {
-        X.seen = 0u;
+    // The rest is compiled twice: UNI (a compile-time fact) when every valid
+    // pair of the group has one length, so that a group of one length runs
+    // the code of the kernel without a length array (the masks from the
+    // positions, no mask table or length planes kept live).
+    auto rest = [&](auto uni_tag) __attribute__((always_inline)) {
+        constexpr bool UNI = decltype(uni_tag)::value;
+        Ends X;
+        if constexpr (TWO) {
+            X.seen = 0u;
 #pragma unroll
-        for (int b = 0; b < kLenBits; b++) X.first[b] = X.last[b] = 0u;
-    }
-
-    FsmState F;
-    F.s0 = F.s1 = F.s2 = ~0u;
-    F.ones = F.twos = F.fours = 0u;
-#pragma unroll
-    for (int b = 0; b < 8; b++) F.e[b] = 0u;
-
-    const int nblocks = (m_max + kBlock - 1) / kBlock;
-    const int niter = (nblocks + 1) / 2;
-    const int ebits = 32 - __builtin_clz((unsigned)niter | 1u);   // bits of niter (each half: <= niter blocks)
-    const int nhalves = (m_words + kHalf - 1) / kHalf;  // words holding positions < m_words
-    const int H0 = (kBlock + kCols - 1 + Ee) / kHalf; // last pattern word iteration 0 reads
-
-    // Masks "position x is past the pair's end" (x < 0 counts as past) for
-    // positions x0 .. x0+count-1, stored at dst[s * 32], from the length bit
-    // planes at planes[b * 32] (nlb of them, higher bits zero), bit-sliced
-    // over the 32 pairs.  The first non-negative position takes a full
-    // compare (length <= x); each next one adds the pairs whose length
-    // equals it, one gate per length bit.
-    auto fill_range = [&](int x0, int count, const uint32_t *planes, uint32_t *dst) {
-        // x0 opaque: its bit tests are not strength-reduced into values
-        // carried through the window loop
-        asm volatile("" : "+v"(x0));
-        uint32_t lb[kLenBits];
-#pragma unroll
-        for (int b = 0; b < kLenBits; b++) lb[b] = b < nlb ? planes[b * kPairLanes] : 0u;
-        uint32_t msk = ~0u;
-        for (int s = 0; s < count; s++) {
-            const int x = x0 + s;
-            if (x == max(x0, 0)) {
-                uint32_t g = 0u;  // g = (length > x)
-#pragma unroll
-                for (int b = 0; b < kLenBits; b++) {
-                    const uint32_t sx = ((x >> b) & 1) ? ~0u : 0u;
-                    g = mux(sx, lb[b] & g, lb[b] | g);
-                }
-                msk = ~g;
-            } else if (x > 0) {
-                uint32_t e = ~0u;  // e = (length == x)
-#pragma unroll
-                for (int b = 0; b < kLenBits; b++) {
-                    const uint32_t sx = ((x >> b) & 1) ? ~0u : 0u;
-                    e = gate<kTTAndXnor>(e, lb[b], sx);
-                }
-                msk |= e;
-            }
-            dst[s * kPairLanes] = x < 0 ? ~0u : msk;
+            for (int b = 0; b < kLenBits; b++) X.first[b] = X.last[b] = 0u;
         }
-    };
-    // per-lane masks of positions i0 .. i0+count-1, stored at dst[s * 32]
-    // (groups of mixed lengths; a group of one length takes its masks from
-    // the positions)
-    auto fill_masks = [&](int i0, uint32_t *dst, int count) { fill_range(i0, count, lbv, dst); };
-    // TWO: text masks of i0 .. i0+C-1 and pattern masks of i0-Ee .. i0+C-1+Ee
-    // (a negative pattern position is outside the read)
-    auto fill_masks2 = [&](int i0, uint32_t *dst, uint32_t *dstp, int C) {
-        fill_range(i0, C, lbv, dst);
-        fill_range(i0 - Ee, C + 2 * Ee, lbvp, dstp);
-    };
 
-    // One transpose pass: the low lane half turns pattern word pw into ring
-    // entries (positions 16pw..16pw+15), the high half turns text word tw into
-    // planes left in raw (plane 2u = low code bit of position 16tw+u).  A word
-    // outside [0, limit) is replaced by a valid one: its positions lie beyond
-    // every pair's length, where the masks override every cell, and a pattern
-    // word outside the range is not written to the ring.
-    auto pass_load = [&](int pw, int tw, int limit, uint32_t (&raw)[32]) {
-        const int w = min(max(half ? tw : pw, 0), limit - 1);
-        const uint32_t *row = seq + (int64_t)w * J.ld + base;
-        load_word(row, full, left, pl, raw);
-    };
-    // The ring entries of pattern word pw (low half): slot by slot with the
-    // wrap test when R is the minimal size, or as two runs of 8 consecutive
-    // slots when R is a multiple of 8.
-    auto ring_write = [&](int pw, int limit, uint32_t (&raw)[32]) {
-        if (half == 0 && pw < limit && (R & 7) != 0) {
-            int slot = (pw * kHalf) % R;
+        FsmState F;
+        F.s0 = F.s1 = F.s2 = ~0u;
+        F.ones = F.twos = F.fours = 0u;
 #pragma unroll
-            for (int u = 0; u < kHalf; u++) {
-                const uint2 v = make_uint2(raw[2 * u], raw[2 * u + 1]);
-                ring[slot * kRingStride + pl] = v;
-                if (slot < kMirror) ring[(slot + R) * kRingStride + pl] = v;
-                slot = slot + 1 == R ? 0 : slot + 1;
+        for (int b = 0; b < 8; b++) F.e[b] = 0u;
+
+        const int nblocks = (m_max + kBlock - 1) / kBlock;
+        const int niter = (nblocks + 1) / 2;
+        const int ebits = 32 - __builtin_clz((unsigned)niter | 1u);   // bits of niter (each half: <= niter blocks)
+        const int nhalves = (m_words + kHalf - 1) / kHalf;  // words holding positions < m_words
+        const int H0 = (kBlock + kCols - 1 + Ee) / kHalf; // last pattern word iteration 0 reads
+
+        // Masks "position x is past the pair's end" (x < 0 counts as past) for
+        // positions x0 .. x0+count-1, stored at dst[s * 32], from the length bit
+        // planes at planes[b * 32] (nlb of them, higher bits zero), bit-sliced
+        // over the 32 pairs.  The first non-negative position takes a full
+        // compare (length <= x); each next one adds the pairs whose length
+        // equals it, one gate per length bit.
+        auto fill_range = [&](int x0, int count, const uint32_t *planes, uint32_t *dst) {
+            // x0 opaque: its bit tests are not strength-reduced into values
+            // carried through the window loop
+            asm volatile("" : "+v"(x0));
+            uint32_t lb[kLenBits];
+#pragma unroll
+            for (int b = 0; b < kLenBits; b++) lb[b] = b < nlb ? planes[b * kPairLanes] : 0u;
+            uint32_t msk = ~0u;
+            for (int s = 0; s < count; s++) {
+                const int x = x0 + s;
+                if (x == max(x0, 0)) {
+                    uint32_t g = 0u;  // g = (length > x)
+#pragma unroll
+                    for (int b = 0; b < kLenBits; b++) {
+                        const uint32_t sx = ((x >> b) & 1) ? ~0u : 0u;
+                        g = mux(sx, lb[b] & g, lb[b] | g);
+                    }
+                    msk = ~g;
+                } else if (x > 0) {
+                    uint32_t e = ~0u;  // e = (length == x)
+#pragma unroll
+                    for (int b = 0; b < kLenBits; b++) {
+                        const uint32_t sx = ((x >> b) & 1) ? ~0u : 0u;
+                        e = gate<kTTAndXnor>(e, lb[b], sx);
+                    }
+                    msk |= e;
+                }
+                dst[s * kPairLanes] = x < 0 ? ~0u : msk;
             }
-        } else if (half == 0 && pw < limit) {
-            // R is a multiple of 8: each half word goes to 8 consecutive
-            // slots (paired writes), the slots below kMirror also past R
+        };
+        // per-lane masks of positions i0 .. i0+count-1, stored at dst[s * 32]
+        // (groups of mixed lengths; a group of one length takes its masks from
+        // the positions)
+        auto fill_masks = [&](int i0, uint32_t *dst, int count) { fill_range(i0, count, lbv, dst); };
+        // TWO: text masks of i0 .. i0+C-1 and pattern masks of i0-Ee .. i0+C-1+Ee
+        // (a negative pattern position is outside the read)
+        auto fill_masks2 = [&](int i0, uint32_t *dst, uint32_t *dstp, int C) {
+            fill_range(i0, C, lbv, dst);
+            fill_range(i0 - Ee, C + 2 * Ee, lbvp, dstp);
+        };
+
+        // One transpose pass: the low lane half turns pattern word pw into ring
+        // entries (positions 16pw..16pw+15), the high half turns text word tw into
+        // planes left in raw (plane 2u = low code bit of position 16tw+u).  A word
+        // outside [0, limit) is replaced by a valid one: its positions lie beyond
+        // every pair's length, where the masks override every cell, and a pattern
+        // word outside the range is not written to the ring.
+        auto pass_load = [&](int pw, int tw, int limit, uint32_t (&raw)[32]) {
+            const int w = min(max(half ? tw : pw, 0), limit - 1);
+            const uint32_t *row = seq + (int64_t)w * J.ld + base;
+            load_word(row, full, left, pl, raw);
+        };
+        // The ring entries of pattern word pw (low half): slot by slot with the
+        // wrap test when R is the minimal size, or as two runs of 8 consecutive
+        // slots when R is a multiple of 8.
+        auto ring_write = [&](int pw, int limit, uint32_t (&raw)[32]) {
+            if (half == 0 && pw < limit && (R & 7) != 0) {
+                int slot = (pw * kHalf) % R;
 #pragma unroll
-            for (int h = 0; h < 2; h++) {
-                const int s0 = (pw * kHalf + 8 * h) % R;
-                uint2 *dst = ring + s0 * kRingStride + pl;
+                for (int u = 0; u < kHalf; u++) {
+                    const uint2 v = make_uint2(raw[2 * u], raw[2 * u + 1]);
+                    ring[slot * kRingStride + pl] = v;
+                    if (slot < kMirror) ring[(slot + R) * kRingStride + pl] = v;
+                    slot = slot + 1 == R ? 0 : slot + 1;
+                }
+            } else if (half == 0 && pw < limit) {
+                // R is a multiple of 8: each half word goes to 8 consecutive
+                // slots (paired writes), the slots below kMirror also past R
 #pragma unroll
-                for (int u = 0; u < 8; u++)
-                    dst[u * kRingStride] = make_uint2(raw[2 * (8 * h + u)], raw[2 * (8 * h + u) + 1]);
-                if (s0 < kMirror) {
+                for (int h = 0; h < 2; h++) {
+                    const int s0 = (pw * kHalf + 8 * h) % R;
+                    uint2 *dst = ring + s0 * kRingStride + pl;
 #pragma unroll
                     for (int u = 0; u < 8; u++)
-                        if (s0 + u < kMirror)
-                            dst[(R + u) * kRingStride] = make_uint2(raw[2 * (8 * h + u)], raw[2 * (8 * h + u) + 1]);
-                }
-            }
-        }
-    };
-    auto pass_finish = [&](int pw, int limit, uint32_t (&raw)[32]) {
-        transpose32(raw);
-        ring_write(pw, limit, raw);
-    };
-    auto pass = [&](int pw, int tw, uint32_t (&raw)[32]) {
-        pass_load(pw, tw, nhalves, raw);
-        pass_finish(pw, nhalves, raw);
-    };
-
-    // Text planes of a block: the 11 positions (low, high plane) of this lane's
-    // block.  The low half's block 2j reads positions 0..10 of text word j, the
-    // high half's block 2j+1 positions 8..15 of word j and 0..2 of word j+1.
-    // The high half transposes every text word once and the low half receives
-    // what it needs by lane swaps.  Two arrays alternate between iterations:
-    // one holds the current block's planes; the other is started from the
-    // newest word (start_text) and completed one pass later (finish_text).
-    //
-    // start_text, from text word w in the high half's raw: low half <- its
-    // positions 0..10 (from the high half), high half <- its positions 8..15.
-    auto start_text = [&](uint32_t (&T)[2 * kCols], const uint32_t (&raw)[32]) {
+                        dst[u * kRingStride] = make_uint2(raw[2 * (8 * h + u)], raw[2 * (8 * h + u) + 1]);
+                    if (s0 < kMirror) {
 #pragma unroll
-        for (int t = 0; t < 2 * kBlock; t++)  // low lanes: raw[t] of the high half; high lanes: own raw[16+t]
-            T[t] = __builtin_amdgcn_permlane32_swap(raw[t], raw[2 * kBlock + t], false, false)[1];
-        // low lanes: raw[t] of the high half (the partner raw[t+6] is a
-        // position the block does not read, free to be overwritten)
-#pragma unroll
-        for (int t = 2 * kBlock; t < 2 * kCols; t++)
-            T[t] = __builtin_amdgcn_permlane32_swap(raw[t], raw[t + 6], false, false)[1];
-    };
-    // finish_text, from text word w+1 in the high half's raw: high half <- its
-    // positions 0..2 (the low half's planes are complete already).
-    auto finish_text = [&](uint32_t (&T)[2 * kCols], const uint32_t (&raw)[32]) {
-#pragma unroll
-        for (int t = 2 * kBlock; t < 2 * kCols; t++) T[t] = half ? raw[t - 2 * kBlock] : T[t];
-    };
-
-    uint32_t TA[2 * kCols], TB[2 * kCols];
-    if (nblocks > 0) {
-        // pattern words 0..H0 into the ring; text words 0 and 1
-        uint32_t raw1[32];
-        ring_write(0, nhalves, raw0);
-        start_text(TA, raw0);
-        if (nhalves > 1) {       // else word 1 holds no position of any pair
-            pass(1, 1, raw1);
-            finish_text(TA, raw1);
-            start_text(TB, raw1);
-        }
-        for (int hp = 2; hp <= H0; hp++) pass(hp, -1, raw1);
-    }
-
-    // Iteration j: blocks 2j (low half) and 2j+1 (high half) with text planes
-    // Tc; afterwards Tn (started from word j+1) is completed for iteration j+1
-    // and Tc is restarted from word j+2 for iteration j+2.
-    // Every iteration but a short last one has two full blocks (its 16
-    // windows start below m_max - 8).
-    auto iteration = [&](int j, uint32_t (&Tc)[2 * kCols], uint32_t (&Tn)[2 * kCols]) {
-        const int lo = kHalf * j;                       // first window of the iteration
-        const int i0 = lo + kBlock * half;              // this lane's block
-        const int hi_col = lo + kBlock + kCols - 1;     // last text column read
-        Winner<kBlock> W;
-        {
-            uint32_t tl[kCols], th[kCols];
-#pragma unroll
-            for (int t = 0; t < kCols; t++) { tl[t] = Tc[2 * t]; th[t] = Tc[2 * t + 1]; }
-            const int sb = i0 % R;
-            if ((Ee > lo) || (hi_col + Ee >= m_min)) {
-                if constexpr (TWO) {
-                    if (read_uniform) {
-                        // one read length: pattern masks from the positions
-                        fill_range(i0, kCols, lbv, nvh);
-                        block_winners<kBlock, TWO, true, true>(W, ring, nvh, nvph, pl, i0, sb, Ee, R, lo, hi_col,
-                                                               m_min, tl, th, rmax);
-                    } else {
-                        fill_masks2(i0, nvh, nvph, kCols);
-                        block_winners<kBlock, TWO, true, false>(W, ring, nvh, nvph, pl, i0, sb, Ee, R, lo, hi_col,
-                                                                m_min, tl, th);
+                        for (int u = 0; u < 8; u++)
+                            if (s0 + u < kMirror)
+                                dst[(R + u) * kRingStride] = make_uint2(raw[2 * (8 * h + u)], raw[2 * (8 * h + u) + 1]);
                     }
-                } else if (RO || uniform) {
-                    // one length for every valid pair: the masks follow from
-                    // the positions, as without a length array
-                    block_winners<kBlock, false, true, true>(W, ring, nvh, nvph, pl, i0, sb, Ee, R, lo, hi_col,
-                                                             m_min, tl, th, m_max);
-                } else {
-                    fill_masks(i0, nvh, kCols + Ee);
-                    block_winners<kBlock, false, true, false>(W, ring, nvh, nvph, pl, i0, sb, Ee, R, lo, hi_col,
-                                                              m_min, tl, th);
                 }
-            } else {
-                // interior: every pattern index i0+t-d lies in [0, m_min) and every
-                // text column below m_min, so no candidate needs a mask
-                block_winners<kBlock, TWO, false, RO>(W, ring, nvh, nvph, pl, i0, sb, Ee, R, lo, hi_col, m_min,
-                                                      tl, th);
             }
-        }
-        // the next pass (after all reads of iteration j): the pattern word
-        // iteration j+1 first needs, and text word j+2 (a pass whose two words
-        // both lie past every pair's end is skipped: their planes are never
-        // unmasked).  Its loads are issued here, before the serial update and
-        // the count, which cover their latency; the ring write comes after.
-        const bool do_pass = j + 1 < niter && (j + 1 + H0 < nhalves || j + 2 < nhalves);
-        uint32_t raw[32];
-        if (do_pass) pass_load(j + 1 + H0, j + 2, nhalves, raw);
-        // serial bit-vector update: block 2j on the low half, 2j+1 on the
-        // high; then both halves count their final bits at once
-        uint32_t o[kBlock];
-        if (half == 0) block_fsm<kBlock>(F, W, o);
-        F.s0 = from_half0(F.s0); F.s1 = from_half0(F.s1); F.s2 = from_half0(F.s2);
-        if (half == 1) block_fsm<kBlock>(F, W, o);
-        F.s0 = from_half1(F.s0); F.s1 = from_half1(F.s1); F.s2 = from_half1(F.s2);
-        block_count<kBlock, TWO>(F, o, X, lo + kBlock * half, ebits);
-        if (do_pass) {
-            pass_finish(j + 1 + H0, nhalves, raw);
-            finish_text(Tn, raw);
-            start_text(Tc, raw);
-        }
-    };
-    // A last iteration with at most 8 windows left runs blocks of NB = 4
-    // windows (at most 4 left: NB = 2): the low half's at lo, the high half's
-    // at lo+NB (if any window is left there).  Its text planes: the low half's
-    // positions 0..NB+2 of word j are its own, the high half's positions
-    // NB..2NB+2 are the low half's.
-    auto short_iteration = [&](auto nb, int j, const uint32_t (&Tc)[2 * kCols], bool activeB) {
-        constexpr int NB = decltype(nb)::value, C = NB + 3;
-        const int lo = kHalf * j;
-        const int i0 = lo + NB * half;
-        uint32_t tl[C], th[C];
-#pragma unroll
-        for (int t = 0; t < C; t++) {
-            tl[t] = __builtin_amdgcn_permlane32_swap(Tc[2 * t], Tc[2 * t + 2 * NB], false, false)[0];
-            th[t] = __builtin_amdgcn_permlane32_swap(Tc[2 * t + 1], Tc[2 * t + 1 + 2 * NB], false, false)[0];
-        }
-        uint32_t *nvs = nv + NB * half * kPairLanes + pl;
-        uint32_t *nvps = nvp + NB * half * kPairLanes + pl;
-        Winner<NB> W;
-        if constexpr (TWO) {
-            if (read_uniform) {
-                fill_range(i0, C, lbv, nvs);
-                block_winners<NB, TWO, true, true>(W, ring, nvs, nvps, pl, i0, i0 % R, Ee, R, lo, lo + NB + C - 1,
-                                                   m_min, tl, th, rmax);
-            } else {
-                fill_masks2(i0, nvs, nvps, C);
-                block_winners<NB, TWO, true, false>(W, ring, nvs, nvps, pl, i0, i0 % R, Ee, R, lo, lo + NB + C - 1,
-                                                    m_min, tl, th);
-            }
-        } else if (RO || uniform) {
-            block_winners<NB, false, true, true>(W, ring, nvs, nvps, pl, i0, i0 % R, Ee, R, lo, lo + NB + C - 1,
-                                                 m_min, tl, th, m_max);
-        } else {
-            fill_masks(i0, nvs, C + Ee);
-            block_winners<NB, false, true, false>(W, ring, nvs, nvps, pl, i0, i0 % R, Ee, R, lo, lo + NB + C - 1,
-                                                  m_min, tl, th);
-        }
-        uint32_t o[NB];
-        if (half == 0) block_fsm<NB>(F, W, o);
-        F.s0 = from_half0(F.s0); F.s1 = from_half0(F.s1); F.s2 = from_half0(F.s2);
-        if (half == 1 && activeB) block_fsm<NB>(F, W, o);
-        if (half == 0 || activeB) block_count<NB, TWO>(F, o, X, lo + NB * half, ebits);
-    };
-    const int rem = m_max - kHalf * (niter - 1);        // windows of the last iteration
-    const bool short_last = niter > 0 && rem <= kBlock;
-    const int nlong = niter - (short_last ? 1 : 0);
-    int j = 0;
-    for (; j + 1 < nlong; j += 2) {
-        iteration(j, TA, TB);
-        iteration(j + 1, TB, TA);
-    }
-    if (j < nlong) iteration(j, TA, TB);
-    if (short_last) {
-        uint32_t Tl[2 * kCols];
-#pragma unroll
-        for (int t = 0; t < 2 * kCols; t++) Tl[t] = (nlong & 1) ? TB[t] : TA[t];
-        if (rem > 4)
-            short_iteration(std::integral_constant<int, 4>(), nlong, Tl, true);
-        else
-            short_iteration(std::integral_constant<int, 2>(), nlong, Tl, rem > 2);
-    }
-    // windows whose final S bit went into the counter
-    const int nwin = !short_last ? kHalf * niter
-                                 : kHalf * nlong + (rem > 4 ? kBlock : (rem > 2 ? kBlock / 2 : kBlock / 4));
+        };
+        auto pass_finish = [&](int pw, int limit, uint32_t (&raw)[32]) {
+            transpose32(raw);
+            ring_write(pw, limit, raw);
+        };
+        auto pass = [&](int pw, int tw, uint32_t (&raw)[32]) {
+            pass_load(pw, tw, nhalves, raw);
+            pass_finish(pw, nhalves, raw);
+        };
 
-    // ---- add the two halves' ones counters (each half then holds the
-    // total), then each half writes 16 of the 32 pairs of its lanes
-    // the same register of the other lane half (one lane swap, no LDS)
-    auto other_half = [half](uint32_t v) {
-        const auto sw = __builtin_amdgcn_permlane32_swap(v, v, false, false);
-        return half ? (uint32_t)sw[0] : (uint32_t)sw[1];
-    };
-    uint32_t cnt[32];
-    cnt[0] = F.ones; cnt[1] = F.twos; cnt[2] = F.fours;
+        // Text planes of a block: the 11 positions (low, high plane) of this lane's
+        // block.  The low half's block 2j reads positions 0..10 of text word j, the
+        // high half's block 2j+1 positions 8..15 of word j and 0..2 of word j+1.
+        // The high half transposes every text word once and the low half receives
+        // what it needs by lane swaps.  Two arrays alternate between iterations:
+        // one holds the current block's planes; the other is started from the
+        // newest word (start_text) and completed one pass later (finish_text).
+        //
+        // start_text, from text word w in the high half's raw: low half <- its
+        // positions 0..10 (from the high half), high half <- its positions 8..15.
+        auto start_text = [&](uint32_t (&T)[2 * kCols], const uint32_t (&raw)[32]) {
 #pragma unroll
-    for (int b = 0; b < 8; b++) cnt[3 + b] = F.e[b];
-    {
-        uint32_t cy = 0u;
+            for (int t = 0; t < 2 * kBlock; t++)  // low lanes: raw[t] of the high half; high lanes: own raw[16+t]
+                T[t] = __builtin_amdgcn_permlane32_swap(raw[t], raw[2 * kBlock + t], false, false)[1];
+            // low lanes: raw[t] of the high half (the partner raw[t+6] is a
+            // position the block does not read, free to be overwritten)
 #pragma unroll
-        for (int b = 0; b < 11; b++) {
-            const uint32_t o = other_half(cnt[b]);
-            const uint32_t s_ = gate<kTTXor3>(cnt[b], o, cy);
-            cy = gate<kTTMaj>(cnt[b], o, cy);
-            cnt[b] = s_;
+            for (int t = 2 * kBlock; t < 2 * kCols; t++)
+                T[t] = __builtin_amdgcn_permlane32_swap(raw[t], raw[t + 6], false, false)[1];
+        };
+        // finish_text, from text word w+1 in the high half's raw: high half <- its
+        // positions 0..2 (the low half's planes are complete already).
+        auto finish_text = [&](uint32_t (&T)[2 * kCols], const uint32_t (&raw)[32]) {
+#pragma unroll
+            for (int t = 2 * kBlock; t < 2 * kCols; t++) T[t] = half ? raw[t - 2 * kBlock] : T[t];
+        };
+
+        uint32_t TA[2 * kCols], TB[2 * kCols];
+        if (nblocks > 0) {
+            // pattern words 0..H0 into the ring; text words 0 and 1
+            uint32_t raw1[32];
+            ring_write(0, nhalves, raw0);
+            start_text(TA, raw0);
+            if (nhalves > 1) {       // else word 1 holds no position of any pair
+                pass(1, 1, raw1);
+                finish_text(TA, raw1);
+                start_text(TB, raw1);
+            }
+            for (int hp = 2; hp <= H0; hp++) pass(hp, -1, raw1);
         }
-    }
-    // TWO: the zeros' first and last positions over both halves' blocks
-    uint32_t pos[TWO ? 32 : 1];
-    if constexpr (TWO) {
-        uint32_t fh[kLenBits], lh[kLenBits];
-        const uint32_t seen_h = other_half(X.seen);
+
+        // Iteration j: blocks 2j (low half) and 2j+1 (high half) with text planes
+        // Tc; afterwards Tn (started from word j+1) is completed for iteration j+1
+        // and Tc is restarted from word j+2 for iteration j+2.
+        // Every iteration but a short last one has two full blocks (its 16
+        // windows start below m_max - 8).
+        auto iteration = [&](int j, uint32_t (&Tc)[2 * kCols], uint32_t (&Tn)[2 * kCols]) {
+            const int lo = kHalf * j;                       // first window of the iteration
+            const int i0 = lo + kBlock * half;              // this lane's block
+            const int hi_col = lo + kBlock + kCols - 1;     // last text column read
+            Winner<kBlock> W;
+            {
+                uint32_t tl[kCols], th[kCols];
 #pragma unroll
-        for (int b = 0; b < kLenBits; b++) { fh[b] = other_half(X.first[b]); lh[b] = other_half(X.last[b]); }
-        // fh < first and last < lh: borrow chains from the low bit
-        uint32_t flt = gate<kTTAndNotA>(fh[0], X.first[0], X.first[0]);
-        uint32_t lgt = gate<kTTAndNotA>(X.last[0], lh[0], lh[0]);
-#pragma unroll
-        for (int b = 1; b < kLenBits; b++) {
-            flt = gate<kTTMajNotA>(fh[b], X.first[b], flt);
-            lgt = gate<kTTMajNotA>(X.last[b], lh[b], lgt);
-        }
-        // take the other half's position if it has a zero and this one has
-        // none or a later first (earlier last) zero
-        const uint32_t tf = seen_h & (~X.seen | flt);
-        const uint32_t tl_ = seen_h & (~X.seen | lgt);
-#pragma unroll
-        for (int b = 0; b < 32; b++) pos[b] = 0u;
-#pragma unroll
-        for (int b = 0; b < kLenBits; b++) {
-            pos[b] = mux(tf, fh[b], X.first[b]);
-            pos[16 + b] = mux(tl_, lh[b], X.last[b]);
-        }
-        X.seen |= seen_h;
-    }
-    // rows 16.. carry each pair's length (unless all valid pairs have
-    // length m_max) and valid bit through the transpose
-#pragma unroll
-    for (int b = 11; b < 32; b++)
-        cnt[b] = (b >= 16 && b < 16 + nlb && !uniform) ? lbv[(b - 16) * kPairLanes] : 0u;
-    cnt[16 + kLenBits] = valid;
-    if constexpr (TWO) {
-        cnt[17 + kLenBits] = X.seen;
-        transpose32(pos);  // pos[k]: first zero | last zero << 16
-    }
-    transpose32(cnt);  // cnt[k]: ones of S over windows [0, nwin) | length << 16 | valid << 27 (| seen << 28)
-    // both halves hold the same rows: the low half writes pairs k < 16, the
-    // high half pairs k >= 16 (a lane swap brings row 16+k to register k)
-#pragma unroll
-    for (int k = 0; k < 16; k++) {
-        cnt[k] = __builtin_amdgcn_permlane32_swap(cnt[k], cnt[16 + k], false, false)[0];
-        if constexpr (TWO) pos[k] = __builtin_amdgcn_permlane32_swap(pos[k], pos[16 + k], false, false)[0];
-    }
-    // the pair-count bound again, opaque to the compiler here, so that the
-    // stores' range checks are not computed (and kept live) before the loop
-    int left_out = __builtin_amdgcn_readfirstlane(left);
-    asm volatile("" : "+s"(left_out));
-#pragma unroll
-    for (int k = 0; k < 16; k++) {
-        const int kk = k + 16 * half;
-        const int64_t p = base + (int64_t)kk * kPairLanes + pl;
-        if (!full && kk * kPairLanes + pl >= left_out) continue;
-        const uint32_t w = cnt[k];
-        const int m = uniform ? m_max : (int)((w >> 16) & ((1u << kLenBits) - 1));
-        uint8_t acc;
-        int16_t pc;
-        if (!((w >> (16 + kLenBits)) & 1u)) {
-            acc = 0xFF;
-            pc = -1;
-        } else {
-            // S stays 1 on [m, nwin): those ones are not part of the pair
-            int ones = (int)(w & 0xFFFFu) - (nwin - m);
-            if constexpr (TWO) {
-                if ((w >> (17 + kLenBits)) & 1u) {
-                    // ones before the first zero, after the last zero
-                    const int first = (int)(pos[k] & ((1u << kLenBits) - 1));
-                    const int last = (int)((pos[k] >> 16) & ((1u << kLenBits) - 1));
-                    if (J.mode == 1 || J.mode == 2) ones -= first;
-                    if (J.mode == 1 || J.mode == 3) ones -= m - 1 - last;
+                for (int t = 0; t < kCols; t++) { tl[t] = Tc[2 * t]; th[t] = Tc[2 * t + 1]; }
+                const int sb = i0 % R;
+                if ((Ee > lo) || (hi_col + Ee >= m_min)) {
+                    if constexpr (TWO) {
+                        if (read_uniform) {
+                            // one read length: pattern masks from the positions
+                            fill_range(i0, kCols, lbv, nvh);
+                            block_winners<kBlock, TWO, true, true>(W, ring, nvh, nvph, pl, i0, sb, Ee, R, lo, hi_col,
+                                                                   m_min, tl, th, rmax);
+                        } else {
+                            fill_masks2(i0, nvh, nvph, kCols);
+                            block_winners<kBlock, TWO, true, false>(W, ring, nvh, nvph, pl, i0, sb, Ee, R, lo, hi_col,
+                                                                    m_min, tl, th);
+                        }
+                    } else if (UNI) {
+                        // one length for every valid pair: the masks follow from
+                        // the positions, as without a length array
+                        block_winners<kBlock, false, true, true>(W, ring, nvh, nvph, pl, i0, sb, Ee, R, lo, hi_col,
+                                                                 m_min, tl, th, m_max);
+                    } else {
+                        fill_masks(i0, nvh, kCols + Ee);
+                        block_winners<kBlock, false, true, false>(W, ring, nvh, nvph, pl, i0, sb, Ee, R, lo, hi_col,
+                                                                  m_min, tl, th);
+                    }
+                } else {
+                    // interior: every pattern index i0+t-d lies in [0, m_min) and every
+                    // text column below m_min, so no candidate needs a mask
+                    block_winners<kBlock, TWO, false, UNI>(W, ring, nvh, nvph, pl, i0, sb, Ee, R, lo, hi_col, m_min,
+                                                          tl, th);
                 }
             }
-            const int E = J.Edec ? J.Edec[p] : J.E;
-            acc = ones <= E ? 1 : 0;
-            pc = (int16_t)ones;
+            // the next pass (after all reads of iteration j): the pattern word
+            // iteration j+1 first needs, and text word j+2 (a pass whose two words
+            // both lie past every pair's end is skipped: their planes are never
+            // unmasked).  Its loads are issued here, before the serial update and
+            // the count, which cover their latency; the ring write comes after.
+            const bool do_pass = j + 1 < niter && (j + 1 + H0 < nhalves || j + 2 < nhalves);
+            uint32_t raw[32];
+            if (do_pass) pass_load(j + 1 + H0, j + 2, nhalves, raw);
+            // serial bit-vector update: block 2j on the low half, 2j+1 on the
+            // high; then both halves count their final bits at once
+            uint32_t o[kBlock];
+            if (half == 0) block_fsm<kBlock>(F, W, o);
+            F.s0 = from_half0(F.s0); F.s1 = from_half0(F.s1); F.s2 = from_half0(F.s2);
+            if (half == 1) block_fsm<kBlock>(F, W, o);
+            F.s0 = from_half1(F.s0); F.s1 = from_half1(F.s1); F.s2 = from_half1(F.s2);
+            block_count<kBlock, TWO>(F, o, X, lo + kBlock * half, ebits);
+            if (do_pass) {
+                pass_finish(j + 1 + H0, nhalves, raw);
+                finish_text(Tn, raw);
+                start_text(Tc, raw);
+            }
+        };
+        // A last iteration with at most 8 windows left runs blocks of NB = 4
+        // windows (at most 4 left: NB = 2): the low half's at lo, the high half's
+        // at lo+NB (if any window is left there).  Its text planes: the low half's
+        // positions 0..NB+2 of word j are its own, the high half's positions
+        // NB..2NB+2 are the low half's.
+        auto short_iteration = [&](auto nb, int j, const uint32_t (&Tc)[2 * kCols], bool activeB) {
+            constexpr int NB = decltype(nb)::value, C = NB + 3;
+            const int lo = kHalf * j;
+            const int i0 = lo + NB * half;
+            uint32_t tl[C], th[C];
+#pragma unroll
+            for (int t = 0; t < C; t++) {
+                tl[t] = __builtin_amdgcn_permlane32_swap(Tc[2 * t], Tc[2 * t + 2 * NB], false, false)[0];
+                th[t] = __builtin_amdgcn_permlane32_swap(Tc[2 * t + 1], Tc[2 * t + 1 + 2 * NB], false, false)[0];
+            }
+            uint32_t *nvs = nv + NB * half * kPairLanes + pl;
+            uint32_t *nvps = nvp + NB * half * kPairLanes + pl;
+            Winner<NB> W;
+            if constexpr (TWO) {
+                if (read_uniform) {
+                    fill_range(i0, C, lbv, nvs);
+                    block_winners<NB, TWO, true, true>(W, ring, nvs, nvps, pl, i0, i0 % R, Ee, R, lo, lo + NB + C - 1,
+                                                       m_min, tl, th, rmax);
+                } else {
+                    fill_masks2(i0, nvs, nvps, C);
+                    block_winners<NB, TWO, true, false>(W, ring, nvs, nvps, pl, i0, i0 % R, Ee, R, lo, lo + NB + C - 1,
+                                                        m_min, tl, th);
+                }
+            } else if (UNI) {
+                block_winners<NB, false, true, true>(W, ring, nvs, nvps, pl, i0, i0 % R, Ee, R, lo, lo + NB + C - 1,
+                                                     m_min, tl, th, m_max);
+            } else {
+                fill_masks(i0, nvs, C + Ee);
+                block_winners<NB, false, true, false>(W, ring, nvs, nvps, pl, i0, i0 % R, Ee, R, lo, lo + NB + C - 1,
+                                                      m_min, tl, th);
+            }
+            uint32_t o[NB];
+            if (half == 0) block_fsm<NB>(F, W, o);
+            F.s0 = from_half0(F.s0); F.s1 = from_half0(F.s1); F.s2 = from_half0(F.s2);
+            if (half == 1 && activeB) block_fsm<NB>(F, W, o);
+            if (half == 0 || activeB) block_count<NB, TWO>(F, o, X, lo + NB * half, ebits);
+        };
+        const int rem = m_max - kHalf * (niter - 1);        // windows of the last iteration
+        const bool short_last = niter > 0 && rem <= kBlock;
+        const int nlong = niter - (short_last ? 1 : 0);
+        int j = 0;
+        for (; j + 1 < nlong; j += 2) {
+            iteration(j, TA, TB);
+            iteration(j + 1, TB, TA);
         }
-        const int64_t o = J.perm ? J.perm[p] : p;
-        J.out_accept[o] = acc;
-        if (J.out_popcount) J.out_popcount[o] = pc;
+        if (j < nlong) iteration(j, TA, TB);
+        if (short_last) {
+            uint32_t Tl[2 * kCols];
+#pragma unroll
+            for (int t = 0; t < 2 * kCols; t++) Tl[t] = (nlong & 1) ? TB[t] : TA[t];
+            if (rem > 4)
+                short_iteration(std::integral_constant<int, 4>(), nlong, Tl, true);
+            else
+                short_iteration(std::integral_constant<int, 2>(), nlong, Tl, rem > 2);
+        }
+        // windows whose final S bit went into the counter
+        const int nwin = !short_last ? kHalf * niter
+                                     : kHalf * nlong + (rem > 4 ? kBlock : (rem > 2 ? kBlock / 2 : kBlock / 4));
+
+        // ---- add the two halves' ones counters (each half then holds the
+        // total), then each half writes 16 of the 32 pairs of its lanes
+        // the same register of the other lane half (one lane swap, no LDS)
+        auto other_half = [half](uint32_t v) {
+            const auto sw = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+            return half ? (uint32_t)sw[0] : (uint32_t)sw[1];
+        };
+        uint32_t cnt[32];
+        cnt[0] = F.ones; cnt[1] = F.twos; cnt[2] = F.fours;
+#pragma unroll
+        for (int b = 0; b < 8; b++) cnt[3 + b] = F.e[b];
+        {
+            uint32_t cy = 0u;
+#pragma unroll
+            for (int b = 0; b < 11; b++) {
+                const uint32_t o = other_half(cnt[b]);
+                const uint32_t s_ = gate<kTTXor3>(cnt[b], o, cy);
+                cy = gate<kTTMaj>(cnt[b], o, cy);
+                cnt[b] = s_;
+            }
+        }
+        // TWO: the zeros' first and last positions over both halves' blocks
+        uint32_t pos[TWO ? 32 : 1];
+        if constexpr (TWO) {
+            uint32_t fh[kLenBits], lh[kLenBits];
+            const uint32_t seen_h = other_half(X.seen);
+#pragma unroll
+            for (int b = 0; b < kLenBits; b++) { fh[b] = other_half(X.first[b]); lh[b] = other_half(X.last[b]); }
+            // fh < first and last < lh: borrow chains from the low bit
+            uint32_t flt = gate<kTTAndNotA>(fh[0], X.first[0], X.first[0]);
+            uint32_t lgt = gate<kTTAndNotA>(X.last[0], lh[0], lh[0]);
+#pragma unroll
+            for (int b = 1; b < kLenBits; b++) {
+                flt = gate<kTTMajNotA>(fh[b], X.first[b], flt);
+                lgt = gate<kTTMajNotA>(X.last[b], lh[b], lgt);
+            }
+            // take the other half's position if it has a zero and this one has
+            // none or a later first (earlier last) zero
+            const uint32_t tf = seen_h & (~X.seen | flt);
+            const uint32_t tl_ = seen_h & (~X.seen | lgt);
+#pragma unroll
+            for (int b = 0; b < 32; b++) pos[b] = 0u;
+#pragma unroll
+            for (int b = 0; b < kLenBits; b++) {
+                pos[b] = mux(tf, fh[b], X.first[b]);
+                pos[16 + b] = mux(tl_, lh[b], X.last[b]);
+            }
+            X.seen |= seen_h;
+        }
+        // rows 16.. carry each pair's length (unless all valid pairs have
+        // length m_max) and valid bit through the transpose
+#pragma unroll
+        for (int b = 11; b < 32; b++)
+            cnt[b] = (b >= 16 && b < 16 + nlb && !UNI) ? lbv[(b - 16) * kPairLanes] : 0u;
+        cnt[16 + kLenBits] = valid;
+        if constexpr (TWO) {
+            cnt[17 + kLenBits] = X.seen;
+            transpose32(pos);  // pos[k]: first zero | last zero << 16
+        }
+        transpose32(cnt);  // cnt[k]: ones of S over windows [0, nwin) | length << 16 | valid << 27 (| seen << 28)
+        // both halves hold the same rows: the low half writes pairs k < 16, the
+        // high half pairs k >= 16 (a lane swap brings row 16+k to register k)
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            cnt[k] = __builtin_amdgcn_permlane32_swap(cnt[k], cnt[16 + k], false, false)[0];
+            if constexpr (TWO) pos[k] = __builtin_amdgcn_permlane32_swap(pos[k], pos[16 + k], false, false)[0];
+        }
+        // the pair-count bound again, opaque to the compiler here, so that the
+        // stores' range checks are not computed (and kept live) before the loop
+        int left_out = __builtin_amdgcn_readfirstlane(left);
+        asm volatile("" : "+s"(left_out));
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            const int kk = k + 16 * half;
+            const int64_t p = base + (int64_t)kk * kPairLanes + pl;
+            if (!full && kk * kPairLanes + pl >= left_out) continue;
+            const uint32_t w = cnt[k];
+            const int m = UNI ? m_max : (int)((w >> 16) & ((1u << kLenBits) - 1));
+            uint8_t acc;
+            int16_t pc;
+            if (!((w >> (16 + kLenBits)) & 1u)) {
+                acc = 0xFF;
+                pc = -1;
+            } else {
+                // S stays 1 on [m, nwin): those ones are not part of the pair
+                int ones = (int)(w & 0xFFFFu) - (nwin - m);
+                if constexpr (TWO) {
+                    if ((w >> (17 + kLenBits)) & 1u) {
+                        // ones before the first zero, after the last zero
+                        const int first = (int)(pos[k] & ((1u << kLenBits) - 1));
+                        const int last = (int)((pos[k] >> 16) & ((1u << kLenBits) - 1));
+                        if (J.mode == 1 || J.mode == 2) ones -= first;
+                        if (J.mode == 1 || J.mode == 3) ones -= m - 1 - last;
+                    }
+                }
+                const int E = J.Edec ? J.Edec[p] : J.E;
+                acc = ones <= E ? 1 : 0;
+                pc = (int16_t)ones;
+            }
+            const int64_t o = J.perm ? J.perm[p] : p;
+            J.out_accept[o] = acc;
+            if (J.out_popcount) J.out_popcount[o] = pc;
+        }
+
+    };
+    if constexpr (TWO) {
+        rest(std::false_type());
+    } else if constexpr (RO) {
+        rest(std::true_type());
+    } else {
+        if (uniform)
+            rest(std::true_type());
+        else
+            rest(std::false_type());
     }
 }
 
