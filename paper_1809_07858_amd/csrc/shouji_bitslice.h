@@ -82,6 +82,20 @@ __device__ __forceinline__ void transpose32(uint32_t (&a)[32]) {
 #undef SHOUJI_TSTAGE
 }
 
+// Parity of this wavefront's slot on its SIMD (field WAVE_ID of the HW_ID
+// hardware register).  Two wavefronts that share a SIMD from the start of a
+// launch sit in consecutive slots.
+__device__ __forceinline__ int wave_slot_parity() {
+    return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 4) & 1;   // hwreg(HW_ID, offset 0, 4 bits)
+}
+// Issue priority of this wavefront, 1 or 0 (s_setprio takes an immediate).
+__device__ __forceinline__ void wave_priority(int hi) {
+    if (hi)
+        __builtin_amdgcn_s_setprio(1);
+    else
+        __builtin_amdgcn_s_setprio(0);
+}
+
 // Wave-wide maximum / minimum (all 64 lanes active), returned uniform: DPP
 // lane swaps within each row of 16 lanes (quad permutes, then the half-row
 // and row mirrors), then the four rows' values read into scalar registers.

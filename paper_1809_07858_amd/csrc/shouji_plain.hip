@@ -844,8 +844,15 @@ __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, i
         const bool short_last = niter > 0 && rem <= kBlock;
         const int nlong = niter - (short_last ? 1 : 0);
         int j = 0;
+        // The two wavefronts of a SIMD take issue priority in turn, one
+        // iteration each (by slot parity).  At equal priority the SIMD
+        // favours the older one, which then ends about an iteration ahead and
+        // leaves the other to finish alone at a lower issue rate.
+        const int par = wave_slot_parity();
         for (; j + 1 < nlong; j += 2) {
+            wave_priority(par);
             iteration(j, TA, TB);
+            wave_priority(par ^ 1);
             iteration(j + 1, TB, TA);
         }
         if (j < nlong) iteration(j, TA, TB);
@@ -1282,8 +1289,12 @@ __device__ __forceinline__ void filter_group4(const GroupJob &J, uint32_t *lds, 
         }
     };
     int j = 0;
+    // issue priority in turn, as in the layout above
+    const int par = wave_slot_parity();
     for (; j + 1 < niter; j += 2) {
+        wave_priority(par);
         iteration(j, TA, TB);
+        wave_priority(par ^ 1);
         iteration(j + 1, TB, TA);
     }
     if (j < niter) iteration(j, TA, TB);
