@@ -194,6 +194,52 @@ __device__ __forceinline__ void candidate(Winner<NB> &W, const uint2 (&pv)[NB + 
     }
 }
 
+// Issue pacing of the two wavefronts that share a SIMD, for the quarter
+// layout's long iterations.  At equal priority the SIMD favours the older
+// one, which then finishes its window loop ahead and leaves the other to run
+// alone at a lower issue rate.  Each posts the index of the iteration it
+// starts in a table held per SIMD (hardware ids XCC_ID and HW_ID: SE, SH, CU,
+// SIMD) and slot parity and reads the other's post one iteration later; the
+// one behind takes priority, the one ahead gives it up, level ones take
+// turns by iteration and slot parity.  Only scheduling reads the table: a
+// stale post, or one from another kernel on the same SIMD, changes the
+// speed, never a result.  (The two-half layout takes turns only: with its
+// shorter iterations the post and its read cost more than they balance,
+// E = 2 taking 15% longer.)
+__device__ uint32_t g_simd_pace[8 * 8 * 2 * 16 * 4 * 2];
+
+struct SimdPace {
+    uint32_t *mine, *other;
+    int par;
+    uint32_t seen;  // the other's post, loaded at the previous step
+    __device__ __forceinline__ void begin() {
+        const unsigned hw = __builtin_amdgcn_s_getreg((31 << 11) | 4);          // HW_ID, all 32 bits
+        const unsigned xcc = __builtin_amdgcn_s_getreg((3 << 11) | 20) & 7u;    // XCC_ID
+        const unsigned simd = (hw >> 4) & 3u, cu = (hw >> 8) & 15u, sh = (hw >> 12) & 1u, se = (hw >> 13) & 7u;
+        const unsigned slot = (((xcc * 8u + se) * 2u + sh) * 16u + cu) * 4u + simd;
+        par = (int)(hw & 1u);   // WAVE_ID bit 0: two wavefronts that share a SIMD from the start sit in slots 0 and 1
+        mine = g_simd_pace + 2 * slot + par;
+        other = g_simd_pace + 2 * slot + (par ^ 1);
+        __hip_atomic_store(mine, 0xFFFFFFFFu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);   // not in the loop yet
+    }
+    // before iteration j of the window loop
+    __device__ __forceinline__ void step(int j) {
+        if (j == 0) {
+            wave_priority(par);
+        } else {
+            const int o = (int)__builtin_amdgcn_readfirstlane(seen);   // the other's iteration one step ago
+            if (o > j - 1)
+                wave_priority(1);
+            else if (o < j - 1)
+                wave_priority(0);
+            else
+                wave_priority((j & 1) ^ par);
+        }
+        __hip_atomic_store(mine, (uint32_t)j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        seen = __hip_atomic_load(other, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+};
+
 struct FsmState {
     uint32_t s0, s1, s2;                 // S[i], S[i+1], S[i+2] before window i
     uint32_t ones, twos, fours, e[8];    // carry-save ones counter of final S bits
@@ -1013,6 +1059,8 @@ constexpr int kQWin = 4 * kBlock;                   // windows per iteration
 
 template <bool RO>
 __device__ __forceinline__ void filter_group4(const GroupJob &J, uint32_t *lds, int R, int h, int lane) {
+    SimdPace pace;
+    pace.begin();
     const int g = lane >> 4;
     const int q = g == 0 ? 0 : (g == 1 ? 1 : (g == 3 ? 2 : 3));   // block of the iteration
     const int pl = lane & (kQLanes - 1);
@@ -1289,12 +1337,10 @@ __device__ __forceinline__ void filter_group4(const GroupJob &J, uint32_t *lds, 
         }
     };
     int j = 0;
-    // issue priority in turn, as in the layout above
-    const int par = wave_slot_parity();
     for (; j + 1 < niter; j += 2) {
-        wave_priority(par);
+        pace.step(j);
         iteration(j, TA, TB);
-        wave_priority(par ^ 1);
+        pace.step(j + 1);
         iteration(j + 1, TB, TA);
     }
     if (j < niter) iteration(j, TA, TB);
