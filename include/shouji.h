@@ -83,6 +83,10 @@ typedef enum {
  *   max_len       0..SHOUJI_MAX_LEN, the longest length in the batch.
  *   ld            leading dimension in words, >= n_pairs.
  *   stream        hipStream_t or NULL.
+ * Nothing is allocated.  Above E = 13 with lengths (E = 22 without) the
+ * kernel's wavefronts also post their progress in a 64 KB library-owned
+ * device table per GPU, read only to set issue priority: calls that overlap
+ * share it without any effect on their results.
  */
 int shouji_filter(const uint32_t *reads, const uint32_t *refs, const int32_t *lengths,
                   int32_t E, uint8_t *out_accept, int16_t *out_popcount,

@@ -272,6 +272,36 @@ def test_one_length_below_max_len(sj, E):
         _check(sj, p, E, max_len)
 
 
+def test_concurrent_launches_share_the_pacing_table(sj):
+    # launches on three streams at once, two in the quarter layout (whose
+    # wavefronts post their progress in a table per SIMD and read their SIMD
+    # neighbour's) and one in the two-half layout: the posts only steer issue
+    # priority, so every output still equals the oracle's
+    dev = torch.device("cuda:0")
+    cases = [(syninput.generate(30_000, 250, E=20, seed=8100, p_repeat=0.3), 20, 250),
+             (syninput.generate(30_000, 180, 250, E=25, seed=8101), 25, 250),
+             (syninput.generate(30_000, 100, E=5, seed=8102), 5, 100)]
+    prepared = []
+    for p, E, max_len in cases:
+        reads = torch.from_numpy(sj.pack_words(p.P, max_len)).to(dev)
+        refs = torch.from_numpy(sj.pack_words(p.T, max_len)).to(dev)
+        lens = torch.from_numpy(np.ascontiguousarray(p.lengths, dtype=np.int32)).to(dev)
+        ea, ep = oracle.shouji_batch(p.P, p.T, p.lengths, E=E)
+        prepared.append((reads, refs, lens, E, max_len, p.n, ea, ep))
+    streams = [torch.cuda.Stream() for _ in cases]
+    torch.cuda.synchronize()
+    for rep in range(3):
+        print("concurrent rep %d" % rep, flush=True)
+        outs = []
+        for st, (reads, refs, lens, E, max_len, n, _, _) in zip(streams, prepared):
+            with torch.cuda.stream(st):
+                outs.append(sj.shouji_filter(reads, refs, lens, E, n_pairs=n, max_len=max_len, stream=st))
+        torch.cuda.synchronize()
+        for (a, c), (_, _, _, E, _, _, ea, ep) in zip(outs, prepared):
+            assert np.array_equal(a.cpu().numpy(), ea), "accept, E=%d rep %d" % (E, rep)
+            assert np.array_equal(c.cpu().numpy(), ep), "popcount, E=%d rep %d" % (E, rep)
+
+
 @pytest.mark.parametrize("seed", range(24))
 def test_random_shapes(sj, seed):
     # random batch sizes, maximum lengths and thresholds, with four length
