@@ -125,11 +125,14 @@ def test_max_len_1024(sj):
     _check(sj, p, 10, 1024)
 
 
-def test_invalid_lengths_get_sentinels(sj):
-    p = syninput.generate(3_000, 100, E=2, seed=3)
+@pytest.mark.parametrize("E", [2, 20])
+def test_invalid_lengths_get_sentinels(sj, E):
+    # the valid pairs all have max_len bases: each group takes the one-length
+    # path while its invalid pairs get the sentinels (E = 20: quarter layout)
+    p = syninput.generate(3_000, 100, E=E, seed=3)
     p.lengths[::7] = 101
     p.lengths[3::11] = -5
-    _check(sj, p, 2, 100)
+    _check(sj, p, E, 100)
 
 
 def test_identical_pairs(sj):
