@@ -93,12 +93,16 @@ def strip_comments(src):
 
 
 def kernel_source_hash():
-    """Hash of the plain kernel's code (comments and layout excluded), which
-    ties a committed counter summary to the code it was taken on."""
+    """Hash of the plain kernel's code (comments and layout excluded) and of
+    the compiler flags it is built with (paths left out), which ties a
+    committed counter summary to the code it was taken on."""
+    from paper_1809_07858_amd import build as hipbuild
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
         with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
             h.update(strip_comments(f.read()).encode())
+    flags = hipbuild.FLAGS + hipbuild.EXTRA.get("csrc/shouji_plain.hip", [])
+    h.update(" ".join(f for f in flags if not os.path.isabs(f)).encode())
     return h.hexdigest()[:16]
 
 
