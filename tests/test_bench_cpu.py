@@ -41,6 +41,25 @@ def test_source_hash_ignores_comments_and_layout():
     assert len(h) == 16 and h == bench.kernel_source_hash()
 
 
+def test_source_hash_covers_the_plain_kernels_compile_flags(monkeypatch):
+    # counters taken on one build of the kernel do not vouch for another one
+    # compiled with other flags; include paths (machine-specific) are left out
+    from paper_1809_07858_amd import build as hipbuild
+    for src in hipbuild.EXTRA:
+        assert src in hipbuild.SOURCES
+    h = bench.kernel_source_hash()
+    original = dict(hipbuild.EXTRA)
+    # the same code built somewhere else: same hash
+    flags = [f if not os.path.isabs(f) else "/elsewhere/include" for f in hipbuild.FLAGS]
+    monkeypatch.setattr(hipbuild, "FLAGS", flags)
+    assert bench.kernel_source_hash() == h
+    # other flags for the plain kernels' source: another hash
+    extra = dict(original)
+    extra["csrc/shouji_plain.hip"] = []
+    monkeypatch.setattr(hipbuild, "EXTRA", extra)
+    assert bench.kernel_source_hash() != h
+
+
 def test_committed_traffic_matches_its_summary():
     # reported only for the source the counters were taken on, and then
     # exactly the summary's figure
