@@ -457,6 +457,10 @@ __device__ __forceinline__ uint32_t from_half1(uint32_t v) {
 // left out of the count (Sec. 2.2.3).
 template <bool TWO, bool RO = false>
 __device__ __forceinline__ void filter_group(const GroupJob &J, uint32_t *lds, int R, int lane) {
+    // The younger of the two wavefronts on a SIMD (odd slot) takes issue
+    // priority through the prologue, so that both reach the window loop at
+    // about the same time (the older one's loads were issued first).
+    wave_priority(wave_slot_parity());
     const int half = lane >> 5;
     const int pl = lane & (kPairLanes - 1);
     const int Ee = J.Ee;
