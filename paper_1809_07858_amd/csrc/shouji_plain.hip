@@ -1144,266 +1144,279 @@ __device__ __forceinline__ void filter_group4(const GroupJob &J, uint32_t *lds, 
         for (int b = 0; b < kLenBits; b++) lbv[b * kQLanes] = lenw[b];
     }
 
-    FsmState F;
-    F.s0 = F.s1 = F.s2 = ~0u;
-    F.ones = F.twos = F.fours = 0u;
+    // The rest is compiled twice, as in filter_group: UNI when every valid
+    // pair of the group has one length.
+    auto rest = [&](auto uni_tag) __attribute__((always_inline)) {
+        constexpr bool UNI = decltype(uni_tag)::value;
+        FsmState F;
+        F.s0 = F.s1 = F.s2 = ~0u;
+        F.ones = F.twos = F.fours = 0u;
 #pragma unroll
-    for (int b = 0; b < 8; b++) F.e[b] = 0u;
-    Ends X;   // unused (global counting)
+        for (int b = 0; b < 8; b++) F.e[b] = 0u;
+        Ends X;   // unused (global counting)
 
-    const int niter = (m_max + kQWin - 1) / kQWin;
-    const int ebits = 32 - __builtin_clz((unsigned)niter | 1u);   // bits of niter (one block per group and iteration)
-    const int nhalves = (m_max + kHalf - 1) / kHalf;   // words holding positions < m_max
+        const int niter = (m_max + kQWin - 1) / kQWin;
+        const int ebits = 32 - __builtin_clz((unsigned)niter | 1u);   // bits of niter (one block per group and iteration)
+        const int nhalves = (m_max + kHalf - 1) / kHalf;   // words holding positions < m_max
 
-    // masks "position x is past the pair's end" for positions x0 .. x0+count-1
-    // (as in filter_group; groups of mixed lengths only, a group of one
-    // length takes its masks from the positions)
-    auto fill_masks = [&](int i0, uint32_t *dst, int count) {
-        int x0 = i0;
-        asm volatile("" : "+v"(x0));
-        uint32_t lb[kLenBits];
+        // masks "position x is past the pair's end" for positions x0 .. x0+count-1
+        // (as in filter_group; groups of mixed lengths only, a group of one
+        // length takes its masks from the positions)
+        auto fill_masks = [&](int i0, uint32_t *dst, int count) {
+            int x0 = i0;
+            asm volatile("" : "+v"(x0));
+            uint32_t lb[kLenBits];
 #pragma unroll
-        for (int b = 0; b < kLenBits; b++) lb[b] = lbv[b * kQLanes];
-        uint32_t msk = ~0u;
-        for (int s = 0; s < count; s++) {
-            const int x = x0 + s;
-            if (s == 0) {
-                uint32_t gt = 0u;  // gt = (length > x)
+            for (int b = 0; b < kLenBits; b++) lb[b] = lbv[b * kQLanes];
+            uint32_t msk = ~0u;
+            for (int s = 0; s < count; s++) {
+                const int x = x0 + s;
+                if (s == 0) {
+                    uint32_t gt = 0u;  // gt = (length > x)
 #pragma unroll
-                for (int b = 0; b < kLenBits; b++) {
-                    const uint32_t sx = ((x >> b) & 1) ? ~0u : 0u;
-                    gt = mux(sx, lb[b] & gt, lb[b] | gt);
-                }
-                msk = ~gt;
-            } else {
-                uint32_t e = ~0u;  // e = (length == x)
-#pragma unroll
-                for (int b = 0; b < kLenBits; b++) {
-                    const uint32_t sx = ((x >> b) & 1) ? ~0u : 0u;
-                    e = gate<kTTAndXnor>(e, lb[b], sx);
-                }
-                msk |= e;
-            }
-            dst[s * kQLanes] = msk;
-        }
-    };
-
-    // One pass: load (word indices clamped into [0, limit); a word outside it
-    // is loaded from a valid index, its planes lie beyond every pair's length
-    // or are never used), then transpose and write the pattern words.
-    auto pass_load = [&](int k, uint32_t (&raw)[32]) {
-        const int w = g == 0 ? 2 * k : (g == 3 ? 2 * k + 1 : (g == 1 ? 2 * k + h : 2 * k + h + 1));
-        const int wc = min(max(w, 0), nhalves - 1);
-        load_word<kQLanes>(seq + (int64_t)wc * J.ld + base, full, left, pl, raw);
-    };
-    auto pass_finish = [&](int k, uint32_t (&raw)[32]) {
-        transpose32(raw);
-        if (!text_group) {
-            const int pw = g == 1 ? 2 * k + h : 2 * k + h + 1;
-            if (pw >= 0 && pw < nhalves) {
-                if ((R & 7) != 0) {
-                    int slot = (pw * kHalf) % R;
-#pragma unroll
-                    for (int u = 0; u < kHalf; u++) {
-                        const uint2 v = make_uint2(raw[2 * u], raw[2 * u + 1]);
-                        ring[slot * kQLanes + pl] = v;
-                        if (slot < kMirror) ring[(slot + R) * kQLanes + pl] = v;
-                        slot = slot + 1 == R ? 0 : slot + 1;
+                    for (int b = 0; b < kLenBits; b++) {
+                        const uint32_t sx = ((x >> b) & 1) ? ~0u : 0u;
+                        gt = mux(sx, lb[b] & gt, lb[b] | gt);
                     }
+                    msk = ~gt;
                 } else {
+                    uint32_t e = ~0u;  // e = (length == x)
 #pragma unroll
-                    for (int hh = 0; hh < 2; hh++) {
-                        const int s0 = (pw * kHalf + 8 * hh) % R;
-                        uint2 *dst = ring + s0 * kQLanes + pl;
+                    for (int b = 0; b < kLenBits; b++) {
+                        const uint32_t sx = ((x >> b) & 1) ? ~0u : 0u;
+                        e = gate<kTTAndXnor>(e, lb[b], sx);
+                    }
+                    msk |= e;
+                }
+                dst[s * kQLanes] = msk;
+            }
+        };
+
+        // One pass: load (word indices clamped into [0, limit); a word outside it
+        // is loaded from a valid index, its planes lie beyond every pair's length
+        // or are never used), then transpose and write the pattern words.
+        auto pass_load = [&](int k, uint32_t (&raw)[32]) {
+            const int w = g == 0 ? 2 * k : (g == 3 ? 2 * k + 1 : (g == 1 ? 2 * k + h : 2 * k + h + 1));
+            const int wc = min(max(w, 0), nhalves - 1);
+            load_word<kQLanes>(seq + (int64_t)wc * J.ld + base, full, left, pl, raw);
+        };
+        auto pass_finish = [&](int k, uint32_t (&raw)[32]) {
+            transpose32(raw);
+            if (!text_group) {
+                const int pw = g == 1 ? 2 * k + h : 2 * k + h + 1;
+                if (pw >= 0 && pw < nhalves) {
+                    if ((R & 7) != 0) {
+                        int slot = (pw * kHalf) % R;
 #pragma unroll
-                        for (int u = 0; u < 8; u++)
-                            dst[u * kQLanes] = make_uint2(raw[2 * (8 * hh + u)], raw[2 * (8 * hh + u) + 1]);
-                        if (s0 < kMirror) {
+                        for (int u = 0; u < kHalf; u++) {
+                            const uint2 v = make_uint2(raw[2 * u], raw[2 * u + 1]);
+                            ring[slot * kQLanes + pl] = v;
+                            if (slot < kMirror) ring[(slot + R) * kQLanes + pl] = v;
+                            slot = slot + 1 == R ? 0 : slot + 1;
+                        }
+                    } else {
+#pragma unroll
+                        for (int hh = 0; hh < 2; hh++) {
+                            const int s0 = (pw * kHalf + 8 * hh) % R;
+                            uint2 *dst = ring + s0 * kQLanes + pl;
 #pragma unroll
                             for (int u = 0; u < 8; u++)
-                                if (s0 + u < kMirror)
-                                    dst[(R + u) * kQLanes] =
-                                        make_uint2(raw[2 * (8 * hh + u)], raw[2 * (8 * hh + u) + 1]);
+                                dst[u * kQLanes] = make_uint2(raw[2 * (8 * hh + u)], raw[2 * (8 * hh + u) + 1]);
+                            if (s0 < kMirror) {
+#pragma unroll
+                                for (int u = 0; u < 8; u++)
+                                    if (s0 + u < kMirror)
+                                        dst[(R + u) * kQLanes] =
+                                            make_uint2(raw[2 * (8 * hh + u)], raw[2 * (8 * hh + u) + 1]);
+                            }
                         }
                     }
                 }
             }
-        }
-    };
-    // Text planes of an iteration's block (11 positions, low and high plane):
-    // start_text from pass k (all but group 2's positions 8..10), finish_text
-    // from pass k+1 (group 2's positions 8..10 = word 2k+2's 0..2, from group 0).
-    auto start_text = [&](uint32_t (&T)[2 * kCols], const uint32_t (&raw)[32]) {
+        };
+        // Text planes of an iteration's block (11 positions, low and high plane):
+        // start_text from pass k (all but group 2's positions 8..10), finish_text
+        // from pass k+1 (group 2's positions 8..10 = word 2k+2's 0..2, from group 0).
+        auto start_text = [&](uint32_t (&T)[2 * kCols], const uint32_t (&raw)[32]) {
 #pragma unroll
-        for (int t = 0; t < 2 * kBlock; t++) {
-            // groups 1 / 2: positions 8..15 of group 0's / group 3's word
-            const auto sw = __builtin_amdgcn_permlane16_swap(raw[2 * kBlock + t], raw[2 * kBlock + t], false, false);
-            T[t] = text_group ? raw[t] : (g == 1 ? (uint32_t)sw[0] : (uint32_t)sw[1]);
-        }
+            for (int t = 0; t < 2 * kBlock; t++) {
+                // groups 1 / 2: positions 8..15 of group 0's / group 3's word
+                const auto sw = __builtin_amdgcn_permlane16_swap(raw[2 * kBlock + t], raw[2 * kBlock + t], false, false);
+                T[t] = text_group ? raw[t] : (g == 1 ? (uint32_t)sw[0] : (uint32_t)sw[1]);
+            }
 #pragma unroll
-        for (int t = 2 * kBlock; t < 2 * kCols; t++) {
-            // group 1: positions 0..2 of group 3's word
-            const auto sw = __builtin_amdgcn_permlane32_swap(raw[t - 2 * kBlock], raw[t - 2 * kBlock], false, false);
-            T[t] = text_group ? raw[t] : (uint32_t)sw[1];
-        }
-    };
-    auto finish_text = [&](uint32_t (&T)[2 * kCols], const uint32_t (&raw)[32]) {
+            for (int t = 2 * kBlock; t < 2 * kCols; t++) {
+                // group 1: positions 0..2 of group 3's word
+                const auto sw = __builtin_amdgcn_permlane32_swap(raw[t - 2 * kBlock], raw[t - 2 * kBlock], false, false);
+                T[t] = text_group ? raw[t] : (uint32_t)sw[1];
+            }
+        };
+        auto finish_text = [&](uint32_t (&T)[2 * kCols], const uint32_t (&raw)[32]) {
 #pragma unroll
-        for (int t = 2 * kBlock; t < 2 * kCols; t++) {
-            // group 2: positions 0..2 of group 0's word (the next text word)
-            const auto sw = __builtin_amdgcn_permlane32_swap(raw[t - 2 * kBlock], raw[t - 2 * kBlock], false, false);
-            T[t] = g == 2 ? (uint32_t)sw[0] : T[t];
-        }
-    };
+            for (int t = 2 * kBlock; t < 2 * kCols; t++) {
+                // group 2: positions 0..2 of group 0's word (the next text word)
+                const auto sw = __builtin_amdgcn_permlane32_swap(raw[t - 2 * kBlock], raw[t - 2 * kBlock], false, false);
+                T[t] = g == 2 ? (uint32_t)sw[0] : T[t];
+            }
+        };
 
-    uint32_t TA[2 * kCols], TB[2 * kCols];
-    if (niter > 0) {
-        // pattern-only passes for words 0 .. h-1 (h > 0 only for E >= 30)
-        for (int k = -((h + 1) / 2); k < 0; k++) {
+        uint32_t TA[2 * kCols], TB[2 * kCols];
+        if (niter > 0) {
+            // pattern-only passes for words 0 .. h-1 (h > 0 only for E >= 30)
+            for (int k = -((h + 1) / 2); k < 0; k++) {
+                uint32_t raw[32];
+                pass_load(k, raw);
+                pass_finish(k, raw);
+            }
             uint32_t raw[32];
-            pass_load(k, raw);
-            pass_finish(k, raw);
+            pass_load(0, raw);
+            pass_finish(0, raw);
+            start_text(TA, raw);
+            pass_load(1, raw);
+            pass_finish(1, raw);
+            finish_text(TA, raw);
+            start_text(TB, raw);
         }
-        uint32_t raw[32];
-        pass_load(0, raw);
-        pass_finish(0, raw);
-        start_text(TA, raw);
-        pass_load(1, raw);
-        pass_finish(1, raw);
-        finish_text(TA, raw);
-        start_text(TB, raw);
-    }
 
-    auto iteration = [&](int j, uint32_t (&Tc)[2 * kCols], uint32_t (&Tn)[2 * kCols]) {
-        const int lo = kQWin * j;
-        const int i0 = lo + kBlock * q;
-        const int hi_col = lo + 3 * kBlock + kCols - 1;   // last text column of the iteration
-        Winner<kBlock> W;
-        {
-            uint32_t tl[kCols], th[kCols];
+        auto iteration = [&](int j, uint32_t (&Tc)[2 * kCols], uint32_t (&Tn)[2 * kCols]) {
+            const int lo = kQWin * j;
+            const int i0 = lo + kBlock * q;
+            const int hi_col = lo + 3 * kBlock + kCols - 1;   // last text column of the iteration
+            Winner<kBlock> W;
+            {
+                uint32_t tl[kCols], th[kCols];
 #pragma unroll
-            for (int t = 0; t < kCols; t++) { tl[t] = Tc[2 * t]; th[t] = Tc[2 * t + 1]; }
-            const int sb = i0 % R;
-            if ((Ee > lo) || (hi_col + Ee >= m_min)) {
-                if (RO || uniform) {
-                    block_winners<kBlock, false, true, true, kQLanes>(W, ring, nvg, nvg, pl, i0, sb, Ee, R, lo,
-                                                                      hi_col, m_min, tl, th, m_max);
+                for (int t = 0; t < kCols; t++) { tl[t] = Tc[2 * t]; th[t] = Tc[2 * t + 1]; }
+                const int sb = i0 % R;
+                if ((Ee > lo) || (hi_col + Ee >= m_min)) {
+                    if (UNI) {
+                        block_winners<kBlock, false, true, true, kQLanes>(W, ring, nvg, nvg, pl, i0, sb, Ee, R, lo,
+                                                                          hi_col, m_min, tl, th, m_max);
+                    } else {
+                        fill_masks(i0, nvg, kCols + Ee);
+                        block_winners<kBlock, false, true, false, kQLanes>(W, ring, nvg, nvg, pl, i0, sb, Ee, R, lo,
+                                                                           hi_col, m_min, tl, th);
+                    }
                 } else {
-                    fill_masks(i0, nvg, kCols + Ee);
-                    block_winners<kBlock, false, true, false, kQLanes>(W, ring, nvg, nvg, pl, i0, sb, Ee, R, lo,
-                                                                       hi_col, m_min, tl, th);
+                    block_winners<kBlock, false, false, UNI, kQLanes>(W, ring, nvg, nvg, pl, i0, sb, Ee, R, lo, hi_col,
+                                                                     m_min, tl, th);
                 }
-            } else {
-                block_winners<kBlock, false, false, RO, kQLanes>(W, ring, nvg, nvg, pl, i0, sb, Ee, R, lo, hi_col,
-                                                                 m_min, tl, th);
+            }
+            // the next pass's loads before the serial update (their latency is
+            // covered by it)
+            const bool do_pass = j + 2 <= niter;
+            uint32_t raw[32];
+            if (do_pass) pass_load(j + 2, raw);
+            // serial update: blocks in the order of groups 0, 1, 3, 2
+            uint32_t o[kBlock];
+            if (g == 0) block_fsm<kBlock>(F, W, o);
+            {   // 0 -> 1
+                auto a = __builtin_amdgcn_permlane16_swap(F.s0, F.s0, false, false);
+                auto b = __builtin_amdgcn_permlane16_swap(F.s1, F.s1, false, false);
+                auto c = __builtin_amdgcn_permlane16_swap(F.s2, F.s2, false, false);
+                F.s0 = a[0]; F.s1 = b[0]; F.s2 = c[0];
+            }
+            if (g == 1) block_fsm<kBlock>(F, W, o);
+            {   // 1 -> 3
+                auto a = __builtin_amdgcn_permlane32_swap(F.s0, F.s0, false, false);
+                auto b = __builtin_amdgcn_permlane32_swap(F.s1, F.s1, false, false);
+                auto c = __builtin_amdgcn_permlane32_swap(F.s2, F.s2, false, false);
+                F.s0 = a[0]; F.s1 = b[0]; F.s2 = c[0];
+            }
+            if (g == 3) block_fsm<kBlock>(F, W, o);
+            {   // 3 -> 2
+                auto a = __builtin_amdgcn_permlane16_swap(F.s0, F.s0, false, false);
+                auto b = __builtin_amdgcn_permlane16_swap(F.s1, F.s1, false, false);
+                auto c = __builtin_amdgcn_permlane16_swap(F.s2, F.s2, false, false);
+                F.s0 = a[1]; F.s1 = b[1]; F.s2 = c[1];
+            }
+            if (g == 2) block_fsm<kBlock>(F, W, o);
+            {   // 2 -> 0
+                auto a = __builtin_amdgcn_permlane32_swap(F.s0, F.s0, false, false);
+                auto b = __builtin_amdgcn_permlane32_swap(F.s1, F.s1, false, false);
+                auto c = __builtin_amdgcn_permlane32_swap(F.s2, F.s2, false, false);
+                F.s0 = a[1]; F.s1 = b[1]; F.s2 = c[1];
+            }
+            block_count<kBlock, false>(F, o, X, i0, ebits);
+            if (do_pass) {
+                pass_finish(j + 2, raw);
+                finish_text(Tn, raw);
+                start_text(Tc, raw);
+            }
+        };
+        int j = 0;
+        for (; j + 1 < niter; j += 2) {
+            pace.step(j);
+            iteration(j, TA, TB);
+            pace.step(j + 1);
+            iteration(j + 1, TB, TA);
+        }
+        if (j < niter) iteration(j, TA, TB);
+        const int nwin = kQWin * niter;
+
+        // ---- sum the four groups' counters (each group then holds the total)
+        uint32_t cnt[32];
+        cnt[0] = F.ones; cnt[1] = F.twos; cnt[2] = F.fours;
+#pragma unroll
+        for (int b = 0; b < 8; b++) cnt[3 + b] = F.e[b];
+        {
+            uint32_t cy = 0u;
+#pragma unroll
+            for (int b = 0; b < 11; b++) {   // + the partner group in the same 32-lane half
+                const auto sw = __builtin_amdgcn_permlane16_swap(cnt[b], cnt[b], false, false);
+                const uint32_t o = (g & 1) ? (uint32_t)sw[0] : (uint32_t)sw[1];
+                const uint32_t s_ = gate<kTTXor3>(cnt[b], o, cy);
+                cy = gate<kTTMaj>(cnt[b], o, cy);
+                cnt[b] = s_;
+            }
+            cy = 0u;
+#pragma unroll
+            for (int b = 0; b < 11; b++) {   // + the other half
+                const auto sw = __builtin_amdgcn_permlane32_swap(cnt[b], cnt[b], false, false);
+                const uint32_t o = (g >= 2) ? (uint32_t)sw[0] : (uint32_t)sw[1];
+                const uint32_t s_ = gate<kTTXor3>(cnt[b], o, cy);
+                cy = gate<kTTMaj>(cnt[b], o, cy);
+                cnt[b] = s_;
             }
         }
-        // the next pass's loads before the serial update (their latency is
-        // covered by it)
-        const bool do_pass = j + 2 <= niter;
-        uint32_t raw[32];
-        if (do_pass) pass_load(j + 2, raw);
-        // serial update: blocks in the order of groups 0, 1, 3, 2
-        uint32_t o[kBlock];
-        if (g == 0) block_fsm<kBlock>(F, W, o);
-        {   // 0 -> 1
-            auto a = __builtin_amdgcn_permlane16_swap(F.s0, F.s0, false, false);
-            auto b = __builtin_amdgcn_permlane16_swap(F.s1, F.s1, false, false);
-            auto c = __builtin_amdgcn_permlane16_swap(F.s2, F.s2, false, false);
-            F.s0 = a[0]; F.s1 = b[0]; F.s2 = c[0];
-        }
-        if (g == 1) block_fsm<kBlock>(F, W, o);
-        {   // 1 -> 3
-            auto a = __builtin_amdgcn_permlane32_swap(F.s0, F.s0, false, false);
-            auto b = __builtin_amdgcn_permlane32_swap(F.s1, F.s1, false, false);
-            auto c = __builtin_amdgcn_permlane32_swap(F.s2, F.s2, false, false);
-            F.s0 = a[0]; F.s1 = b[0]; F.s2 = c[0];
-        }
-        if (g == 3) block_fsm<kBlock>(F, W, o);
-        {   // 3 -> 2
-            auto a = __builtin_amdgcn_permlane16_swap(F.s0, F.s0, false, false);
-            auto b = __builtin_amdgcn_permlane16_swap(F.s1, F.s1, false, false);
-            auto c = __builtin_amdgcn_permlane16_swap(F.s2, F.s2, false, false);
-            F.s0 = a[1]; F.s1 = b[1]; F.s2 = c[1];
-        }
-        if (g == 2) block_fsm<kBlock>(F, W, o);
-        {   // 2 -> 0
-            auto a = __builtin_amdgcn_permlane32_swap(F.s0, F.s0, false, false);
-            auto b = __builtin_amdgcn_permlane32_swap(F.s1, F.s1, false, false);
-            auto c = __builtin_amdgcn_permlane32_swap(F.s2, F.s2, false, false);
-            F.s0 = a[1]; F.s1 = b[1]; F.s2 = c[1];
-        }
-        block_count<kBlock, false>(F, o, X, i0, ebits);
-        if (do_pass) {
-            pass_finish(j + 2, raw);
-            finish_text(Tn, raw);
-            start_text(Tc, raw);
+#pragma unroll
+        for (int b = 11; b < 32; b++)
+            cnt[b] = (b >= 16 && b < 16 + kLenBits && !UNI) ? lbv[(b - 16) * kQLanes] : 0u;
+        cnt[16 + kLenBits] = valid;
+        transpose32(cnt);  // cnt[k]: ones of S over windows [0, nwin) | length << 16 | valid << 27
+        // group g writes pairs k = 8g .. 8g+7 of its lanes
+        int left_out = __builtin_amdgcn_readfirstlane(left);
+        asm volatile("" : "+s"(left_out));
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const uint32_t w = g == 0 ? cnt[i] : (g == 1 ? cnt[8 + i] : (g == 2 ? cnt[16 + i] : cnt[24 + i]));
+            const int kk = 8 * g + i;
+            const int64_t p = base + (int64_t)kk * kQLanes + pl;
+            if (!full && kk * kQLanes + pl >= left_out) continue;
+            const int m = UNI ? m_max : (int)((w >> 16) & ((1u << kLenBits) - 1));
+            uint8_t acc;
+            int16_t pc;
+            if (!((w >> (16 + kLenBits)) & 1u)) {
+                acc = 0xFF;
+                pc = -1;
+            } else {
+                const int ones = (int)(w & 0xFFFFu) - (nwin - m);   // S stays 1 on [m, nwin)
+                const int E = J.Edec ? J.Edec[p] : J.E;
+                acc = ones <= E ? 1 : 0;
+                pc = (int16_t)ones;
+            }
+            const int64_t o = J.perm ? J.perm[p] : p;
+            J.out_accept[o] = acc;
+            if (J.out_popcount) J.out_popcount[o] = pc;
         }
     };
-    int j = 0;
-    for (; j + 1 < niter; j += 2) {
-        pace.step(j);
-        iteration(j, TA, TB);
-        pace.step(j + 1);
-        iteration(j + 1, TB, TA);
-    }
-    if (j < niter) iteration(j, TA, TB);
-    const int nwin = kQWin * niter;
-
-    // ---- sum the four groups' counters (each group then holds the total)
-    uint32_t cnt[32];
-    cnt[0] = F.ones; cnt[1] = F.twos; cnt[2] = F.fours;
-#pragma unroll
-    for (int b = 0; b < 8; b++) cnt[3 + b] = F.e[b];
-    {
-        uint32_t cy = 0u;
-#pragma unroll
-        for (int b = 0; b < 11; b++) {   // + the partner group in the same 32-lane half
-            const auto sw = __builtin_amdgcn_permlane16_swap(cnt[b], cnt[b], false, false);
-            const uint32_t o = (g & 1) ? (uint32_t)sw[0] : (uint32_t)sw[1];
-            const uint32_t s_ = gate<kTTXor3>(cnt[b], o, cy);
-            cy = gate<kTTMaj>(cnt[b], o, cy);
-            cnt[b] = s_;
-        }
-        cy = 0u;
-#pragma unroll
-        for (int b = 0; b < 11; b++) {   // + the other half
-            const auto sw = __builtin_amdgcn_permlane32_swap(cnt[b], cnt[b], false, false);
-            const uint32_t o = (g >= 2) ? (uint32_t)sw[0] : (uint32_t)sw[1];
-            const uint32_t s_ = gate<kTTXor3>(cnt[b], o, cy);
-            cy = gate<kTTMaj>(cnt[b], o, cy);
-            cnt[b] = s_;
-        }
-    }
-#pragma unroll
-    for (int b = 11; b < 32; b++)
-        cnt[b] = (b >= 16 && b < 16 + kLenBits && !uniform) ? lbv[(b - 16) * kQLanes] : 0u;
-    cnt[16 + kLenBits] = valid;
-    transpose32(cnt);  // cnt[k]: ones of S over windows [0, nwin) | length << 16 | valid << 27
-    // group g writes pairs k = 8g .. 8g+7 of its lanes
-    int left_out = __builtin_amdgcn_readfirstlane(left);
-    asm volatile("" : "+s"(left_out));
-#pragma unroll
-    for (int i = 0; i < 8; i++) {
-        const uint32_t w = g == 0 ? cnt[i] : (g == 1 ? cnt[8 + i] : (g == 2 ? cnt[16 + i] : cnt[24 + i]));
-        const int kk = 8 * g + i;
-        const int64_t p = base + (int64_t)kk * kQLanes + pl;
-        if (!full && kk * kQLanes + pl >= left_out) continue;
-        const int m = uniform ? m_max : (int)((w >> 16) & ((1u << kLenBits) - 1));
-        uint8_t acc;
-        int16_t pc;
-        if (!((w >> (16 + kLenBits)) & 1u)) {
-            acc = 0xFF;
-            pc = -1;
-        } else {
-            const int ones = (int)(w & 0xFFFFu) - (nwin - m);   // S stays 1 on [m, nwin)
-            const int E = J.Edec ? J.Edec[p] : J.E;
-            acc = ones <= E ? 1 : 0;
-            pc = (int16_t)ones;
-        }
-        const int64_t o = J.perm ? J.perm[p] : p;
-        J.out_accept[o] = acc;
-        if (J.out_popcount) J.out_popcount[o] = pc;
+    if constexpr (RO) {
+        rest(std::true_type());
+    } else {
+        if (uniform)
+            rest(std::true_type());
+        else
+            rest(std::false_type());
     }
 }
 
