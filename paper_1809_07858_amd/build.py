@@ -16,10 +16,9 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-I", os.path.join(ROOT, "include")]
 # Per-source flags.  The plain, tile and two-length kernels' window loop is
 # long straight-line gate code run at two wavefronts per SIMD: the machine
-# scheduler's ILP strategy (within the 256 VGPRs that occupancy allows; 12
-# bytes of scratch per lane in the quarter layout's tile kernel only) gave
-# 2-5% shorter launches than the default one on the shapes measured, with
-# identical outputs.
+# scheduler's ILP strategy (within the 256 VGPRs that occupancy allows, no
+# scratch) gave 2-5% shorter launches than the default one on the shapes
+# measured, with identical outputs.
 EXTRA = {
     "csrc/shouji_plain.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
 }
